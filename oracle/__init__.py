@@ -1,0 +1,29 @@
+"""FP64 CPU oracle for the per-band HRMS reconstruction under the local Laplacian prior (LLP).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's CPU-baseline leg import this
+package; the library's product path never does, and nothing here is shared with the HIP implementation.
+
+Every function states the passage of the paper it follows.  Pins (checks against brute force, closed forms and
+identities that do not reuse this code) live in the CPU test suite.  Functions without such a pin say
+"parity unpinned" in their docstring.
+"""
+from .llp import (  # noqa: F401
+    Problem,
+    apply_A,
+    apply_data,
+    apply_llp,
+    blur,
+    blur_adjoint,
+    cg,
+    decimate,
+    decimate_adjoint,
+    kernel_otf,
+    laplacian,
+    matting_apply,
+    matting_stats,
+    objective,
+    objective_levin,
+    rhs,
+    solve,
+    window_sum,
+)
