@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Throughput of the LLP HRMS solve on one MI355X.
+
+One step = one full call of the library on one synthetic scene with inputs already in HBM: PAN statistics,
+right-hand sides, conjugate gradients from Z = 0 to ||r|| <= 1e-6 ||b|| for every band, the true residual and
+the objective of the result.  The workload is the 8-band scene with a 2048 x 2048 PAN image and 512 x 512 LRMS
+(x4), a 17 x 17 anisotropic Gaussian blur, window radius 2, lambda 1e-2, eps 1e-3.
+
+Prints one JSON line.  `value` is HRMS Mpixel*bands per second (N*H*W / time per step).  `roofline` is the
+operator kernel's algorithmic HBM bytes over its measured average launch time (HIP events on the solver's
+stream, summed over the timed steps).  `cpu_baseline` is the FP64 CPU oracle on a bounded sample of the same
+scene (its setup plus a few CG iterations, extrapolated to the GPU's iteration count).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--side", type=int, default=None, help="PAN side override (same recipe, smaller scene)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(sc, st, gpu_iters, budget_s):
+    """FP64 oracle on the host: setup (operator data + right-hand sides) plus as many CG iterations of all bands
+    as fit in the budget, extrapolated to the GPU's per-band iteration count."""
+    import numpy as np
+    import oracle
+    from oracle.llp import Problem
+
+    t0 = time.perf_counter()
+    prob = Problem(u=sc.u, c=sc.c, Y=sc.Y, r=st.r, lam=float(np.float32(st.lam)), eps=float(np.float32(st.eps)))
+    b = oracle.rhs(sc.X, prob)
+    t_setup = time.perf_counter() - t0
+    k = 0
+    t1 = time.perf_counter()
+    while True:
+        oracle.cg(prob, b, max_iters=1)  # one iteration of every band (the first: same cost as any other)
+        k += 1
+        if time.perf_counter() - t1 > budget_s / 2 or k >= 50:
+            break
+    t_iter = (time.perf_counter() - t1) / k
+    N, H, W = sc.Z.shape
+    t_solve = t_setup + gpu_iters * t_iter
+    return {
+        "value": N * H * W / t_solve / 1e6,
+        "unit": "Mpixel*bands/s",
+        "cores": os.cpu_count(),
+        "kind": "oracle",
+        "sample": f"setup + {k} CG iteration(s) of all {N} bands at {H}x{W}, FP64 numpy/scipy.fft "
+                  f"(fft workers = all cores); extrapolated to {gpu_iters} iterations "
+                  f"({t_setup:.2f} s setup, {t_iter:.2f} s per iteration)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the per-band solves would shard "
+              "across GPUs with no communication, but this build runs on one device.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2103_09943_amd import binding as B
+    from paper_2103_09943_amd import scenes
+
+    sc, st = scenes.config_scene(1, 0, side=args.side)
+    N, H, W = sc.Z.shape
+    X = torch.from_numpy(sc.X).cuda()
+    Y = torch.from_numpy(sc.Y).cuda()
+    u = torch.from_numpy(sc.u).cuda()
+    out = torch.empty((N, H, W), dtype=torch.float32, device="cuda")
+    ctx = B.Context(0)
+    kw = dict(r=st.r, lam=st.lam, eps=st.eps, max_iters=st.max_iters, tol=st.tol, out=out)
+
+    for _ in range(args.warmup):
+        ctx.pansharpen(X, Y, u, **kw)
+    ctx.set_profiling(True)
+    ctx.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(args.steps):
+        _, rep, status = ctx.pansharpen(X, Y, u, **kw)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = ctx.kernel_times(reset=True)
+    ctx.set_profiling(False)
+
+    ms_per_step = elapsed / args.steps * 1e3
+    value = N * H * W / (elapsed / args.steps) / 1e6
+    iters = [r["iters"] for r in reps[-1]]
+    # Algorithmic bytes of the operator kernel per launch: read r and the previous direction, write the new
+    # direction and q = A p (16 B per active pixel-band) plus the PAN statistics G, mu, dinv (12 B per pixel,
+    # read once per launch for all bands).
+    HW = H * W
+    band_iters = sum(sum(r["iters"] for r in rep) for rep in reps)
+    launches = kt["apply_launches"]
+    apply_bytes = 16.0 * HW * band_iters + 12.0 * HW * launches
+    upd_bytes = 24.0 * HW * band_iters
+    apply_gbs = apply_bytes / (kt["apply_ms"] * 1e-3) / 1e9 if kt["apply_ms"] > 0 else 0.0
+    iter_gbs = (apply_bytes + upd_bytes) / ((kt["apply_ms"] + kt["update_ms"]) * 1e-3) / 1e9 if launches else 0.0
+    line = {
+        "metric": "HRMS Mpixel·channels/s at fixed residual tol, plain vs CNN warm-start",
+        "value": round(value, 3),
+        "unit": "Mpixel*bands/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"plain LLP solve (cold start), 1 scene, {N} bands, PAN {H}x{W}, LRMS {H // sc.c}x{W // sc.c} "
+                        f"(x{sc.c}), {sc.u.shape[0]}x{sc.u.shape[0]} anisotropic Gaussian blur, r={st.r}, "
+                        f"lambda={st.lam}, eps={st.eps}, tol={st.tol}",
+            "iters_per_band": iters,
+            "max_true_rel_residual": max(r["true_rel_residual"] for r in reps[-1]),
+            "status": status,
+            "ms_per_cg_iteration": round((kt["apply_ms"] + kt["update_ms"]) / max(launches, 1), 4),
+            "iteration_gbs": round(iter_gbs, 1),
+            "iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_apply (direction update + A p + p^T A p)",
+            "achieved": round(apply_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(apply_gbs / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(kt["apply_ms"] / max(launches, 1) * 1e3, 2),
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(sc, st, int(statistics.median(iters)), args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

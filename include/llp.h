@@ -1,0 +1,153 @@
+/*
+ * llp.h -- C ABI of libllp, the MI355X (gfx950) solver for the per-band HRMS reconstruction under the local
+ * Laplacian prior (LLP) of "Fast and High-Quality Blind Multi-Spectral Image Pansharpening" (Sec. III-B).
+ *
+ * For every band i of a scene the library computes Z_i, the minimiser of eq. (initialize_z_fast)
+ *     1/2 || D B(u) Z_i - X_i ||^2 + lambda/2 (L Z_i)^T M_LY (L Z_i),
+ * i.e. the solution of eq. (Z_ini_matting)
+ *     (B^T D^T D B + lambda L^T M_LY L) Z_i = B^T D^T X_i,
+ * by conjugate gradients, as the paper prescribes for that equation.
+ *
+ * Notation (Sec. II-A): X is the LRMS image (N bands, h x w each), Y the PAN image (H x W), Z the HRMS image
+ * (N bands, H x W), u the n x n blur kernel, c = H/h = W/w.  B(u) is circular convolution (the true
+ * convolution, with the kernel's centre tap u[(n-1)/2][(n-1)/2] at offset 0), D keeps pixels (c*m, c*k),
+ * L is periodic convolution with the 5-point stencil S of eq. (reg2), and M_LY is the matting matrix of
+ * eq. (matting_matrix) built from the Laplacian of the PAN image, with periodic (2r+1) x (2r+1) windows,
+ * population variances and eps/|w| + sigma_k^2 in its denominator (a window with eps/|w| + sigma_k^2 == 0
+ * contributes no slope term).
+ *
+ * Memory: every image argument is a DEVICE pointer to C-contiguous float32 data, planar and row-major:
+ * LRMS [N][h][w], PAN [H][W], kernel [n][n], HRMS [N][H][W].  The caller owns all of them; the library
+ * neither frees nor retains them after a call returns.  The context owns its workspaces (grown on demand,
+ * released by llp_destroy).  A context is not thread-safe: calls on one context must not overlap.
+ *
+ * Streams: all device work of a call is enqueued on `stream` (0 = the null stream).  llp_pansharpen and
+ * llp_objective synchronise that stream before returning; the other operator entry points are asynchronous.
+ *
+ * Errors: every entry point returns an llp_status; no exception crosses the ABI.  Negative values are errors
+ * (the output buffers are then unspecified), positive values are warnings with valid outputs.
+ */
+#ifndef LLP_H
+#define LLP_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LLP_OK = 0,
+  LLP_NOT_CONVERGED = 1,  /* tolerance not reached within max_iters; output is the last iterate */
+  LLP_E_ARG = -1,         /* NULL pointer or parameter out of range */
+  LLP_E_SHAPE = -2,       /* inconsistent sizes (n even, n > min(H, W), 2r+1 > min(H, W), ...) */
+  LLP_E_UNSUPPORTED = -3, /* valid but beyond this build's limits (see LLP_MAX_*) */
+  LLP_E_HIP = -4,         /* a HIP runtime call failed */
+  LLP_E_OOM = -5,         /* workspace allocation failed */
+  LLP_E_BREAKDOWN = -6,   /* p^T A p <= 0 or not finite in some band: A is not positive definite */
+  LLP_E_NONFINITE = -7    /* an input (LRMS, PAN or kernel) holds NaN or Inf */
+} llp_status;
+
+/* Build limits. */
+#define LLP_MAX_KERNEL 33 /* n <= 33 */
+#define LLP_MAX_RADIUS 4  /* r <= 4 */
+#define LLP_MAX_SCALE 8   /* c <= 8 */
+
+typedef struct {
+  int N; /* bands, >= 1 */
+  int h; /* LRMS rows, >= 1 */
+  int w; /* LRMS columns, >= 1 */
+  int c; /* resolution gap: H = c*h, W = c*w; the paper has c >= 2, c = 1 is accepted */
+  int n; /* blur kernel size, odd, n <= min(H, W) */
+} llp_shape;
+
+typedef struct {
+  int r;         /* LLP window radius (eq. reg2), 0 <= r, 2r+1 <= min(H, W) */
+  float lambda;  /* LLP weight, >= 0 */
+  float eps;     /* matting regulariser epsilon, >= 0 (enters as eps/|w| + sigma^2) */
+  int max_iters; /* CG iteration cap, >= 0 */
+  float tol;     /* > 0: stop a band when ||r_k|| <= tol * ||b|| (r_k the CG residual, b = B^T D^T X_i);
+                    <= 0: run exactly max_iters iterations */
+  int init_mode; /* 0: start from Z = 0; 1: start from the caller's `init` */
+} llp_params;
+
+typedef struct {
+  int iters;                /* CG iterations run for this band */
+  int status;               /* llp_status of this band (LLP_OK, LLP_NOT_CONVERGED, LLP_E_BREAKDOWN) */
+  double rel_residual;      /* ||r_k|| / ||b|| of the CG recursion at exit */
+  double true_rel_residual; /* ||b - A Z|| / ||b|| recomputed from the returned Z */
+  double objective;         /* eq. (initialize_z_fast) at the returned Z */
+} llp_report;
+
+typedef struct llp_ctx llp_ctx;
+
+/* Create a context bound to HIP device `device`.  *out receives the handle. */
+llp_status llp_create(llp_ctx** out, int device);
+
+/* Release a context and all its workspaces.  NULL is accepted. */
+void llp_destroy(llp_ctx* ctx);
+
+/* Static description of a status code. */
+const char* llp_status_str(int status);
+
+/* Host-only check of a problem description against the rules above and this build's limits (no device
+ * work, no context needed).  `params` may be NULL to check the shape alone.  Returns LLP_OK or the error that
+ * llp_pansharpen would return for these arguments. */
+llp_status llp_validate(const llp_shape* shape, const llp_params* params);
+
+/* Solve eq. (Z_ini_matting) for all N bands of one scene (Sec. III-B; Algorithm "Fast Pansharpening": the
+ * matting matrix is formed once from the PAN image, then every band is solved).
+ *   lrms  [N][h][w] device, pan [H][W] device, kernel [n][n] device,
+ *   init  [N][H][W] device or NULL (read only when params->init_mode == 1),
+ *   hrms  [N][H][W] device, written,
+ *   rep   host array of N reports, or NULL.
+ * Returns the worst band status (errors before warnings).  Inputs are checked for NaN/Inf (LLP_E_NONFINITE). */
+llp_status llp_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
+                          const float* pan, const float* kernel, const float* init, float* hrms,
+                          llp_report* rep, hipStream_t stream);
+
+/* ---- Operator entry points (the steps of the solve, exposed for parity checks) ------------------------ */
+
+/* PAN statistics that define M_LY (eq. matting_matrix with I = L Y): G = L Y [H][W], and per window centre
+ * mu [H][W] (window mean of G) and dinv [H][W] = 1/(eps/|w| + sigma^2) (0 where that is 0).
+ * Accumulation in FP64, results rounded once to float32.  All pointers device. */
+llp_status llp_pan_stats(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
+                         float* G, float* mu, float* dinv, hipStream_t stream);
+
+/* Right-hand side of eq. (Z_ini_matting): b = B^T D^T X_i for every band.  b [N][H][W] device. */
+llp_status llp_rhs(llp_ctx* ctx, const llp_shape* shape, const float* lrms, const float* kernel, float* b,
+                   hipStream_t stream);
+
+/* Apply the matrix of eq. (Z_ini_matting): Az = (B^T D^T D B + lambda L^T M_LY L) z for every band.
+ * z, Az [N][H][W] device (must not alias). */
+llp_status llp_apply_A(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
+                       const float* kernel, const float* z, float* Az, hipStream_t stream);
+
+/* Objective of eq. (initialize_z_fast) for every band of z: obj host [N] (FP64).  The LLP part is summed
+ * window by window in the form of eq. (pansharp) with the optimal (a, c) of each window. */
+llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
+                         const float* pan, const float* kernel, const float* z, double* obj,
+                         hipStream_t stream);
+
+/* ---- Kernel timing -------------------------------------------------------------------------------------- */
+
+typedef struct {
+  double apply_ms;          /* summed device time of the operator launches (direction update + A p + p^T A p) */
+  long long apply_launches;
+  double update_ms;         /* summed device time of the CG vector updates (x, r, r^T r) */
+  long long update_launches;
+} llp_kernel_times;
+
+/* Enable (1) or disable (0) timing of the CG kernels of later llp_pansharpen calls on this context.  Timing
+ * brackets each launch with HIP events on the call's stream; it adds two event records per launch. */
+llp_status llp_set_profiling(llp_ctx* ctx, int enable);
+
+/* Accumulated kernel times since the last reset (host struct); reset != 0 clears them afterwards. */
+llp_status llp_get_kernel_times(llp_ctx* ctx, llp_kernel_times* out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLP_H */

@@ -1,0 +1,205 @@
+"""Thin ctypes binding of libllp (include/llp.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.  Tensors are torch CUDA (HIP)
+tensors used as device memory; the current torch stream is passed through.  If the library has not been
+built, every entry point raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libllp.so")
+
+# llp_status values
+OK, NOT_CONVERGED = 0, 1
+E_ARG, E_SHAPE, E_UNSUPPORTED, E_HIP, E_OOM, E_BREAKDOWN, E_NONFINITE = -1, -2, -3, -4, -5, -6, -7
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("h", ctypes.c_int), ("w", ctypes.c_int), ("c", ctypes.c_int),
+                ("n", ctypes.c_int)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int), ("lam", ctypes.c_float), ("eps", ctypes.c_float),
+                ("max_iters", ctypes.c_int), ("tol", ctypes.c_float), ("init_mode", ctypes.c_int)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("true_rel_residual", ctypes.c_double), ("objective", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("apply_ms", ctypes.c_double), ("apply_launches", ctypes.c_longlong),
+                ("update_ms", ctypes.c_double), ("update_launches", ctypes.c_longlong)]
+
+
+class LlpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {status_str(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_SIGS = {
+    "llp_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int]),
+    "llp_destroy": (None, [_vp]),
+    "llp_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "llp_validate": (ctypes.c_int, [ctypes.POINTER(Shape), ctypes.POINTER(Params)]),
+    "llp_pansharpen": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp,
+                                      ctypes.POINTER(Report), _vp]),
+    "llp_pan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
+    "llp_rhs": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), _vp, _vp, _vp, _vp]),
+    "llp_apply_A": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
+    "llp_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "llp_get_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
+    "llp_objective": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
+                                     ctypes.POINTER(ctypes.c_double), _vp]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library.  Raises if libllp.so is missing (build it with paper_2103_09943_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2103_09943_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(status: int) -> str:
+    return lib().llp_status_str(int(status)).decode()
+
+
+def validate(shape: Shape, params: Optional[Params]) -> int:
+    """Host-only validation (llp_validate); returns the status code."""
+    return lib().llp_validate(ctypes.byref(shape), ctypes.byref(params) if params is not None else None)
+
+
+def _check(status: int, where: str, allow=(OK,)):
+    if status not in allow:
+        raise LlpError(status, where)
+    return status
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float32 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def shape_of(lrms, pan, kernel) -> Shape:
+    N, h, w = lrms.shape
+    H, W = pan.shape
+    if H % h or W % w or H // h != W // w:
+        raise ValueError("PAN size must be c times the LRMS size in both directions")
+    n = kernel.shape[0]
+    if kernel.shape != (n, n):
+        raise ValueError("kernel must be square")
+    return Shape(N, h, w, H // h, n)
+
+
+class Context:
+    """Owns an llp_ctx (device workspaces).  Not thread-safe."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        _check(lib().llp_create(ctypes.byref(h), int(device)), "llp_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().llp_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def pansharpen(self, lrms, pan, kernel, *, r: int, lam: float, eps: float, max_iters: int, tol: float = 0.0,
+                   init=None, out=None, report: bool = True, stream=None, allow_not_converged: bool = True):
+        """Solve eq. (Z_ini_matting) for every band.  Returns (hrms, list of report dicts or None, status)."""
+        import torch
+        shp = shape_of(lrms, pan, kernel)
+        H, W = pan.shape
+        if out is None:
+            out = torch.empty((shp.N, H, W), dtype=torch.float32, device=lrms.device)
+        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), 1 if init is not None else 0)
+        reps = (Report * shp.N)() if report else None
+        st = lib().llp_pansharpen(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(lrms), _ptr(pan), _ptr(kernel),
+                                  _ptr(init), _ptr(out), reps, _stream(stream))
+        allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        _check(st, "llp_pansharpen", allow)
+        return out, ([rp.as_dict() for rp in reps] if report else None), st
+
+    def pan_stats(self, pan, *, N: int, c: int, n: int, r: int, eps: float, stream=None):
+        import torch
+        H, W = pan.shape
+        shp = Shape(N, H // c, W // c, c, n)
+        prm = Params(int(r), 0.0, float(eps), 0, 0.0, 0)
+        G, mu, d = (torch.empty((H, W), dtype=torch.float32, device=pan.device) for _ in range(3))
+        _check(lib().llp_pan_stats(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(pan), _ptr(G), _ptr(mu),
+                                   _ptr(d), _stream(stream)), "llp_pan_stats")
+        return G, mu, d
+
+    def rhs(self, lrms, kernel, c: int, stream=None):
+        import torch
+        N, h, w = lrms.shape
+        shp = Shape(N, h, w, c, kernel.shape[0])
+        b = torch.empty((N, h * c, w * c), dtype=torch.float32, device=lrms.device)
+        _check(lib().llp_rhs(self._h, ctypes.byref(shp), _ptr(lrms), _ptr(kernel), _ptr(b), _stream(stream)),
+               "llp_rhs")
+        return b
+
+    def apply_A(self, z, pan, kernel, *, c: int, r: int, lam: float, eps: float, stream=None):
+        import torch
+        N, H, W = z.shape
+        shp = Shape(N, H // c, W // c, c, kernel.shape[0])
+        prm = Params(int(r), float(lam), float(eps), 0, 0.0, 0)
+        out = torch.empty_like(z)
+        _check(lib().llp_apply_A(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(pan), _ptr(kernel), _ptr(z),
+                                 _ptr(out), _stream(stream)), "llp_apply_A")
+        return out
+
+    def objective(self, z, lrms, pan, kernel, *, r: int, lam: float, eps: float, stream=None):
+        shp = shape_of(lrms, pan, kernel)
+        prm = Params(int(r), float(lam), float(eps), 0, 0.0, 0)
+        obj = (ctypes.c_double * shp.N)()
+        _check(lib().llp_objective(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(lrms), _ptr(pan),
+                                   _ptr(kernel), _ptr(z), obj, _stream(stream)), "llp_objective")
+        return list(obj)
+
+    def set_profiling(self, enable: bool):
+        _check(lib().llp_set_profiling(self._h, 1 if enable else 0), "llp_set_profiling")
+
+    def kernel_times(self, reset: bool = True) -> dict:
+        t = KernelTimes()
+        _check(lib().llp_get_kernel_times(self._h, ctypes.byref(t), 1 if reset else 0), "llp_get_kernel_times")
+        return {k: getattr(t, k) for k, _ in t._fields_}
