@@ -105,16 +105,28 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     value = N * H * W / (elapsed / args.steps) / 1e6
     iters = [r["iters"] for r in reps[-1]]
-    # Algorithmic bytes of the operator kernel per launch: read r and the previous direction, write the new
-    # direction and q = A p (16 B per active pixel-band) plus the PAN statistics G, mu, dinv (12 B per pixel,
-    # read once per launch for all bands).
+    # Algorithmic HBM bytes per active pixel-band (float32), c = resolution gap:
+    #   k_apply: read p, r and y (1/c^2 of a plane), write q          -> 12 + 4/c^2
+    #            plus the PAN statistics G, mu, dinv once per launch  -> 12 per pixel
+    #   k_dir:   read r, q, p, x; write r, p, x and y                 -> 28 + 4/c^2
     HW = H * W
+    c2 = float(sc.c * sc.c)
     band_iters = sum(sum(r["iters"] for r in rep) for rep in reps)
     launches = kt["apply_launches"]
-    apply_bytes = 16.0 * HW * band_iters + 12.0 * HW * launches
-    upd_bytes = 24.0 * HW * band_iters
+    busy_launches = sum(max(r["iters"] for r in rep) for rep in reps)  # launches with at least one active band
+    apply_bytes = (12.0 + 4.0 / c2) * HW * band_iters + 12.0 * HW * busy_launches
+    dir_bytes = (28.0 + 4.0 / c2) * HW * band_iters
     apply_gbs = apply_bytes / (kt["apply_ms"] * 1e-3) / 1e9 if kt["apply_ms"] > 0 else 0.0
-    iter_gbs = (apply_bytes + upd_bytes) / ((kt["apply_ms"] + kt["update_ms"]) * 1e-3) / 1e9 if launches else 0.0
+    dir_gbs = dir_bytes / (kt["dir_ms"] * 1e-3) / 1e9 if kt["dir_ms"] > 0 else 0.0
+    it_ms = kt["apply_ms"] + kt["dir_ms"]
+    iter_gbs = (apply_bytes + dir_bytes) / (it_ms * 1e-3) / 1e9 if it_ms > 0 else 0.0
+    dominant = "k_apply" if kt["apply_ms"] >= kt["dir_ms"] else "k_dir"
+    dom = {
+        "k_apply": dict(kernel="k_apply (q = A p: B^T D^T y + lambda L^T M L p; p^T q, r^T q, q^T q)",
+                        achieved=apply_gbs, ms=kt["apply_ms"], n=launches),
+        "k_dir": dict(kernel="k_dir (x, r update; p = r + beta p; y = D B p; r^T r)", achieved=dir_gbs,
+                      ms=kt["dir_ms"], n=kt["dir_launches"]),
+    }[dominant]
     line = {
         "metric": "HRMS Mpixel·channels/s at fixed residual tol, plain vs CNN warm-start",
         "value": round(value, 3),
@@ -135,18 +147,22 @@ def main():
             "iters_per_band": iters,
             "max_true_rel_residual": max(r["true_rel_residual"] for r in reps[-1]),
             "status": status,
-            "ms_per_cg_iteration": round((kt["apply_ms"] + kt["update_ms"]) / max(launches, 1), 4),
+            "ms_per_cg_iteration": round(it_ms / max(launches, 1), 4),
             "iteration_gbs": round(iter_gbs, 1),
             "iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4),
+            "k_apply_gbs": round(apply_gbs, 1),
+            "k_apply_avg_us": round(kt["apply_ms"] / max(launches, 1) * 1e3, 2),
+            "k_dir_gbs": round(dir_gbs, 1),
+            "k_dir_avg_us": round(kt["dir_ms"] / max(kt["dir_launches"], 1) * 1e3, 2),
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_apply (direction update + A p + p^T A p)",
-            "achieved": round(apply_gbs, 1),
+            "kernel": dom["kernel"],
+            "achieved": round(dom["achieved"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(apply_gbs / HBM_PEAK_GBS, 4),
-            "avg_launch_us": round(kt["apply_ms"] / max(launches, 1) * 1e3, 2),
+            "frac": round(dom["achieved"] / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(dom["ms"] / max(dom["n"], 1) * 1e3, 2),
             "traffic": None,
         },
     }

@@ -17,7 +17,8 @@
  * contributes no slope term).
  *
  * Memory: every image argument is a DEVICE pointer to C-contiguous float32 data, planar and row-major:
- * LRMS [N][h][w], PAN [H][W], kernel [n][n], HRMS [N][H][W].  The caller owns all of them; the library
+ * LRMS [N][h][w], PAN [H][W], kernel [n][n], HRMS [N][H][W]; HRMS-sized buffers (hrms, init, z, Az) must be
+ * 16-byte aligned (LLP_E_ARG otherwise).  The caller owns all of them; the library
  * neither frees nor retains them after a call returns.  The context owns its workspaces (grown on demand,
  * released by llp_destroy).  A context is not thread-safe: calls on one context must not overlap.
  *
@@ -52,7 +53,7 @@ typedef enum {
 /* Build limits. */
 #define LLP_MAX_KERNEL 33 /* n <= 33 */
 #define LLP_MAX_RADIUS 4  /* r <= 4 */
-#define LLP_MAX_SCALE 8   /* c <= 8 */
+#define LLP_MAX_SCALE 4   /* c <= 4 */
 
 typedef struct {
   int N; /* bands, >= 1 */
@@ -82,7 +83,9 @@ typedef struct {
 
 typedef struct llp_ctx llp_ctx;
 
-/* Create a context bound to HIP device `device`.  *out receives the handle. */
+/* Create a context bound to HIP device `device`.  *out receives the handle.  If the environment variable
+ * LLP_FORCE_GENERIC is set (and not "0") at creation, the context uses only the generic kernels (no
+ * specialisation on kernel size, scale and window radius); results agree to rounding. */
 llp_status llp_create(llp_ctx** out, int device);
 
 /* Release a context and all its workspaces.  NULL is accepted. */
@@ -133,10 +136,10 @@ llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params*
 /* ---- Kernel timing -------------------------------------------------------------------------------------- */
 
 typedef struct {
-  double apply_ms;          /* summed device time of the operator launches (direction update + A p + p^T A p) */
+  double apply_ms;          /* summed device time of the operator launches (q = A p and its dot products) */
   long long apply_launches;
-  double update_ms;         /* summed device time of the CG vector updates (x, r, r^T r) */
-  long long update_launches;
+  double dir_ms;            /* summed device time of the update launches (x, r, new direction, D B p, r^T r) */
+  long long dir_launches;
 } llp_kernel_times;
 
 /* Enable (1) or disable (0) timing of the CG kernels of later llp_pansharpen calls on this context.  Timing

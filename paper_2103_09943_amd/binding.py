@@ -38,7 +38,7 @@ class Report(ctypes.Structure):
 
 class KernelTimes(ctypes.Structure):
     _fields_ = [("apply_ms", ctypes.c_double), ("apply_launches", ctypes.c_longlong),
-                ("update_ms", ctypes.c_double), ("update_launches", ctypes.c_longlong)]
+                ("dir_ms", ctypes.c_double), ("dir_launches", ctypes.c_longlong)]
 
 
 class LlpError(RuntimeError):
@@ -131,9 +131,9 @@ class Context:
         self._h = h
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().llp_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.llp_destroy(self._h)
+        self._h = None
 
     __del__ = close
 

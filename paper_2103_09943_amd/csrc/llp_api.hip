@@ -15,14 +15,16 @@ using namespace llp;
 
 struct llp_ctx {
   int device = 0;
+  bool allow_fast = true;  // false when LLP_FORCE_GENERIC is set at creation: generic kernels only
+  int want_dir_rows = 0;   // launch-shape overrides (0: default), from LLP_DIR_ROWS / LLP_APPLY_VARIANT
+  int want_apply_variant = -1;
   void* ws = nullptr;
   size_t ws_bytes = 0;
   // views into ws
-  float *G = nullptr, *MU = nullptr, *DI = nullptr, *b = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr,
-        *q = nullptr;
+  float *G = nullptr, *MU = nullptr, *DI = nullptr, *b = nullptr, *q = nullptr, *y = nullptr;
+  float* r[2] = {nullptr, nullptr};  // residual, alternating between iterations
+  float* p[2] = {nullptr, nullptr};  // direction, alternating between iterations
   double* partials = nullptr;
-  unsigned* counters = nullptr;  // own allocation: stays at zero between kernels whatever the geometry
-  int cnt_cap = 0;
   ChanState* st = nullptr;
   double* results = nullptr;
   int* flags = nullptr;
@@ -52,11 +54,14 @@ constexpr int kMaxLdsFloats = 160 * 1024 / 4;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Image buffers are read and written with 16-byte vector accesses.
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 llp_status validate(const llp_shape* s, const llp_params* p, Geom* g) {
   if (!s) return LLP_E_ARG;
   if (s->N < 1 || s->h < 1 || s->w < 1 || s->c < 1 || s->n < 1) return LLP_E_SHAPE;
   if ((s->n & 1) == 0) return LLP_E_SHAPE;
-  if (s->c > LLP_MAX_SCALE || s->n > LLP_MAX_KERNEL) return LLP_E_UNSUPPORTED;
+  if (s->c > kMaxScale || s->n > LLP_MAX_KERNEL) return LLP_E_UNSUPPORTED;
   const long long H = (long long)s->c * s->h, W = (long long)s->c * s->w;
   if (H > 65536 || W > 65536) return LLP_E_UNSUPPORTED;
   if ((long long)s->N * H * W >= (1LL << 31)) return LLP_E_UNSUPPORTED;
@@ -87,25 +92,50 @@ llp_status validate(const llp_shape* s, const llp_params* p, Geom* g) {
   return LLP_OK;
 }
 
-// Tile variant for the operator kernel: the first (in preference order) whose LDS layout fits.
-int pick_variant(const Geom& g) {
-  static const int order[] = {0, 2, 1, 4, 3};
-  for (int v : order) {
-    const ApplyLayout L = apply_layout(kTileVariants[v].TH, kTileVariants[v].TW, g.R, g.r, g.c, g.n);
-    if (L.total <= kMaxLdsFloats) return v;
+// Launch configuration of the iteration kernels: the first shapes (in preference order) whose LDS fits.
+bool pick_config(const Geom& g, OpConfig* cfg, bool allow_fast = true, int want_dir_rows = 0,
+                 int want_apply_variant = -1) {
+  cfg->fast = 0;
+  if (allow_fast && fast_path_available(g.c, g.R, g.r)) {
+    for (int v = 0; v < 2; ++v) {
+      if (want_apply_variant >= 0 && v != want_apply_variant) continue;
+      const int f = fast_apply_lds_floats(g.c, g.R, g.r, v);
+      if (f > 0 && f <= kMaxLdsFloats) {
+        cfg->fast = 1;
+        cfg->dir_rows = want_dir_rows == 8 ? 8 : 4;
+        cfg->apply_variant = v;
+        return true;
+      }
+    }
   }
-  return -1;
+  cfg->dir_rows = 0;
+  for (int tyl : {8, 4}) {
+    if (dir_lds_floats(g.c, tyl, g.R, nullptr) <= kMaxLdsFloats) {
+      cfg->dir_rows = tyl;
+      break;
+    }
+  }
+  cfg->apply_variant = -1;
+  for (int v = 0; v < kApplyVariants; ++v) {
+    int TH = 0, TW = 0;
+    if (apply_tile(g.c, v, &TH, &TW) != 0) continue;
+    if (apply_lds_floats(g.c, TH, TW, g.R, g.r, nullptr, nullptr, nullptr, nullptr) <= kMaxLdsFloats) {
+      cfg->apply_variant = v;
+      break;
+    }
+  }
+  return cfg->dir_rows > 0 && cfg->apply_variant >= 0;
 }
 
 llp_status ensure_workspace(llp_ctx* ctx, const Geom& g) {
   const size_t HW = (size_t)g.H * g.W;
-  const size_t planes = 3 * HW + 5 * (size_t)g.N * HW;
+  const size_t planes = 3 * HW + 6 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w;
   const size_t pstride = max_partials_per_band(g);
   size_t off = 0;
   const size_t o_planes = off;
   off = align_up(off + planes * sizeof(float), 256);
   const size_t o_part = off;
-  off = align_up(off + (size_t)g.N * pstride * sizeof(double), 256);
+  off = align_up(off + (size_t)g.N * pstride * 3 * sizeof(double), 256);
   const size_t o_st = off;
   off = align_up(off + (size_t)g.N * sizeof(ChanState), 256);
   const size_t o_res = off;
@@ -133,27 +163,16 @@ llp_status ensure_workspace(llp_ctx* ctx, const Geom& g) {
   ctx->DI = pl + 2 * HW;
   const size_t NHW = (size_t)g.N * HW;
   ctx->b = pl + 3 * HW;
-  ctx->r = ctx->b + NHW;
-  ctx->p0 = ctx->r + NHW;
-  ctx->p1 = ctx->p0 + NHW;
-  ctx->q = ctx->p1 + NHW;
+  ctx->r[0] = ctx->b + NHW;
+  ctx->r[1] = ctx->r[0] + NHW;
+  ctx->p[0] = ctx->r[1] + NHW;
+  ctx->p[1] = ctx->p[0] + NHW;
+  ctx->q = ctx->p[1] + NHW;
+  ctx->y = ctx->q + NHW;
   ctx->partials = (double*)(base + o_part);
   ctx->st = (ChanState*)(base + o_st);
   ctx->results = (double*)(base + o_res);
   ctx->flags = (int*)(base + o_flags);
-  // Reduction counters: every reduction kernel's last block resets its band's counter, so the array is all
-  // zero between kernels; it is zeroed once when (re)allocated and never moves with the geometry.
-  if (ctx->cnt_cap < g.N) {
-    if (ctx->counters) {
-      HIP_TRY(hipDeviceSynchronize());
-      HIP_TRY(hipFree(ctx->counters));
-      ctx->counters = nullptr;
-      ctx->cnt_cap = 0;
-    }
-    if (hipMalloc((void**)&ctx->counters, sizeof(unsigned) * g.N) != hipSuccess) return LLP_E_OOM;
-    HIP_TRY(hipMemset(ctx->counters, 0, sizeof(unsigned) * g.N));
-    ctx->cnt_cap = g.N;
-  }
   if (ctx->h_cap < g.N) {
     if (ctx->h_st) (void)hipHostFree(ctx->h_st);
     if (ctx->h_results) (void)hipHostFree(ctx->h_results);
@@ -188,9 +207,9 @@ llp_status collect_times(llp_ctx* ctx) {
     HIP_TRY(hipEventElapsedTime(&a, ctx->tev[i], ctx->tev[i + 1]));
     HIP_TRY(hipEventElapsedTime(&b, ctx->tev[i + 1], ctx->tev[i + 2]));
     ctx->times.apply_ms += a;
-    ctx->times.update_ms += b;
+    ctx->times.dir_ms += b;
     ctx->times.apply_launches += 1;
-    ctx->times.update_launches += 1;
+    ctx->times.dir_launches += 1;
   }
   ctx->tev_used = 0;
   return LLP_OK;
@@ -202,6 +221,16 @@ llp_status check_inputs(llp_ctx* ctx, const Geom& g, const float* lrms, const fl
   HIP_TRY(launch_check_finite(lrms, (size_t)g.N * g.h * g.w, ctx->flags, s));
   HIP_TRY(launch_check_finite(pan, (size_t)g.H * g.W, ctx->flags, s));
   HIP_TRY(launch_check_finite(kernel, (size_t)g.n * g.n, ctx->flags, s));
+  return LLP_OK;
+}
+
+// q = A z: y = D B z on the LR lattice, then q = B^T D^T y + lambda L^T M L z.
+llp_status apply_A_into(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const float* z, const float* kernel,
+                        float* q, hipStream_t s) {
+  HIP_TRY(launch_dir(g, cfg, 0, 0, 0, z, nullptr, nullptr, nullptr, nullptr, nullptr, ctx->y, kernel, ctx->partials,
+                     ctx->st, 0, 0.0f, s));
+  HIP_TRY(launch_apply(g, cfg, 0, z, nullptr, ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, q, ctx->partials,
+                       ctx->st, s));
   return LLP_OK;
 }
 
@@ -228,7 +257,8 @@ llp_status llp_validate(const llp_shape* shape, const llp_params* params) {
   Geom g;
   llp_status v = validate(shape, params, &g);
   if (v != LLP_OK) return v;
-  if (params && pick_variant(g) < 0) return LLP_E_UNSUPPORTED;
+  OpConfig cfg;
+  if (params && !pick_config(g, &cfg)) return LLP_E_UNSUPPORTED;
   return LLP_OK;
 }
 
@@ -241,6 +271,10 @@ llp_status llp_create(llp_ctx** out, int device) {
   llp_ctx* ctx = new (std::nothrow) llp_ctx();
   if (!ctx) return LLP_E_OOM;
   ctx->device = device;
+  const char* fg = getenv("LLP_FORCE_GENERIC");
+  ctx->allow_fast = !(fg && fg[0] && fg[0] != '0');
+  if (const char* e = getenv("LLP_DIR_ROWS")) ctx->want_dir_rows = atoi(e);
+  if (const char* e = getenv("LLP_APPLY_VARIANT")) ctx->want_apply_variant = atoi(e);
   for (auto& e : ctx->ev) {
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       llp_destroy(ctx);
@@ -256,7 +290,6 @@ void llp_destroy(llp_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   if (ctx->ws) (void)hipFree(ctx->ws);
-  if (ctx->counters) (void)hipFree(ctx->counters);
   if (ctx->h_st) (void)hipHostFree(ctx->h_st);
   if (ctx->h_results) (void)hipHostFree(ctx->h_results);
   if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
@@ -273,7 +306,7 @@ llp_status llp_pan_stats(llp_ctx* ctx, const llp_shape* shape, const llp_params*
   llp_status v = validate(shape, params, &g);
   if (v != LLP_OK) return v;
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(launch_pan_stats(g, pan, G, mu, dinv, nullptr, stream));
+  HIP_TRY(launch_pan_stats(g, pan, G, mu, dinv, stream));
   return LLP_OK;
 }
 
@@ -286,25 +319,24 @@ llp_status llp_rhs(llp_ctx* ctx, const llp_shape* shape, const float* lrms, cons
   HIP_TRY(hipSetDevice(ctx->device));
   v = ensure_workspace(ctx, g);
   if (v != LLP_OK) return v;
-  HIP_TRY(launch_rhs(g, lrms, kernel, b, ctx->partials, ctx->counters, ctx->st, stream));
+  HIP_TRY(launch_rhs(g, lrms, kernel, b, ctx->partials, ctx->st, stream));
   return LLP_OK;
 }
 
 llp_status llp_apply_A(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
                        const float* kernel, const float* z, float* Az, hipStream_t stream) {
   if (!ctx || !params || !pan || !kernel || !z || !Az || z == Az) return LLP_E_ARG;
+  if (!aligned16(z) || !aligned16(Az)) return LLP_E_ARG;
   Geom g;
   llp_status v = validate(shape, params, &g);
   if (v != LLP_OK) return v;
-  const int variant = pick_variant(g);
-  if (variant < 0) return LLP_E_UNSUPPORTED;
+  OpConfig cfg;
+  if (!pick_config(g, &cfg, ctx->allow_fast, ctx->want_dir_rows, ctx->want_apply_variant)) return LLP_E_UNSUPPORTED;
   HIP_TRY(hipSetDevice(ctx->device));
   v = ensure_workspace(ctx, g);
   if (v != LLP_OK) return v;
-  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, nullptr, stream));
-  HIP_TRY(launch_apply(g, variant, 0, z, nullptr, nullptr, kernel, ctx->G, ctx->MU, ctx->DI, Az, ctx->partials,
-                       ctx->counters, ctx->st, stream));
-  return LLP_OK;
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
+  return apply_A_into(ctx, g, cfg, z, kernel, Az, stream);
 }
 
 llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
@@ -316,8 +348,8 @@ llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params*
   HIP_TRY(hipSetDevice(ctx->device));
   v = ensure_workspace(ctx, g);
   if (v != LLP_OK) return v;
-  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, nullptr, stream));
-  HIP_TRY(launch_objective(g, z, lrms, kernel, ctx->G, ctx->MU, ctx->DI, ctx->partials, ctx->counters, ctx->results,
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
+  HIP_TRY(launch_objective(g, z, lrms, kernel, ctx->G, ctx->MU, ctx->DI, ctx->partials, ctx->st, ctx->results,
                            stream));
   HIP_TRY(hipMemcpyAsync(ctx->h_results, ctx->results, sizeof(double) * kResultSlots * g.N, hipMemcpyDeviceToHost,
                          stream));
@@ -333,40 +365,44 @@ llp_status llp_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params
                           hipStream_t stream) {
   if (!ctx || !params || !lrms || !pan || !kernel || !hrms) return LLP_E_ARG;
   if (params->init_mode == 1 && !init) return LLP_E_ARG;
+  if (!aligned16(hrms) || (params->init_mode == 1 && !aligned16(init))) return LLP_E_ARG;
   Geom g;
   llp_status v = validate(shape, params, &g);
   if (v != LLP_OK) return v;
-  const int variant = pick_variant(g);
-  if (variant < 0) return LLP_E_UNSUPPORTED;
+  OpConfig cfg;
+  if (!pick_config(g, &cfg, ctx->allow_fast, ctx->want_dir_rows, ctx->want_apply_variant)) return LLP_E_UNSUPPORTED;
   HIP_TRY(hipSetDevice(ctx->device));
   v = ensure_workspace(ctx, g);
   if (v != LLP_OK) return v;
   hipStream_t s = stream;
   const size_t NHW = (size_t)g.N * g.H * g.W;
+  const int max_iters = params->max_iters;
+  const float tol = params->tol;
 
   v = check_inputs(ctx, g, lrms, pan, kernel, s);
   if (v != LLP_OK) return v;
   // Per scene: the statistics that define M_LY, then the right-hand sides and ||b||.
-  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, nullptr, s));
-  HIP_TRY(launch_rhs(g, lrms, kernel, ctx->b, ctx->partials, ctx->counters, ctx->st, s));
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, s));
+  HIP_TRY(launch_rhs(g, lrms, kernel, ctx->b, ctx->partials, ctx->st, s));
   const int from_init = params->init_mode == 1;
   if (from_init) {
     if (init != hrms) HIP_TRY(hipMemcpyAsync(hrms, init, NHW * sizeof(float), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(launch_apply(g, variant, 0, hrms, nullptr, nullptr, kernel, ctx->G, ctx->MU, ctx->DI, ctx->q,
-                         ctx->partials, ctx->counters, ctx->st, s));
+    v = apply_A_into(ctx, g, cfg, hrms, kernel, ctx->q, s);
+    if (v != LLP_OK) return v;
   }
-  HIP_TRY(launch_init_residual(g, from_init, ctx->b, ctx->q, ctx->r, hrms, ctx->partials, ctx->counters, ctx->st,
-                               params->max_iters, params->tol, s));
+  HIP_TRY(launch_init(g, from_init, ctx->b, ctx->q, ctx->r[0], hrms, ctx->st, s));
 
-  // CG iterations.  Two direction buffers alternate so that a tile never reads a neighbour's new direction.
-  const bool tol_mode = params->tol > 0.0f;
+  // CG.  k_dir(k) produces x_k, r_k, p_k and y = D B p_k; k_apply(k) produces q_k = A p_k, alpha_k, beta_k.
+  // Residual and direction alternate between two buffers so that no tile reads a neighbour's new values.
+  HIP_TRY(launch_dir(g, cfg, 1, 0, 0, ctx->r[0], nullptr, nullptr, nullptr, ctx->p[0], hrms, ctx->y, kernel,
+                     ctx->partials, ctx->st, max_iters, tol, s));
+  const bool tol_mode = tol > 0.0f;
   int chunk_no = 0;
-  for (int it = 0; it < params->max_iters;) {
-    const int todo = tol_mode ? (params->max_iters - it < kCheckEvery ? params->max_iters - it : kCheckEvery)
-                              : params->max_iters - it;
-    for (int k = 0; k < todo; ++k, ++it) {
-      float* p_prev = (it & 1) ? ctx->p1 : ctx->p0;
-      float* p_cur = (it & 1) ? ctx->p0 : ctx->p1;
+  for (int k = 1; k <= max_iters;) {
+    const int todo = tol_mode ? (max_iters - k + 1 < kCheckEvery ? max_iters - k + 1 : kCheckEvery)
+                              : max_iters - k + 1;
+    for (int t = 0; t < todo; ++t, ++k) {
+      const int prev = (k - 1) & 1, cur = k & 1;
       hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
       if (ctx->profiling) {
         t0 = timing_event(ctx);
@@ -375,21 +411,20 @@ llp_status llp_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params
         if (!t0 || !t1 || !t2) return LLP_E_HIP;
         HIP_TRY(hipEventRecord(t0, s));
       }
-      HIP_TRY(launch_apply(g, variant, 1, ctx->r, p_prev, p_cur, kernel, ctx->G, ctx->MU, ctx->DI, ctx->q,
-                           ctx->partials, ctx->counters, ctx->st, s));
+      HIP_TRY(launch_apply(g, cfg, 1, ctx->p[prev], ctx->r[prev], ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, ctx->q,
+                           ctx->partials, ctx->st, s));
       if (ctx->profiling) HIP_TRY(hipEventRecord(t1, s));
-      HIP_TRY(launch_cg_update(g, hrms, ctx->r, p_cur, ctx->q, ctx->partials, ctx->counters, ctx->st,
-                               params->max_iters, params->tol, s));
+      HIP_TRY(launch_dir(g, cfg, 2, k == max_iters, k, ctx->r[prev], ctx->q, ctx->p[prev], ctx->r[cur],
+                         ctx->p[cur], hrms, ctx->y, kernel, ctx->partials, ctx->st, max_iters, tol, s));
       if (ctx->profiling) HIP_TRY(hipEventRecord(t2, s));
     }
     if (!tol_mode) break;
-    // Poll the band states of the previous chunk while this one runs; keep at most two chunks in flight.
+    // Poll the band states of the chunk before last while this one runs (at most two chunks in flight).
     const int slot = chunk_no & 1;
     if (chunk_no >= 2) {
       HIP_TRY(hipEventSynchronize(ctx->ev[slot]));
       bool any = false;
-      const ChanState* hs = ctx->h_st;
-      for (int i = 0; i < g.N; ++i) any |= hs[i].active != 0;
+      for (int i = 0; i < g.N; ++i) any |= ctx->h_st[i].active != 0;
       if (!any) break;
     }
     HIP_TRY(hipMemcpyAsync(ctx->h_st, ctx->st, sizeof(ChanState) * g.N, hipMemcpyDeviceToHost, s));
@@ -397,12 +432,12 @@ llp_status llp_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params
     ++chunk_no;
   }
 
-  // Final states, the true residual and the objective of the returned iterate.
+  // The true residual and the objective of the returned iterate.
   if (rep) {
-    HIP_TRY(launch_apply(g, variant, 0, hrms, nullptr, nullptr, kernel, ctx->G, ctx->MU, ctx->DI, ctx->q,
-                         ctx->partials, ctx->counters, ctx->st, s));
-    HIP_TRY(launch_residual_norm(g, ctx->b, ctx->q, ctx->partials, ctx->counters, ctx->results, s));
-    HIP_TRY(launch_objective(g, hrms, lrms, kernel, ctx->G, ctx->MU, ctx->DI, ctx->partials, ctx->counters,
+    v = apply_A_into(ctx, g, cfg, hrms, kernel, ctx->q, s);
+    if (v != LLP_OK) return v;
+    HIP_TRY(launch_residual_norm(g, ctx->b, ctx->q, ctx->partials, ctx->st, ctx->results, s));
+    HIP_TRY(launch_objective(g, hrms, lrms, kernel, ctx->G, ctx->MU, ctx->DI, ctx->partials, ctx->st,
                              ctx->results, s));
     HIP_TRY(hipMemcpyAsync(ctx->h_results, ctx->results, sizeof(double) * kResultSlots * g.N,
                            hipMemcpyDeviceToHost, s));

@@ -1,4 +1,4 @@
-// Internal declarations shared by the kernels (llp_kernels.hip) and the C ABI (llp_api.hip).
+// Internal declarations shared by the kernels (llp_kernels.hip, llp_operator.hip) and the C ABI (llp_api.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,63 +14,69 @@ struct Geom {
 
 // Per-band conjugate-gradient state, resident in device memory for the whole solve.
 struct ChanState {
-  double rho;     // r^T r of the current residual
+  double rho;     // r_k^T r_k (summed directly)
   double bnorm2;  // ||b||^2
-  double alpha;   // step of the current iteration
-  double beta;    // rho_new / rho_old, used to form the next direction
-  double gamma;   // p^T A p of the current iteration
-  int iters;      // iterations completed
+  double alpha;   // rho_k / (p_k^T A p_k)
+  double beta;    // ||r_k - alpha q_k||^2 / rho_k
+  double gamma;   // p_k^T A p_k
+  int iters;      // index of the current iterate x_k
   int active;     // 1 while the band still iterates
   int status;     // llp_status of the band
   int pad;
 };
 
+// What k_finalize does with a band's summed partials.
+enum FinOp { kFinBnorm = 0, kFinResult = 1, kFinDir = 2, kFinApply = 3 };
+
 // Reduction slots in the per-band result array (doubles [N][kResultSlots]).
 enum ResultSlot { kSlotTrueRes = 0, kSlotObjData = 1, kSlotObjLlp = 2, kResultSlots = 4 };
 
-// LDS layout of the tiled operator kernel.  All sizes in floats; computed on the host from the tile shape.
-struct ApplyLayout {
-  int TH, TW;         // output tile
-  int E;              // halo of the staged input region: max(2R, 2r+2)
-  int PH, PW;         // staged input region (TH+2E) x (TW+2E)
-  int YHm, YWm;       // capacity of the low-resolution intermediate D B p of the tile
-  int LH, LW;         // l = L p region: (TH + 2(2r+1)) x (TW + 2(2r+1))
-  int AH, AW;         // window-coefficient region: (TH + 2(r+1)) x (TW + 2(r+1))
-  int offP, offL, offX, offY, offU;
-  int total;          // floats
+// Launch configuration of the two iteration kernels (chosen per geometry, see the autotuner).
+struct OpConfig {
+  int fast;           // 1: kernels specialised on (c, R, r) (fast_path_available), 0: generic kernels
+  int dir_rows;       // generic k_dir: LR rows per tile, 4 or 8 (64 LR columns)
+  int apply_variant;  // k_apply tile shape index: generic 0 .. kApplyVariants-1 (apply_tile()); fast 0: 32x64,
+                      // 1: 16x64
 };
+bool fast_path_available(int C, int R, int r);
+int fast_apply_lds_floats(int C, int R, int r, int variant);
+constexpr int kApplyVariants = 3;
+constexpr int kMaxScale = 4;  // scale factors with built kernels: 1..4
 
-ApplyLayout apply_layout(int TH, int TW, int R, int r, int c, int n);
+// LDS sizes (floats) of the two iteration kernels; outputs their layout parameters.
+int dir_lds_floats(int C, int TYL, int R, int* PS_out);
+int apply_lds_floats(int C, int TH, int TW, int R, int r, int* offL, int* offX, int* offY, int* QPS_out);
+int apply_tile(int C, int variant, int* TH, int* TW);
 
-struct Workspace;  // defined in llp_api.hip
-
-// Tile shapes the operator kernel is built for (index = variant id).
-struct TileShape { int TH, TW; };
-constexpr int kNumTileVariants = 5;
-extern const TileShape kTileVariants[kNumTileVariants];
-
-// Kernel launchers (llp_kernels.hip).  All enqueue on `s` and return the launch status.
-hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, int* flag,
-                            hipStream_t s);
+// Kernel launchers.  All enqueue on `s` and return the launch status.  Reductions leave their partial sums in
+// `partials` and finish with a k_finalize launch.
+hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, hipStream_t s);
 hipError_t launch_check_finite(const float* a, size_t count, int* flag, hipStream_t s);
-hipError_t launch_rhs(const Geom& g, const float* X, const float* u, float* b, double* partials,
-                      unsigned* counters, ChanState* st, hipStream_t s);
-// mode 0: q = A z.  mode 1: CG direction update p_new = r + beta p_old, q = A p_new, gamma = p_new^T q.
-hipError_t launch_apply(const Geom& g, int variant, int mode, const float* zr, const float* p_old, float* p_new,
-                        const float* u, const float* G, const float* mu, const float* dinv, float* q,
-                        double* partials, unsigned* counters, ChanState* st, hipStream_t s);
-hipError_t launch_init_residual(const Geom& g, int from_init, const float* b, const float* q, float* r,
-                                float* x, double* partials, unsigned* counters, ChanState* st, int max_iters,
-                                float tol, hipStream_t s);
-hipError_t launch_cg_update(const Geom& g, float* x, float* r, const float* p, const float* q, double* partials,
-                            unsigned* counters, ChanState* st, int max_iters, float tol, hipStream_t s);
-hipError_t launch_residual_norm(const Geom& g, const float* b, const float* q, double* partials,
-                                unsigned* counters, double* results, hipStream_t s);
+hipError_t launch_finalize(const Geom& g, int op, const double* partials, int nblk, ChanState* st,
+                           double* results, int slot, int k_iter, int max_iters, float tol, hipStream_t s);
+// b = B^T D^T X and ||b||^2 (into the band states).
+hipError_t launch_rhs(const Geom& g, const float* X, const float* u, float* b, double* partials, ChanState* st,
+                      hipStream_t s);
+// r_0 = b (Z = 0, x set to 0) or r_0 = b - q (q = A Z0, x already Z0); resets the band states.
+hipError_t launch_init(const Geom& g, int from_init, const float* b, const float* q, float* r, float* x,
+                       ChanState* st, hipStream_t s);
+// mode 0: y = D B z (z = rin).  mode 1: p_0 = r_0 (rin), y = D B p_0, rho_0.  mode 2: the update of iteration
+// k (x, r from alpha; p from beta), y = D B p_k, rho_k; final_step skips p and y.  Modes 1 and 2 finish with
+// the stopping rule for iterate k.
+hipError_t launch_dir(const Geom& g, const OpConfig& cfg, int mode, int final_step, int k_iter, const float* rin,
+                      const float* qin, const float* pin, float* rout, float* pout, float* x, float* y,
+                      const float* u, double* partials, ChanState* st, int max_iters, float tol, hipStream_t s);
+// mode 0: q = A z (z = p, y = D B z).  mode 1: q = A p_k and the dot products -> alpha_k, beta_k.
+hipError_t launch_apply(const Geom& g, const OpConfig& cfg, int mode, const float* p, const float* r,
+                        const float* y, const float* u, const float* G, const float* mu, const float* dinv, float* q,
+                        double* partials, ChanState* st, hipStream_t s);
+hipError_t launch_residual_norm(const Geom& g, const float* b, const float* q, double* partials, ChanState* st,
+                                double* results, hipStream_t s);
 hipError_t launch_objective(const Geom& g, const float* z, const float* X, const float* u, const float* G,
-                            const float* mu, const float* dinv, double* partials, unsigned* counters,
-                            double* results, hipStream_t s);
+                            const float* mu, const float* dinv, double* partials, ChanState* st, double* results,
+                            hipStream_t s);
 
-// Maximum number of reduction partials per band any launcher needs for geometry g.
+// Reduction partials per band (each up to 3 doubles) any launcher needs for geometry g.
 size_t max_partials_per_band(const Geom& g);
 
 }  // namespace llp

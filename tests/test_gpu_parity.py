@@ -63,6 +63,12 @@ OP_SHAPES = [  # N, h, w, c, n, r
     (1, 8, 8, 2, 1, 0),       # n = 1, r = 0
     (2, 34, 18, 4, 33, 4),    # largest kernel and window
     (1, 80, 48, 2, 11, 3),
+    # shapes on the specialised kernels (c in {2, 4}, n in {9..17, 29}, r in {1, 2})
+    (2, 20, 18, 2, 9, 1),
+    (1, 16, 40, 2, 17, 2),
+    (1, 12, 20, 4, 29, 1),
+    (2, 24, 24, 4, 11, 2),
+    (1, 9, 17, 4, 15, 1),     # ragged on both tile shapes
 ]
 
 
@@ -115,6 +121,36 @@ def test_objective(ctx, torch_dev, shape):
     prob = Problem(u=u, c=c, Y=Y, r=r, lam=f32(lam), eps=f32(eps))
     want = oracle.objective(P, X, prob)
     np.testing.assert_allclose(got, want, rtol=1e-6)
+
+
+@pytest.fixture(scope="module")
+def generic_ctx(torch_dev):
+    import os
+    os.environ["LLP_FORCE_GENERIC"] = "1"
+    try:
+        c = B.Context(0)
+    finally:
+        del os.environ["LLP_FORCE_GENERIC"]
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("shape", [(4, 64, 64, 4, 9, 1), (2, 24, 24, 4, 17, 2), (2, 20, 18, 2, 9, 1),
+                                   (1, 12, 20, 4, 29, 1)])
+def test_specialised_matches_generic(ctx, generic_ctx, torch_dev, shape):
+    """The specialised kernels and the generic ones compute the same operator and the same CG iterates."""
+    N, h, w, c, n, r = shape
+    rng = rng_for(7, *shape)
+    X, Y, u, P = scenes.random_problem(rng, N, h * c, w * c, c, n)
+    d = {k: dev(torch_dev, v) for k, v in dict(X=X, Y=Y, u=u, P=P).items()}
+    kw = dict(c=c, r=r, lam=0.05, eps=1e-3)
+    a1 = host(ctx.apply_A(d["P"], d["Y"], d["u"], **kw))
+    a2 = host(generic_ctx.apply_A(d["P"], d["Y"], d["u"], **kw))
+    assert np.all(rel_l2(a1, a2) < 2e-6)
+    skw = dict(r=r, lam=0.05, eps=1e-3, max_iters=25, tol=0.0)
+    z1, _, _ = ctx.pansharpen(d["X"], d["Y"], d["u"], **skw)
+    z2, _, _ = generic_ctx.pansharpen(d["X"], d["Y"], d["u"], **skw)
+    assert np.all(rel_l2(host(z1), host(z2)) < 1e-5)
 
 
 # ------------------------------------------------------------------------------------- the solve ---
