@@ -7,8 +7,9 @@ the objective of the result.  The workload is the 8-band scene with a 2048 x 204
 (x4), a 17 x 17 anisotropic Gaussian blur, window radius 2, lambda 1e-2, eps 1e-3.
 
 Prints one JSON line.  `value` is HRMS Mpixel*bands per second (N*H*W / time per step).  `roofline` is the
-operator kernel's algorithmic HBM bytes over its measured average launch time (HIP events on the solver's
-stream, summed over the timed steps).  `cpu_baseline` is the FP64 CPU oracle on a bounded sample of the same
+dominant kernel's algorithmic HBM bytes over its measured launch time (HIP events on the solver's stream around
+each launch, summed over the timed steps); `traffic` is that kernel's counter-measured HBM bytes per launch from
+profiles/traffic_8x2048.json while the kernel sources match the record.  `cpu_baseline` is the FP64 CPU oracle on a bounded sample of the same
 scene (its setup plus a few CG iterations, extrapolated to the GPU's iteration count).
 """
 from __future__ import annotations
@@ -21,6 +22,27 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_8x2048.json")
+
+
+def measured_traffic(kernel_prefix):
+    """HBM bytes per launch of the kernel from the committed counter record, or None if the kernel sources have
+    changed since the counters were taken (or there is no record for it)."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+        h = hashlib.sha256()
+        for f in rec["source_files"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != rec["source_hash"]:
+            return None
+        for name, v in rec["kernels"].items():
+            if name.startswith(kernel_prefix):
+                return v["traffic_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+    return None
 
 
 def parse():
@@ -121,6 +143,11 @@ def main():
     it_ms = kt["apply_ms"] + kt["dir_ms"]
     iter_gbs = (apply_bytes + dir_bytes) / (it_ms * 1e-3) / 1e9 if it_ms > 0 else 0.0
     dominant = "k_apply" if kt["apply_ms"] >= kt["dir_ms"] else "k_dir"
+    # counter-measured HBM bytes per launch (8 x 2048^2 workload, all bands active) for the specialised kernels
+    traffic = None
+    if args.side is None:
+        traffic = measured_traffic("llp::k_apply_fast<4, 8, 2, 16, 64, 1>" if dominant == "k_apply"
+                                   else "llp::k_dir_fast<4, 8, 4, 2>")
     dom = {
         "k_apply": dict(kernel="k_apply (q = A p: B^T D^T y + lambda L^T M L p; p^T q, r^T q, q^T q)",
                         achieved=apply_gbs, ms=kt["apply_ms"], n=launches),
@@ -163,7 +190,7 @@ def main():
             "unit": "GB/s",
             "frac": round(dom["achieved"] / HBM_PEAK_GBS, 4),
             "avg_launch_us": round(dom["ms"] / max(dom["n"], 1) * 1e3, 2),
-            "traffic": None,
+            "traffic": round(traffic) if traffic is not None else None,
         },
     }
     if not args.no_cpu_baseline:

@@ -26,6 +26,10 @@ constexpr int odd(int v) { return v | 1; }
 constexpr int al4(int v) { return (v + 3) & ~3; }
 constexpr int pad_to(int v, int want) { return v + ((want - v % 64) + 64) % 64; }
 
+// Periodic index for -n <= i < 2n (the host routes a geometry here only when every tile region overhangs the
+// image by less than one period; see fast_path_fits).
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
 }  // namespace
 
 // ==================================================================================== k_dir_fast ===
@@ -60,7 +64,6 @@ __global__ __launch_bounds__(kBlock) void k_dir_fast(Geom g, DirArgs A, const fl
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row0 = C * (m0 - S::HYR), col0 = C * (k0 - S::HYR);
   constexpr int in_r0 = C * S::HYR, in_r1 = C * (S::HYR + S::TYL), in_c0 = C * S::HYR, in_c1 = C * (S::HYR + S::TXL);
-  const bool wrapped = row0 < 0 || col0 < 0 || row0 + S::RH > H || col0 + S::RW > W;
   // Per-band planes; every element offset below is a 32-bit unsigned offset from these (H W <= 2^31).
   const float* __restrict__ rin = A.rin + (size_t)ch * HW;
   const float* __restrict__ qin = A.qin + (size_t)ch * HW;
@@ -79,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_dir_fast(Geom g, DirArgs A, const fl
     const int gc = col0 + col;
     cval[ci] = col < S::RW;
     cown[ci] = col >= in_c0 && col < in_c1 && gc < W;
-    gcol[ci] = wrapped ? wrapi(gc, W) : gc;
+    gcol[ci] = wrap1(gc, W);
     lcol[ci] = (col % C) * S::PS + col / C;
   }
   double acc = 0.0;
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_dir_fast(Geom g, DirArgs A, const fl
       const int row = row_b + j * kWaves;
       const int gr = row0 + row;
       rval[j] = row < S::RH;
-      roff[j] = (unsigned)((wrapped ? wrapi(gr, H) : gr) * W);
+      roff[j] = (unsigned)(wrap1(gr, H) * W);
       own_row[j] = row >= in_r0 && row < in_r1 && gr < H;
 #pragma unroll
       for (int ci = 0; ci < NCI; ++ci) {
@@ -259,12 +262,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
   const int H = g.H, W = g.W;
   const size_t HW = (size_t)H * W;
   if (MODE == 1 && !A.st[ch].active) return;
-  const bool wrapped = i0 - S::E < 0 || j0 - S::E < 0 || i0 + TH + S::E > H || j0 + TW + S::E > W;
   // 32-bit unsigned element offsets within a plane (H W <= 2^31), so loads take a scalar base plus a vector
   // offset.
-  auto goff = [&](int gi, int gj) -> unsigned {
-    return wrapped ? (unsigned)(wrapi(gi, H) * W + wrapi(gj, W)) : (unsigned)(gi * W + gj);
-  };
+  auto goff = [&](int gi, int gj) -> unsigned { return (unsigned)(wrap1(gi, H) * W + wrap1(gj, W)); };
   const float* __restrict__ Gp = A.G;
   const float* __restrict__ MUp = A.MU;
   const float* __restrict__ DIp = A.DI;
@@ -274,19 +274,86 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
   float* Ys = smem + S::oY;      // y on the LR cells the tile's taps reach
   const float* pc = A.p + (size_t)ch * HW;
 
-  // S1: stage p on [i0-E, i0+TH+E) x [j0-E, j0+TW+E) and y on LR [i0/C-YL, i0/C+NI+YR) x [...].
-  {
-    constexpr int NP = (S::PH * S::PW + kBlock - 1) / kBlock;
-    float pv[NP];
+  // Prefetch: every global value this thread will need in the later stages is requested now, so that the
+  // workgroup waits for global memory once instead of once per stage (barriers do not wait for these loads).
+  constexpr int T2 = S::LW * S::NS2, T4 = S::AW * S::NS4, T6 = S::W3 * S::NS6, T8 = S::NI * S::NJ * S::SPLIT;
+  constexpr int NT2 = (T2 + kBlock - 1) / kBlock, NT4 = (T4 + kBlock - 1) / kBlock, NT6 = (T6 + kBlock - 1) / kBlock,
+                NT8 = (T8 + kBlock - 1) / kBlock;
+  float g2[NT2][K], mu4[NT4][K], di4[NT4][K], g6[NT6][K];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const int idx = threadIdx.x + k * kBlock;
-      if (idx < S::PH * S::PW) pv[k] = pc[goff(i0 - S::E + idx / S::PW, j0 - S::E + idx % S::PW)];
+  for (int k = 0; k < NT2; ++k) {
+    const int task = min((int)threadIdx.x + k * kBlock, T2 - 1);
+    const int col = task % S::LW, y0 = (task / S::LW) * K;
+    const int gcj = wrap1(j0 - S::h1 + col, W);
+#pragma unroll
+    for (int t = 0; t < K; ++t) g2[k][t] = Gp[(unsigned)(wrap1(i0 - S::h1 + min(y0 + t, S::LH - 1), H) * W + gcj)];
+  }
+#pragma unroll
+  for (int k = 0; k < NT4; ++k) {
+    const int task = min((int)threadIdx.x + k * kBlock, T4 - 1);
+    const int col = task % S::AW, y0 = (task / S::AW) * K;
+    const int gcj = wrap1(j0 - S::h2 + col, W);
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const unsigned o = (unsigned)(wrap1(i0 - S::h2 + min(y0 + t, S::AH - 1), H) * W + gcj);
+      mu4[k][t] = MUp[o];
+      di4[k][t] = DIp[o];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NT6; ++k) {
+    const int task = min((int)threadIdx.x + k * kBlock, T6 - 1);
+    const int col = task % S::W3, y0 = (task / S::W3) * K;
+    const int gcj = wrap1(j0 - 1 + col, W);
+#pragma unroll
+    for (int t = 0; t < K; ++t) g6[k][t] = Gp[(unsigned)(wrap1(i0 - 1 + min(y0 + t, S::H3 - 1), H) * W + gcj)];
+  }
+  float p8[NT8][S::CR][C], r8[NT8][S::CR][C];
+  if (MODE == 1) {
+    const float* rc0 = A.r + (size_t)ch * HW;
+#pragma unroll
+    for (int k = 0; k < NT8; ++k) {
+      const int task = min((int)threadIdx.x + k * kBlock, T8 - 1);
+      const int J = task % S::NJ, I = (task / S::NJ) % S::NI, part = task / (S::NI * S::NJ);
+      const int j = min(j0 + C * J, W - C);
+#pragma unroll
+      for (int f = 0; f < S::CR; ++f) {
+        const int i = min(i0 + C * I + part * S::CR + f, H - 1);
+        const unsigned o = (unsigned)(i * W + j);
+#pragma unroll
+        for (int fj = 0; fj < C; ++fj) {
+          p8[k][f][fj] = pc[o + fj];
+          r8[k][f][fj] = rc0[o + fj];
+        }
+      }
+    }
+  }
+
+  // S1: stage p on [i0-E, i0+TH+E) x [j0-E, j0+TW+E) (rows by wave, columns by lane; the row offset is a
+  // scalar, the lane's column indices are computed once) and y on LR [i0/C-YL, i0/C+NI+YR) x [...].
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NCI = (S::PW + 63) / 64;
+    int pcol[NCI];
+#pragma unroll
+    for (int ci = 0; ci < NCI; ++ci) pcol[ci] = wrap1(j0 - S::E + min(ci * 64 + lane, S::PW - 1), W);
+    constexpr int RPW = (S::PH + kWaves - 1) / kWaves;
+    float pv[RPW][NCI];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int row = wave + k * kWaves;
+      const unsigned ro = (unsigned)(wrap1(i0 - S::E + min(row, S::PH - 1), H) * W);
+#pragma unroll
+      for (int ci = 0; ci < NCI; ++ci) pv[k][ci] = pc[ro + (unsigned)pcol[ci]];
     }
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const int idx = threadIdx.x + k * kBlock;
-      if (idx < S::PH * S::PW) R1[idx] = pv[k];
+    for (int k = 0; k < RPW; ++k) {
+      const int row = wave + k * kWaves;
+#pragma unroll
+      for (int ci = 0; ci < NCI; ++ci) {
+        const int col = ci * 64 + lane;
+        if (row < S::PH && col < S::PW) R1[row * S::PW + col] = pv[k][ci];
+      }
     }
   }
   {
@@ -294,13 +361,16 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
     const int I0 = i0 / C - S::YL, J0 = j0 / C - S::YL;
     for (int idx = threadIdx.x; idx < S::YH * S::YW; idx += kBlock) {
       const int row = idx / S::YW, col = idx % S::YW;
-      Ys[row * S::YWs + col] = yc[(unsigned)(wrapi(I0 + row, g.h) * g.w + wrapi(J0 + col, g.w))];
+      Ys[row * S::YWs + col] = yc[(unsigned)(wrap1(I0 + row, g.h) * g.w + wrap1(J0 + col, g.w))];
     }
   }
   __syncthreads();
 
   // S2: l = L p (and G l) on rows [-h1, TH+h1), cols [-h1, TW+h1); column strips of K rows, stored transposed.
-  for (int task = threadIdx.x; task < S::LW * S::NS2; task += kBlock) {
+#pragma unroll
+  for (int kt = 0; kt < NT2; ++kt) {
+    const int task = threadIdx.x + kt * kBlock;
+    if (task >= T2) break;
     const int col = task % S::LW, y0 = (task / S::LW) * K;
     float cv[K + 2], lv[K], rv[K];
 #pragma unroll
@@ -310,16 +380,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
       lv[t] = R1[(y0 + t + 1) * S::PW + col];
       rv[t] = R1[(y0 + t + 1) * S::PW + col + 2];
     }
-    float gv[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) gv[t] = Gp[goff(i0 - S::h1 + min(y0 + t, S::LH - 1), j0 - S::h1 + col)];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
       const int y = y0 + t;
       if (y < S::LH) {
         const float l = 4.0f * cv[t + 1] - cv[t] - cv[t + 2] - lv[t] - rv[t];
         LT[col * S::LHs + y] = l;
-        R2[col * S::LHs + y] = gv[t] * l;
+        R2[col * S::LHs + y] = g2[kt][t] * l;
       }
     }
   }
@@ -352,7 +419,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
   constexpr float inv_nw = 1.0f / (float)(WN * WN);
   float* AT = R2;
   float* BT = R2 + S::AWa * S::AHs;
-  for (int task = threadIdx.x; task < S::AW * S::NS4; task += kBlock) {
+#pragma unroll
+  for (int kt = 0; kt < NT4; ++kt) {
+    const int task = threadIdx.x + kt * kBlock;
+    if (task >= T4) break;
     const int col = task % S::AW, y0 = (task / S::AW) * K;
     float v1[K + WN - 1], v2[K + WN - 1], o1[K], o2[K];
 #pragma unroll
@@ -360,20 +430,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
       v1[t] = HB1[(y0 + t) * S::AWs + col];
       v2[t] = HB2[(y0 + t) * S::AWs + col];
     }
-    float muv[K], div_[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const unsigned o = goff(i0 - S::h2 + min(y0 + t, S::AH - 1), j0 - S::h2 + col);
-      muv[t] = MUp[o];
-      div_[t] = DIp[o];
-    }
     window_sums<K, WN>(v1, o1);
     window_sums<K, WN>(v2, o2);
 #pragma unroll
     for (int t = 0; t < K; ++t) {
       const int y = y0 + t;
       if (y < S::AH) {
-        const float mu = muv[t], di = div_[t];
+        const float mu = mu4[kt][t], di = di4[kt][t];
         const float m1 = o1[t] * inv_nw, m2 = o2[t] * inv_nw;
         const float av = (m2 - mu * m1) * di;
         AT[col * S::AHs + y] = av;
@@ -409,7 +472,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
   // S6: M l = |w| l - G S(a) - S(b) on rows [-1, TH+1), cols [-1, TW+1); column strips, row-major out.
   constexpr float nwf = (float)(WN * WN);
   float* Ml = R2;
-  for (int task = threadIdx.x; task < S::W3 * S::NS6; task += kBlock) {
+#pragma unroll
+  for (int kt = 0; kt < NT6; ++kt) {
+    const int task = threadIdx.x + kt * kBlock;
+    if (task >= T6) break;
     const int col = task % S::W3, y0 = (task / S::W3) * K;
     float v1[K + WN - 1], v2[K + WN - 1], o1[K], o2[K];
 #pragma unroll
@@ -417,9 +483,6 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
       v1[t] = HA1[(y0 + t) * S::W3s + col];
       v2[t] = HA2[(y0 + t) * S::W3s + col];
     }
-    float gv[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) gv[t] = Gp[goff(i0 - 1 + min(y0 + t, S::H3 - 1), j0 - 1 + col)];
     window_sums<K, WN>(v1, o1);
     window_sums<K, WN>(v2, o2);
 #pragma unroll
@@ -427,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
       const int y = y0 + t;
       if (y < S::H3) {
         const float l = LT[(col - 1 + S::h1) * S::LHs + (y - 1 + S::h1)];
-        Ml[y * S::W3s + col] = nwf * l - gv[t] * o1[t] - o2[t];
+        Ml[y * S::W3s + col] = nwf * l - g6[kt][t] * o1[t] - o2[t];
       }
     }
   }
@@ -461,8 +524,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
   // S8: per LR cell: q = B^T D^T y + lambda L M l, written row by row; partial p^T q, r^T q, q^T q.
   double v[3] = {0.0, 0.0, 0.0};
   float* qc = A.q + (size_t)ch * HW;
-  const float* rc = A.r + (size_t)ch * HW;
-  for (int task = threadIdx.x; task < S::NI * S::NJ * S::SPLIT; task += kBlock) {
+#pragma unroll
+  for (int kt = 0; kt < NT8; ++kt) {
+    const int task = threadIdx.x + kt * kBlock;
+    if (task >= T8) break;
     const int J = task % S::NJ, I = (task / S::NJ) % S::NI, part = task / (S::NI * S::NJ);
     float yv[S::YK][S::YK];
 #pragma unroll
@@ -497,28 +562,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
         const unsigned o = (unsigned)(i * W + j);
         if constexpr (C == 4) {
           *reinterpret_cast<float4*>(qc + o) = make_float4(qv[0], qv[1], qv[2], qv[3]);
-          if (MODE == 1) {
-            const float4 pp = *reinterpret_cast<const float4*>(pc + o);
-            const float4 rr = *reinterpret_cast<const float4*>(rc + o);
-            v[0] += (double)pp.x * qv[0] + (double)pp.y * qv[1] + (double)pp.z * qv[2] + (double)pp.w * qv[3];
-            v[1] += (double)rr.x * qv[0] + (double)rr.y * qv[1] + (double)rr.z * qv[2] + (double)rr.w * qv[3];
-          }
         } else if constexpr (C == 2) {
           *reinterpret_cast<float2*>(qc + o) = make_float2(qv[0], qv[1]);
-          if (MODE == 1) {
-            const float2 pp = *reinterpret_cast<const float2*>(pc + o);
-            const float2 rr = *reinterpret_cast<const float2*>(rc + o);
-            v[0] += (double)pp.x * qv[0] + (double)pp.y * qv[1];
-            v[1] += (double)rr.x * qv[0] + (double)rr.y * qv[1];
-          }
         } else {
 #pragma unroll
+          for (int fj = 0; fj < C; ++fj) qc[o + fj] = qv[fj];
+        }
+        if (MODE == 1) {
+#pragma unroll
           for (int fj = 0; fj < C; ++fj) {
-            qc[o + fj] = qv[fj];
-            if (MODE == 1) {
-              v[0] += (double)pc[o + fj] * qv[fj];
-              v[1] += (double)rc[o + fj] * qv[fj];
-            }
+            v[0] += (double)p8[kt][f][fj] * qv[fj];
+            v[1] += (double)r8[kt][f][fj] * qv[fj];
           }
         }
         if (MODE == 1) {
@@ -593,6 +647,22 @@ hipError_t run_apply_fast(const Geom& g, ApplyArgs A, const float* u, hipStream_
 #define LLP_FAST_R_LIST2(X, r) X(2, 4, r) X(2, 5, r) X(2, 6, r) X(2, 7, r) X(2, 8, r)
 
 }  // namespace
+
+// Every tile region of both fast kernels must overhang the image by less than one period (wrap1).
+bool fast_path_fits(const Geom& g, int dir_rows, int apply_variant) {
+  const int C = g.c, R = g.R, r = g.r;
+  const int HYR = (R + C - 1) / C;
+  const int k0_last = ((g.w - 1) / 64) * 64, m0_last = ((g.h - 1) / dir_rows) * dir_rows;
+  if (C * HYR > g.W || C * HYR > g.H) return false;
+  if (C * (k0_last + 64 + HYR) > 2 * g.W || C * (m0_last + dir_rows + HYR) > 2 * g.H) return false;
+  const int TH = apply_variant == 0 ? 32 : 16, TW = 64, E = 2 * r + 2;
+  const int i0_last = ((g.H - 1) / TH) * TH, j0_last = ((g.W - 1) / TW) * TW;
+  if (E > g.H || E > g.W || i0_last + TH + E > 2 * g.H || j0_last + TW + E > 2 * g.W) return false;
+  const int YL = R / C, YR = (C - 1 + R) / C;
+  if (YL > g.h || YL > g.w) return false;
+  if (i0_last / C + TH / C + YR > 2 * g.h || j0_last / C + TW / C + YR > 2 * g.w) return false;
+  return true;
+}
 
 bool fast_path_available(int C, int R, int r) {
   if (r != 1 && r != 2) return false;

@@ -39,6 +39,7 @@ struct OpConfig {
                       // 1: 16x64
 };
 bool fast_path_available(int C, int R, int r);
+bool fast_path_fits(const Geom& g, int dir_rows, int apply_variant);
 int fast_apply_lds_floats(int C, int R, int r, int variant);
 constexpr int kApplyVariants = 3;
 constexpr int kMaxScale = 4;  // scale factors with built kernels: 1..4
@@ -60,16 +61,19 @@ hipError_t launch_rhs(const Geom& g, const float* X, const float* u, float* b, d
 // r_0 = b (Z = 0, x set to 0) or r_0 = b - q (q = A Z0, x already Z0); resets the band states.
 hipError_t launch_init(const Geom& g, int from_init, const float* b, const float* q, float* r, float* x,
                        ChanState* st, hipStream_t s);
-// mode 0: y = D B z (z = rin).  mode 1: p_0 = r_0 (rin), y = D B p_0, rho_0.  mode 2: the update of iteration
-// k (x, r from alpha; p from beta), y = D B p_k, rho_k; final_step skips p and y.  Modes 1 and 2 finish with
-// the stopping rule for iterate k.
+// mode 0: y = D B z (z = rin).  mode 1: p_0 = r_0 (rin), y = D B p_0, partials of rho_0.  mode 2: the update
+// of iteration k (x, r from alpha; p from beta), y = D B p_k, partials of rho_k; final_step skips p and y.
+// Modes 1 and 2 are followed by launch_finalize(kFinDir, nblk = dir_ntiles) for the stopping rule of x_k.
 hipError_t launch_dir(const Geom& g, const OpConfig& cfg, int mode, int final_step, int k_iter, const float* rin,
                       const float* qin, const float* pin, float* rout, float* pout, float* x, float* y,
                       const float* u, double* partials, ChanState* st, int max_iters, float tol, hipStream_t s);
-// mode 0: q = A z (z = p, y = D B z).  mode 1: q = A p_k and the dot products -> alpha_k, beta_k.
+// mode 0: q = A z (z = p, y = D B z).  mode 1: q = A p_k and partials of the dot products; followed by
+// launch_finalize(kFinApply, nblk = apply_ntiles) for alpha_k, beta_k.
 hipError_t launch_apply(const Geom& g, const OpConfig& cfg, int mode, const float* p, const float* r,
                         const float* y, const float* u, const float* G, const float* mu, const float* dinv, float* q,
                         double* partials, ChanState* st, hipStream_t s);
+int dir_ntiles(const Geom& g, const OpConfig& cfg);
+int apply_ntiles(const Geom& g, const OpConfig& cfg);
 hipError_t launch_residual_norm(const Geom& g, const float* b, const float* q, double* partials, ChanState* st,
                                 double* results, hipStream_t s);
 hipError_t launch_objective(const Geom& g, const float* z, const float* X, const float* u, const float* G,

@@ -432,10 +432,20 @@ hipError_t launch_dir(const Geom& g, const OpConfig& cfg, int mode, int final_st
   A.partials = partials;
   A.st = st;
   A.pstride = (int)max_partials_per_band(g);
-  hipError_t e = launch_dir_kernel(g, cfg, A, u, s);
-  if (e != hipSuccess || mode == 0) return e;
-  const int ntiles = ((g.w + 63) / 64) * ((g.h + cfg.dir_rows - 1) / cfg.dir_rows);
-  return launch_finalize(g, kFinDir, partials, ntiles, st, nullptr, 0, k_iter, max_iters, tol, s);
+  (void)max_iters;
+  (void)tol;
+  return launch_dir_kernel(g, cfg, A, u, s);
+}
+
+int dir_ntiles(const Geom& g, const OpConfig& cfg) {
+  return ((g.w + 63) / 64) * ((g.h + cfg.dir_rows - 1) / cfg.dir_rows);
+}
+
+int apply_ntiles(const Geom& g, const OpConfig& cfg) {
+  int TH = 16, TW = 64;
+  if (cfg.fast) TH = cfg.apply_variant == 0 ? 32 : 16;
+  else if (apply_tile(g.c, cfg.apply_variant, &TH, &TW) != 0) return 0;
+  return ((g.W + TW - 1) / TW) * ((g.H + TH - 1) / TH);
 }
 
 static hipError_t launch_dir_kernel(const Geom& g, const OpConfig& cfg, DirArgs A, const float* u, hipStream_t s) {
@@ -472,13 +482,7 @@ hipError_t launch_apply(const Geom& g, const OpConfig& cfg, int mode, const floa
   A.partials = partials;
   A.st = st;
   A.pstride = (int)max_partials_per_band(g);
-  hipError_t e = launch_apply_kernel(g, cfg, A, u, s);
-  if (e != hipSuccess || mode == 0) return e;
-  int TH = 16, TW = 64;
-  if (cfg.fast) TH = cfg.apply_variant == 0 ? 32 : 16;
-  else if (apply_tile(g.c, cfg.apply_variant, &TH, &TW) != 0) return hipErrorInvalidValue;
-  const int ntiles = ((g.W + TW - 1) / TW) * ((g.H + TH - 1) / TH);
-  return launch_finalize(g, kFinApply, partials, ntiles, st, nullptr, 0, 0, 0, 0.0f, s);
+  return launch_apply_kernel(g, cfg, A, u, s);
 }
 
 static hipError_t launch_apply_kernel(const Geom& g, const OpConfig& cfg, ApplyArgs A, const float* u,
