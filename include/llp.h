@@ -110,6 +110,35 @@ llp_status llp_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params
                           const float* pan, const float* kernel, const float* init, float* hrms,
                           llp_report* rep, hipStream_t stream);
 
+/* ---- Batched solve ---------------------------------------------------------------------------------------- */
+
+/* Flags of llp_pansharpen_batch. */
+#define LLP_BATCH_NO_GRAPH 1 /* enqueue the batched iteration kernels directly instead of replaying a graph */
+#define LLP_BATCH_SERIAL 2   /* solve the scenes one after another with llp_pansharpen (for comparison) */
+
+/* Solve eq. (Z_ini_matting) for every band of S scenes of any sizes at once.  The paper solves the bands of a
+ * scene independently (the parallel loop over bands of Algorithm "Fast Pansharpening", Sec. III-B); here all
+ * bands of all scenes advance together: each CG iteration is one launch of the operator kernel and one of
+ * the update kernel per class of scenes that share (c, n, r) and a tile shape, plus two launches that finish
+ * the per-band reductions, and a band that meets its stopping rule stops while the others go on.  Chunks of
+ * iterations are captured once in a HIP graph and replayed (cached in the context while the classes and the
+ * workspace stay the same).  Scenes without specialised kernels (llp_validate accepts them, but their
+ * (c, n, r) has no specialised kernels in this build) are solved after the batch with llp_pansharpen.
+ *   S        number of scenes, >= 0 (0: nothing to do, LLP_OK)
+ *   shapes   host array [S]; params: ONE llp_params for all scenes (host)
+ *   lrms, pan, kernel, hrms   host arrays [S] of device pointers, laid out as for llp_pansharpen
+ *   init     host array [S] of device pointers, read when params->init_mode == 1 (may be NULL otherwise)
+ *   rep      host array of sum(shapes[i].N) reports in scene order, band order within a scene, or NULL
+ *   flags    0 or LLP_BATCH_* bits
+ * Device work runs on a stream owned by the context that first waits for the work already enqueued on
+ * `stream`; the call returns after all of it has finished.  Returns the worst status over all bands
+ * (errors before warnings); LLP_E_NONFINITE if any scene's inputs hold NaN or Inf (the other scenes' outputs
+ * and reports are still valid).  Argument errors are detected before any device work. */
+llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, const llp_params* params,
+                                const float* const* lrms, const float* const* pan, const float* const* kernel,
+                                const float* const* init, float* const* hrms, llp_report* rep, int flags,
+                                hipStream_t stream);
+
 /* ---- Operator entry points (the steps of the solve, exposed for parity checks) ------------------------ */
 
 /* PAN statistics that define M_LY (eq. matting_matrix with I = L Y): G = L Y [H][W], and per window centre

@@ -63,7 +63,14 @@ _SIGS = {
     "llp_get_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
     "llp_objective": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
                                      ctypes.POINTER(ctypes.c_double), _vp]),
+    "llp_pansharpen_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(Shape), ctypes.POINTER(Params),
+                                            ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(Report),
+                                            ctypes.c_int, _vp]),
 }
+
+BATCH_NO_GRAPH = 1
+BATCH_SERIAL = 2
 
 
 def lib() -> ctypes.CDLL:
@@ -158,6 +165,38 @@ class Context:
         allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
         _check(st, "llp_pansharpen", allow)
         return out, ([rp.as_dict() for rp in reps] if report else None), st
+
+    def pansharpen_batch(self, scenes, *, r: int, lam: float, eps: float, max_iters: int, tol: float = 0.0,
+                         inits=None, outs=None, report: bool = True, flags: int = 0, stream=None,
+                         allow_not_converged: bool = True):
+        """Solve every band of several scenes together (llp_pansharpen_batch).  `scenes` is a sequence of
+        (lrms, pan, kernel) device tensors.  Returns (list of hrms, list of per-scene report lists or None,
+        status)."""
+        import torch
+        S = len(scenes)
+        shapes = (Shape * max(S, 1))()
+        for i, (X, Y, u) in enumerate(scenes):
+            shapes[i] = shape_of(X, Y, u)
+        if outs is None:
+            outs = [torch.empty((X.shape[0], Y.shape[0], Y.shape[1]), dtype=torch.float32, device=X.device)
+                    for X, Y, u in scenes]
+        arr = lambda ts: (_vp * max(S, 1))(*[_ptr(t) for t in ts])  # noqa: E731
+        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), 1 if inits is not None else 0)
+        nb = sum(shapes[i].N for i in range(S))
+        reps = (Report * max(nb, 1))() if report else None
+        st = lib().llp_pansharpen_batch(self._h, S, shapes, ctypes.byref(prm), arr([s[0] for s in scenes]),
+                                        arr([s[1] for s in scenes]), arr([s[2] for s in scenes]),
+                                        arr(inits) if inits is not None else None, arr(outs), reps, int(flags),
+                                        _stream(stream))
+        allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        _check(st, "llp_pansharpen_batch", allow)
+        out_reps = None
+        if report:
+            out_reps, k = [], 0
+            for i in range(S):
+                out_reps.append([reps[k + c].as_dict() for c in range(shapes[i].N)])
+                k += shapes[i].N
+        return outs, out_reps, st
 
     def pan_stats(self, pan, *, N: int, c: int, n: int, r: int, eps: float, stream=None):
         import torch

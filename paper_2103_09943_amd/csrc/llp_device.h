@@ -54,10 +54,9 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* red, doub
 
 // Workgroups are dealt round-robin to the 8 XCDs.  Remap the flat id so that each XCD walks a contiguous run of
 // (tile, band) pairs, bands of one tile adjacent: halos and per-scene PAN statistics stay in one XCD's L2.
-__device__ __forceinline__ void tile_and_band(int ntiles, int N, int& tile, int& ch) {
+__device__ __forceinline__ void tile_and_band(int ntiles, int N, int bid, int& tile, int& ch) {
   const int nb = ntiles * N;
   const int b8 = (nb / 8) * 8;
-  const int bid = blockIdx.x;
   const int lin = bid < b8 ? (bid % 8) * (b8 / 8) + bid / 8 : bid;
   tile = lin / N;
   ch = lin % N;
@@ -98,10 +97,15 @@ struct ApplyArgs {
   int offL, offX, offY, QPS;  // LDS layout (floats); the region buffer starts at 0
 };
 
+
 // Fast path (llp_fast.hip): kernels specialised on (C, R, r).
 bool fast_path_available(int C, int R, int r);
 int fast_apply_lds_floats(int C, int R, int r, int variant);
 hipError_t launch_dir_fast(const Geom& g, DirArgs A, int tyl, const float* u, hipStream_t s);
 hipError_t launch_apply_fast(const Geom& g, int variant, ApplyArgs A, const float* u, hipStream_t s);
+// Batched CG launches over the scenes [first, first+count) of a class table (all of one (c, R, r) class and one
+// launch configuration): every workgroup finds its scene by binary search on the block offsets.  parity selects
+// the residual/direction buffers: iteration k reads r[parity], p[parity] and writes r[1-parity], p[1-parity].
+// total_blocks == 0 only prepares the kernel (its LDS limit) without launching it.
 
 }  // namespace llp

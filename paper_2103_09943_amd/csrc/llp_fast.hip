@@ -45,13 +45,13 @@ struct DirShape {
 };
 
 template <int C, int R, int TYL, int MODE>
-__global__ __launch_bounds__(kBlock) void k_dir_fast(Geom g, DirArgs A, const float* __restrict__ u) {
+__device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, const float* __restrict__ u, int bid) {
   using S = DirShape<C, R, TYL>;
   constexpr int n = 2 * R + 1;
   extern __shared__ float smem[];
   __shared__ double red[kWaves];
   int tile, ch;
-  tile_and_band(A.ntiles, g.N, tile, ch);
+  tile_and_band(A.ntiles, g.N, bid, tile, ch);
   const int m0 = (tile / A.tiles_x) * S::TYL, k0 = (tile % A.tiles_x) * S::TXL;
   const int H = g.H, W = g.W;
   const size_t HW = (size_t)H * W;
@@ -251,13 +251,14 @@ __device__ __forceinline__ void cell_data_term(const float (&yv)[YK][YK], const 
 }
 
 template <int C, int R, int r, int TH, int TW, int MODE>
-__global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, const float* __restrict__ u) {
+__device__ __forceinline__ void apply_fast_body(const Geom& g, const ApplyArgs& A, const float* __restrict__ u,
+                                                int bid) {
   using S = ApplyShape<C, R, r, TH, TW>;
   constexpr int K = S::K, WN = S::WN;
   extern __shared__ float smem[];
   __shared__ double red[3 * kWaves];
   int tile, ch;
-  tile_and_band(A.ntiles, g.N, tile, ch);
+  tile_and_band(A.ntiles, g.N, bid, tile, ch);
   const int i0 = (tile / A.tiles_x) * TH, j0 = (tile % A.tiles_x) * TW;
   const int H = g.H, W = g.W;
   const size_t HW = (size_t)H * W;
@@ -586,6 +587,81 @@ __global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, cons
   block_partials<3>(v, red, A.partials + (size_t)ch * A.pstride * 3 + (size_t)tile * 3);
 }
 
+// ================================================================================ kernel wrappers ===
+
+template <int C, int R, int TYL, int MODE>
+__global__ __launch_bounds__(kBlock) void k_dir_fast(Geom g, DirArgs A, const float* __restrict__ u) {
+  dir_fast_body<C, R, TYL, MODE>(g, A, u, blockIdx.x);
+}
+
+template <int C, int R, int r, int TH, int TW, int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply_fast(Geom g, ApplyArgs A, const float* __restrict__ u) {
+  apply_fast_body<C, R, r, TH, TW, MODE>(g, A, u, blockIdx.x);
+}
+
+// Scene of workgroup b: the last table entry whose first block is <= b.
+template <bool kDir>
+__device__ __forceinline__ int find_scene(const SceneDesc* __restrict__ t, int count, int b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int b0 = kDir ? t[mid].dir_block0 : t[mid].apply_block0;
+    if (b0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Batched CG iteration kernels (mode 2 / mode 1 of the single-scene kernels) over a table of scenes.
+template <int C, int R, int TYL>
+__global__ __launch_bounds__(kBlock) void k_dir_fast_batch(const SceneDesc* __restrict__ t, int count, int parity,
+                                                           ChanState* __restrict__ st) {
+  const int si = find_scene<true>(t, count, blockIdx.x);
+  const SceneDesc& d = t[si];
+  const int local = blockIdx.x - d.dir_block0;  // scenes start on multiples of 8 workgroups (one per XCD)
+  if (local >= d.dir_ntiles * d.g.N) return;
+  DirArgs A{};
+  A.mode = 2;
+  A.rin = d.r[parity];
+  A.qin = d.q;
+  A.pin = d.p[parity];
+  A.rout = d.r[1 - parity];
+  A.pout = d.p[1 - parity];
+  A.x = d.x;
+  A.y = d.y;
+  A.partials = d.partials;
+  A.st = st + d.band0;
+  A.pstride = d.pstride;
+  A.tiles_x = (d.g.w + DirShape<C, R, TYL>::TXL - 1) / DirShape<C, R, TYL>::TXL;
+  A.ntiles = d.dir_ntiles;
+  A.PS = DirShape<C, R, TYL>::PS;
+  dir_fast_body<C, R, TYL, 2>(d.g, A, d.u, local);
+}
+
+template <int C, int R, int r, int TH, int TW>
+__global__ __launch_bounds__(kBlock) void k_apply_fast_batch(const SceneDesc* __restrict__ t, int count, int parity,
+                                                             ChanState* __restrict__ st) {
+  const int si = find_scene<false>(t, count, blockIdx.x);
+  const SceneDesc& d = t[si];
+  const int local = blockIdx.x - d.apply_block0;
+  if (local >= d.apply_ntiles * d.g.N) return;
+  ApplyArgs A{};
+  A.mode = 1;
+  A.p = d.p[parity];
+  A.r = d.r[parity];
+  A.y = d.y;
+  A.G = d.G;
+  A.MU = d.MU;
+  A.DI = d.DI;
+  A.q = d.q;
+  A.partials = d.partials;
+  A.st = st + d.band0;
+  A.pstride = d.pstride;
+  A.tiles_x = (d.g.W + TW - 1) / TW;
+  A.ntiles = d.apply_ntiles;
+  apply_fast_body<C, R, r, TH, TW, 1>(d.g, A, d.u, local);
+}
+
 // ===================================================================================== dispatch ===
 
 namespace {
@@ -701,6 +777,57 @@ hipError_t launch_apply_fast(const Geom& g, int variant, ApplyArgs A, const floa
   LLP_FAST_R_LIST4(LLP_APPLY_CASE, 1)
   LLP_FAST_R_LIST4(LLP_APPLY_CASE, 2)
 #undef LLP_APPLY_CASE
+  return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <int C, int R, int TYL>
+hipError_t run_dir_batch(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, hipStream_t s) {
+  const size_t bytes = (size_t)DirShape<C, R, TYL>::LDS * sizeof(float);
+  hipError_t e = set_lds_fast(k_dir_fast_batch<C, R, TYL>, bytes);
+  if (e != hipSuccess) return e;
+  if (blocks == 0) return hipSuccess;  // prepare only (before a graph capture)
+  hipLaunchKernelGGL((k_dir_fast_batch<C, R, TYL>), dim3(blocks), dim3(kBlock), bytes, s, t, count, parity, st);
+  return hipGetLastError();
+}
+
+template <int C, int R, int r, int TH, int TW>
+hipError_t run_apply_batch(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, hipStream_t s) {
+  const size_t bytes = (size_t)ApplyShape<C, R, r, TH, TW>::total * sizeof(float);
+  hipError_t e = set_lds_fast(k_apply_fast_batch<C, R, r, TH, TW>, bytes);
+  if (e != hipSuccess) return e;
+  if (blocks == 0) return hipSuccess;  // prepare only (before a graph capture)
+  hipLaunchKernelGGL((k_apply_fast_batch<C, R, r, TH, TW>), dim3(blocks), dim3(kBlock), bytes, s, t, count, parity,
+                     st);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_dir_fast_batch(const SceneDesc* table, int count, int total_blocks, int C, int R, int tyl,
+                                 int parity, ChanState* st, hipStream_t s) {
+#define LLP_DIRB_CASE(CC, RR, rr)                                                                     \
+  if (C == CC && R == RR)                                                                             \
+    return tyl == 8 ? run_dir_batch<CC, RR, 8>(table, count, total_blocks, parity, st, s)             \
+                    : run_dir_batch<CC, RR, 4>(table, count, total_blocks, parity, st, s);
+  LLP_FAST_R_LIST2(LLP_DIRB_CASE, 0)
+  LLP_FAST_R_LIST4(LLP_DIRB_CASE, 0)
+#undef LLP_DIRB_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_apply_fast_batch(const SceneDesc* table, int count, int total_blocks, int C, int R, int r,
+                                   int variant, int parity, ChanState* st, hipStream_t s) {
+#define LLP_APPLYB_CASE(CC, RR, rr)                                                                   \
+  if (C == CC && R == RR && r == rr)                                                                  \
+    return variant == 0 ? run_apply_batch<CC, RR, rr, 32, 64>(table, count, total_blocks, parity, st, s) \
+                        : run_apply_batch<CC, RR, rr, 16, 64>(table, count, total_blocks, parity, st, s);
+  LLP_FAST_R_LIST2(LLP_APPLYB_CASE, 1)
+  LLP_FAST_R_LIST2(LLP_APPLYB_CASE, 2)
+  LLP_FAST_R_LIST4(LLP_APPLYB_CASE, 1)
+  LLP_FAST_R_LIST4(LLP_APPLYB_CASE, 2)
+#undef LLP_APPLYB_CASE
   return hipErrorInvalidValue;
 }
 

@@ -83,4 +83,35 @@ hipError_t launch_objective(const Geom& g, const float* z, const float* X, const
 // Reduction partials per band (each up to 3 doubles) any launcher needs for geometry g.
 size_t max_partials_per_band(const Geom& g);
 
+// One scene of a batch (llp_pansharpen_batch): geometry, the caller's arrays, the scene's workspace, and the
+// scene's place in the batched launches of its kernel class.
+struct SceneDesc {
+  Geom g;
+  const float* X;  // LRMS [N][h][w]
+  const float* Y;  // PAN [H][W]
+  const float* u;  // kernel [n][n]
+  float* x;        // HRMS [N][H][W] (the iterate)
+  float *G, *MU, *DI, *b, *q, *y;
+  float* r[2];
+  float* p[2];
+  double* partials;  // [N][pstride][3]
+  int pstride;
+  int band0;                  // first band of the scene in the batch's band-state array
+  int dir_ntiles, apply_ntiles;
+  int dir_block0, apply_block0;  // first workgroup of the scene in its class's k_dir / k_apply launch
+};
+
+// k_finalize (kFinDir / kFinApply) for all `bands` bands of the `count` scenes of a table; kFinDir advances each
+// active band's iteration count on the device.
+hipError_t launch_finalize_batch(int op, const SceneDesc* table, int count, int bands, ChanState* st,
+                                 int max_iters, float tol, hipStream_t s);
+// Batched CG launches over the scenes [first, first+count) of a class table (all of one (c, R, r) class and one
+// launch configuration): every workgroup finds its scene by binary search on the block offsets.  parity selects
+// the residual/direction buffers: iteration k reads r[parity], p[parity] and writes r[1-parity], p[1-parity].
+// total_blocks == 0 only prepares the kernel (its LDS limit) without launching it.
+hipError_t launch_dir_fast_batch(const SceneDesc* table, int count, int total_blocks, int C, int R, int tyl,
+                                 int parity, ChanState* st, hipStream_t s);
+hipError_t launch_apply_fast_batch(const SceneDesc* table, int count, int total_blocks, int C, int R, int r,
+                                   int variant, int parity, ChanState* st, hipStream_t s);
+
 }  // namespace llp

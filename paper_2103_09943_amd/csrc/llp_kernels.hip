@@ -77,6 +77,47 @@ hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, 
 
 // ------------------------------------------------------------------------------- reduction finalisation ---
 
+// Applies a band's summed partials s[] (op kFinDir: rho of x_k; kFinApply: gamma, sigma, tau) to its CG state.
+__device__ void finish_band(int op, const double (&s)[3], ChanState& c, int k_iter, int max_iters, float tol) {
+  if (op == kFinDir) {  // rho_k of the iterate x_k, and the stopping rule
+    const double rho = s[0];
+    c.rho = rho;
+    c.iters = k_iter;
+    if (!isfinite(rho)) {
+      c.status = -6;
+      c.active = 0;
+    } else if (rho == 0.0 || (tol > 0.0f && sqrt(rho) <= (double)tol * sqrt(c.bnorm2))) {
+      c.status = 0;
+      c.active = 0;
+    } else if (k_iter >= max_iters) {
+      c.status = tol > 0.0f ? 1 : 0;
+      c.active = 0;
+    }
+  } else if (op == kFinApply) {  // gamma = p^T A p, sigma = r^T A p, tau = |A p|^2 -> alpha, beta
+    const double gam = s[0], sig = s[1], tau = s[2];
+    c.gamma = gam;
+    if (!(gam > 0.0) || !isfinite(gam) || !isfinite(sig) || !isfinite(tau)) {
+      c.status = -6;
+      c.active = 0;
+    } else {
+      const double al = c.rho / gam;
+      double rt = c.rho - 2.0 * al * sig + al * al * tau;
+      if (rt < 0.0) rt = 0.0;
+      c.alpha = al;
+      c.beta = rt / c.rho;
+    }
+  }
+}
+
+// Sum, in a fixed order, of nblk partials of K doubles each (result in thread 0).
+__device__ __forceinline__ void sum_partials(const double* __restrict__ base, int nblk, int K, double (&s)[3],
+                                             double* red) {
+  s[0] = s[1] = s[2] = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kBlock)
+    for (int k = 0; k < K; ++k) s[k] += base[(size_t)i * K + k];
+  block_sums<3>(s, red);
+}
+
 // One workgroup per band: adds the band's nblk partials (K doubles each) in a fixed order and applies them.
 __global__ __launch_bounds__(kBlock) void k_finalize(int op, const double* __restrict__ partials, int pstride,
                                                      int nblk, ChanState* __restrict__ st,
@@ -85,55 +126,42 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int op, const double* __res
   __shared__ double red[3 * kWaves];
   const int ch = blockIdx.x;
   if ((op == kFinDir || op == kFinApply) && !st[ch].active) return;
-  const int K = op == kFinApply ? 3 : 1;
-  const double* base = partials + (size_t)ch * pstride * 3;
-  double s[3] = {0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < nblk; i += kBlock)
-    for (int k = 0; k < K; ++k) s[k] += base[(size_t)i * K + k];
-  block_sums<3>(s, red);
+  double s[3];
+  sum_partials(partials + (size_t)ch * pstride * 3, nblk, op == kFinApply ? 3 : 1, s, red);
   if (threadIdx.x != 0) return;
   ChanState& c = st[ch];
-  switch (op) {
-    case kFinBnorm:
-      c.bnorm2 = s[0];
-      break;
-    case kFinResult:
-      results[ch * kResultSlots + slot] = s[0];
-      break;
-    case kFinDir: {  // rho_k of the iterate x_k, and the stopping rule
-      const double rho = s[0];
-      c.rho = rho;
-      c.iters = k_iter;
-      if (!isfinite(rho)) {
-        c.status = -6;
-        c.active = 0;
-      } else if (rho == 0.0 || (tol > 0.0f && sqrt(rho) <= (double)tol * sqrt(c.bnorm2))) {
-        c.status = 0;
-        c.active = 0;
-      } else if (k_iter >= max_iters) {
-        c.status = tol > 0.0f ? 1 : 0;
-        c.active = 0;
-      }
-      break;
-    }
-    case kFinApply: {  // gamma = p^T A p, sigma = r^T A p, tau = |A p|^2 -> alpha, beta
-      const double gam = s[0], sig = s[1], tau = s[2];
-      c.gamma = gam;
-      if (!(gam > 0.0) || !isfinite(gam) || !isfinite(sig) || !isfinite(tau)) {
-        c.status = -6;
-        c.active = 0;
-      } else {
-        const double al = c.rho / gam;
-        double rt = c.rho - 2.0 * al * sig + al * al * tau;
-        if (rt < 0.0) rt = 0.0;
-        c.alpha = al;
-        c.beta = rt / c.rho;
-      }
-      break;
-    }
-    default:
-      break;
+  if (op == kFinBnorm) c.bnorm2 = s[0];
+  else if (op == kFinResult) results[ch * kResultSlots + slot] = s[0];
+  else finish_band(op, s, c, k_iter, max_iters, tol);
+}
+
+// Batched finalisation (kFinDir / kFinApply) over every band of a scene table; one workgroup per band.  The
+// iteration index lives on the device: kFinDir advances a band from x_{k-1} to x_k.
+__global__ __launch_bounds__(kBlock) void k_finalize_batch(int op, const SceneDesc* __restrict__ t, int count,
+                                                           ChanState* __restrict__ st, int max_iters, float tol) {
+  __shared__ double red[3 * kWaves];
+  const int band = blockIdx.x;
+  if (!st[band].active) return;
+  int lo = 0, hi = count - 1;  // scene of the band: the last entry whose band0 <= band
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t[mid].band0 <= band) lo = mid;
+    else hi = mid - 1;
   }
+  const SceneDesc& d = t[lo];
+  const int ch = band - d.band0;
+  const int nblk = op == kFinApply ? d.apply_ntiles : d.dir_ntiles;
+  double s[3];
+  sum_partials(d.partials + (size_t)ch * d.pstride * 3, nblk, op == kFinApply ? 3 : 1, s, red);
+  if (threadIdx.x != 0) return;
+  ChanState& c = st[band];
+  finish_band(op, s, c, c.iters + 1, max_iters, tol);
+}
+
+hipError_t launch_finalize_batch(int op, const SceneDesc* table, int count, int bands, ChanState* st,
+                                 int max_iters, float tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_batch, dim3(bands), dim3(kBlock), 0, s, op, table, count, st, max_iters, tol);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Geom& g, int op, const double* partials, int nblk, ChanState* st,

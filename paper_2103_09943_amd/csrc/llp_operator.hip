@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(Geom g, DirArgs A, const float* 
   extern __shared__ float smem[];
   __shared__ double red[kWaves];
   int tile, ch;
-  tile_and_band(A.ntiles, g.N, tile, ch);
+  tile_and_band(A.ntiles, g.N, blockIdx.x, tile, ch);
   const int m0 = (tile / A.tiles_x) * TYL, k0 = (tile % A.tiles_x) * TXL;
   const int H = g.H, W = g.W, n = g.n, R = g.R;
   const size_t HW = (size_t)H * W;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, ApplyArgs A, const flo
   extern __shared__ float smem[];
   __shared__ double red[3 * kWaves];
   int tile, ch;
-  tile_and_band(A.ntiles, g.N, tile, ch);
+  tile_and_band(A.ntiles, g.N, blockIdx.x, tile, ch);
   const int i0 = (tile / A.tiles_x) * TH, j0 = (tile % A.tiles_x) * TW;
   const int H = g.H, W = g.W, n = g.n, R = g.R, r = g.r;
   const size_t HW = (size_t)H * W;

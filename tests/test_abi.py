@@ -50,6 +50,8 @@ def test_null_context_is_rejected(lib):
     assert st == B.E_ARG
     assert lib.llp_apply_A(None, ctypes.byref(shp), ctypes.byref(prm), None, None, None, None, None) == B.E_ARG
     assert lib.llp_create(None, 0) == B.E_ARG
+    assert lib.llp_pansharpen_batch(None, 1, ctypes.byref(shp), ctypes.byref(prm), None, None, None, None, None,
+                                    None, 0, None) == B.E_ARG
 
 
 GOOD = dict(N=4, h=64, w=64, c=4, n=9)
