@@ -5,6 +5,9 @@ One step = one full call of the library on one synthetic scene with inputs alrea
 right-hand sides, conjugate gradients from Z = 0 to ||r|| <= 1e-6 ||b|| for every band, the true residual and
 the objective of the result.  The workload is the 8-band scene with a 2048 x 2048 PAN image and 512 x 512 LRMS
 (x4), a 17 x 17 anisotropic Gaussian blur, window radius 2, lambda 1e-2, eps 1e-3.
+With --workload batch, one step is one batched call (llp_pansharpen_batch) on 64 scenes of uneven sizes (PAN
+side from {256, 384, ..., 1024}, 4 or 8 bands, 9..17-tap Gaussian blurs, r 1, tol 1e-6); the line also
+carries the same scenes solved one after another (`serial_value`).
 
 Prints one JSON line.  `value` is HRMS Mpixel*bands per second (N*H*W / time per step).  `roofline` is the
 dominant kernel's algorithmic HBM bytes over its measured launch time (HIP events on the solver's stream around
@@ -53,6 +56,8 @@ def parse():
     ap.add_argument("--side", type=int, default=None, help="PAN side override (same recipe, smaller scene)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["scene", "batch"], default="scene")
+    ap.add_argument("--scenes", type=int, default=64, help="batch workload: number of scenes")
     return ap.parse_args()
 
 
@@ -88,12 +93,163 @@ def cpu_baseline(sc, st, gpu_iters, budget_s):
     }
 
 
+def _batch_scene(s):
+    from paper_2103_09943_amd import scenes
+    sc, st = scenes.config_scene(2, s)
+    return sc.X, sc.Y, sc.u, sc.c
+
+
+def apply_bytes_model(HW, c, band_iters, busy_launches):
+    """Algorithmic HBM bytes of k_apply and k_dir for one scene (float32), c = resolution gap:
+      k_apply: read p, r and y (1/c^2 of a plane), write q          -> 12 + 4/c^2 per active pixel-band
+               plus the PAN statistics G, mu, dinv once per launch  -> 12 per pixel
+      k_dir:   read r, q, p, x; write r, p, x and y                 -> 28 + 4/c^2 per active pixel-band"""
+    c2 = float(c * c)
+    return ((12.0 + 4.0 / c2) * HW * band_iters + 12.0 * HW * busy_launches,
+            (28.0 + 4.0 / c2) * HW * band_iters)
+
+
+def cpu_baseline_batch(host, settings, reps, budget_s):
+    """FP64 oracle on the host, on a sample of the batch: the setup and CG iterations of the first scenes that
+    fit the budget; the per-pixel setup cost and per-pixel-band iteration cost extrapolated to the whole batch
+    at the GPU's iteration counts."""
+    import numpy as np
+    import oracle
+    from oracle.llp import Problem
+
+    t_setup = t_iter = 0.0
+    px = pxb = 0
+    used = 0
+    for (X, Y, u, c) in host:
+        t0 = time.perf_counter()
+        prob = Problem(u=u, c=c, Y=Y, r=settings.r, lam=float(np.float32(settings.lam)),
+                       eps=float(np.float32(settings.eps)))
+        b = oracle.rhs(X, prob)
+        t1 = time.perf_counter()
+        oracle.cg(prob, b, max_iters=2)
+        t2 = time.perf_counter()
+        t_setup += t1 - t0
+        t_iter += (t2 - t1) / 2
+        px += Y.size
+        pxb += X.shape[0] * Y.size
+        used += 1
+        if t_setup + 2 * t_iter > budget_s / 2:
+            break
+    setup_per_px = t_setup / px
+    iter_per_pxb = t_iter / pxb
+    total_px = sum(Y.size for _, Y, _, _ in host)
+    total_pxb_it = sum(r["iters"] * Y.size for (X, Y, u, c), rs in zip(host, reps) for r in rs)
+    total_pxb = sum(X.shape[0] * Y.size for X, Y, u, c in host)
+    t_solve = setup_per_px * total_px + iter_per_pxb * total_pxb_it
+    return {
+        "value": total_pxb / t_solve / 1e6,
+        "unit": "Mpixel*bands/s",
+        "cores": os.cpu_count(),
+        "kind": "oracle",
+        "sample": f"setup + 2 CG iterations of every band of the first {used} scene(s), FP64 numpy/scipy.fft "
+                  f"(fft workers = all cores); per-pixel setup and per-pixel-band iteration costs extrapolated "
+                  f"to all {len(host)} scenes at the GPU's iteration counts",
+    }
+
+
+def main_batch(args):
+    from concurrent.futures import ProcessPoolExecutor
+
+    import torch
+
+    from paper_2103_09943_amd import binding as B
+    from paper_2103_09943_amd import scenes
+
+    with ProcessPoolExecutor(min(8, os.cpu_count() or 1)) as ex:
+        host = list(ex.map(_batch_scene, range(args.scenes)))
+    _, st = scenes.config_scene(2, 0, side=256)
+    ds = [(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), torch.from_numpy(u).cuda()) for X, Y, u, _ in host]
+    outs = [torch.empty((X.shape[0],) + Y.shape, dtype=torch.float32, device="cuda") for X, Y, u, _ in host]
+    pxb = sum(X.shape[0] * Y.size for X, Y, u, _ in host)
+    ctx = B.Context(0)
+    kw = dict(r=st.r, lam=st.lam, eps=st.eps, max_iters=st.max_iters, tol=st.tol, outs=outs)
+    for _ in range(args.warmup):
+        ctx.pansharpen_batch(ds, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, reps, status = ctx.pansharpen_batch(ds, **kw)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # the same scenes one after another (single-scene solves), one timed call
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.pansharpen_batch(ds, flags=B.BATCH_SERIAL, **kw)
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - t1
+    # one timed call with events around every class launch (eager launches of the same kernels)
+    ctx.set_profiling(True)
+    ctx.kernel_times(reset=True)
+    _, preps, _ = ctx.pansharpen_batch(ds, **kw)
+    kt = ctx.kernel_times(reset=True)
+    ctx.set_profiling(False)
+    ctx.close()
+
+    apply_b = dir_b = 0.0
+    for (X, Y, u, c), rs in zip(host, preps):
+        a, d = apply_bytes_model(Y.size, c, sum(r["iters"] for r in rs), max(r["iters"] for r in rs))
+        apply_b += a
+        dir_b += d
+    apply_gbs = apply_b / (kt["apply_ms"] * 1e-3) / 1e9 if kt["apply_ms"] > 0 else 0.0
+    dir_gbs = dir_b / (kt["dir_ms"] * 1e-3) / 1e9 if kt["dir_ms"] > 0 else 0.0
+    dominant = "k_apply" if kt["apply_ms"] >= kt["dir_ms"] else "k_dir"
+    dom = dict(k_apply=(apply_gbs, kt["apply_ms"], kt["apply_launches"]),
+               k_dir=(dir_gbs, kt["dir_ms"], kt["dir_launches"]))[dominant]
+    iters = [r["iters"] for rs in reps for r in rs]
+    value = pxb / (elapsed / args.steps) / 1e6
+    line = {
+        "metric": "HRMS Mpixel·channels/s at fixed residual tol, plain vs CNN warm-start",
+        "value": round(value, 3),
+        "unit": "Mpixel*bands/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched plain LLP solve (cold start, one call), {len(host)} scenes, PAN side 256..1024, "
+                        f"4 or 8 bands, 9..17-tap Gaussian blurs, x4, r={st.r}, lambda={st.lam}, eps={st.eps}, "
+                        f"tol={st.tol}; {pxb / 1e6:.1f} Mpixel*bands",
+            "status": status,
+            "iters_min_mean_max": [min(iters), round(sum(iters) / len(iters), 1), max(iters)],
+            "serial_value": round(pxb / serial_s / 1e6, 3),
+            "batch_over_serial": round(serial_s / (elapsed / args.steps), 3),
+            "k_apply_gbs": round(apply_gbs, 1),
+            "k_dir_gbs": round(dir_gbs, 1),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dominant + " (all kernel classes of the batch, eager launches with events)",
+            "achieved": round(dom[0], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(dom[0] / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(dom[1] / max(dom[2], 1) * 1e3, 2),
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(host, st, reps, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the per-band solves would shard "
               "across GPUs with no communication, but this build runs on one device.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return main_batch(args)
     import numpy as np
     import torch
 
@@ -127,17 +283,11 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     value = N * H * W / (elapsed / args.steps) / 1e6
     iters = [r["iters"] for r in reps[-1]]
-    # Algorithmic HBM bytes per active pixel-band (float32), c = resolution gap:
-    #   k_apply: read p, r and y (1/c^2 of a plane), write q          -> 12 + 4/c^2
-    #            plus the PAN statistics G, mu, dinv once per launch  -> 12 per pixel
-    #   k_dir:   read r, q, p, x; write r, p, x and y                 -> 28 + 4/c^2
     HW = H * W
-    c2 = float(sc.c * sc.c)
     band_iters = sum(sum(r["iters"] for r in rep) for rep in reps)
     launches = kt["apply_launches"]
     busy_launches = sum(max(r["iters"] for r in rep) for rep in reps)  # launches with at least one active band
-    apply_bytes = (12.0 + 4.0 / c2) * HW * band_iters + 12.0 * HW * busy_launches
-    dir_bytes = (28.0 + 4.0 / c2) * HW * band_iters
+    apply_bytes, dir_bytes = apply_bytes_model(HW, sc.c, band_iters, busy_launches)
     apply_gbs = apply_bytes / (kt["apply_ms"] * 1e-3) / 1e9 if kt["apply_ms"] > 0 else 0.0
     dir_gbs = dir_bytes / (kt["dir_ms"] * 1e-3) / 1e9 if kt["dir_ms"] > 0 else 0.0
     it_ms = kt["apply_ms"] + kt["dir_ms"]

@@ -171,8 +171,10 @@ typedef struct {
   long long dir_launches;
 } llp_kernel_times;
 
-/* Enable (1) or disable (0) timing of the CG kernels of later llp_pansharpen calls on this context.  Timing
- * brackets each launch with HIP events on the call's stream; it adds two event records per launch. */
+/* Enable (1) or disable (0) timing of the CG kernels of later llp_pansharpen and llp_pansharpen_batch calls on
+ * this context.  Timing brackets each launch with HIP events on the call's stream; it adds two event records
+ * per launch.  A timed llp_pansharpen_batch enqueues its iteration kernels directly (no graph); each class
+ * launch counts as one launch. */
 llp_status llp_set_profiling(llp_ctx* ctx, int enable);
 
 /* Accumulated kernel times since the last reset (host struct); reset != 0 clears them afterwards. */

@@ -302,18 +302,30 @@ llp_status ensure_batch_mirrors(llp_ctx* ctx, int bands, int scenes) {
   return LLP_OK;
 }
 
-// Enqueues `count` CG iterations of every class; the first reads the buffers of `parity`.
+// Enqueues `count` CG iterations of every class; the first reads the buffers of `parity`.  With `prof` set,
+// every class launch is bracketed by timing events of that context.
 llp_status enqueue_batch_iters(const std::vector<BatchClass>& classes, const SceneDesc* d_table, int nscenes,
                                int nbands, ChanState* st, int count, int parity, int max_iters, float tol,
-                               hipStream_t s) {
+                               hipStream_t s, llp_ctx* prof) {
+  std::vector<hipEvent_t> ev(prof ? 4 * classes.size() : 0);
   for (int j = 0; j < count; ++j) {
     const int par = (parity + j) & 1;
-    for (const BatchClass& k : classes)
+    for (auto& e : ev)
+      if (!(e = timing_event(prof))) return LLP_E_HIP;
+    for (size_t c = 0; c < classes.size(); ++c) {
+      const BatchClass& k = classes[c];
+      if (prof) HIP_TRY(hipEventRecord(ev[4 * c], s));
       HIP_TRY(launch_apply_fast_batch(d_table + k.first, k.count, k.apply_blocks, k.C, k.R, k.r, k.variant, par, st,
                                       s));
+      if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 1], s));
+    }
     HIP_TRY(launch_finalize_batch(kFinApply, d_table, nscenes, nbands, st, max_iters, tol, s));
-    for (const BatchClass& k : classes)
+    for (size_t c = 0; c < classes.size(); ++c) {
+      const BatchClass& k = classes[c];
+      if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 2], s));
       HIP_TRY(launch_dir_fast_batch(d_table + k.first, k.count, k.dir_blocks, k.C, k.R, k.dir_rows, par, st, s));
+      if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 3], s));
+    }
     HIP_TRY(launch_finalize_batch(kFinDir, d_table, nscenes, nbands, st, max_iters, tol, s));
   }
   return LLP_OK;
@@ -744,7 +756,9 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     }
 
     // CG iterations of all bands together, in chunks of kCheckEvery (even: every chunk starts on parity 0).
-    const bool use_graph = !(flags & LLP_BATCH_NO_GRAPH);
+    // Timing (llp_set_profiling) needs events between the launches: then the chunks are enqueued directly.
+    llp_ctx* prof = ctx->profiling ? ctx : nullptr;
+    const bool use_graph = !(flags & LLP_BATCH_NO_GRAPH) && !prof;
     if (use_graph && max_iters > 0) {
       uint32_t tol_bits = 0;
       memcpy(&tol_bits, &tol, sizeof(tol_bits));
@@ -772,7 +786,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         llp_status cv = LLP_OK;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) cv = LLP_E_HIP;
         if (cv == LLP_OK)
-          cv = enqueue_batch_iters(classes, d_table, nf, nbands, st, kCheckEvery, 0, max_iters, tol, cs);
+          cv = enqueue_batch_iters(classes, d_table, nf, nbands, st, kCheckEvery, 0, max_iters, tol, cs, nullptr);
         if (hipStreamEndCapture(cs, &graph) != hipSuccess && cv == LLP_OK) cv = LLP_E_HIP;
         (void)hipStreamDestroy(cs);
         if (cv == LLP_OK && hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -788,7 +802,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     for (int k = 1; k <= max_iters; k += kCheckEvery) {
       if (use_graph) HIP_TRY(hipGraphLaunch(ctx->gexec, s));
       else {
-        v = enqueue_batch_iters(classes, d_table, nf, nbands, st, kCheckEvery, 0, max_iters, tol, s);
+        v = enqueue_batch_iters(classes, d_table, nf, nbands, st, kCheckEvery, 0, max_iters, tol, s, prof);
         if (v != LLP_OK) return v;
       }
       if (!tol_mode) continue;
@@ -824,6 +838,10 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     HIP_TRY(hipMemcpyAsync(ctx->h_bst[0], st, sizeof(ChanState) * nbands, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(ctx->h_bflags, bflags, sizeof(int) * nf, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (prof) {
+      v = collect_times(ctx);
+      if (v != LLP_OK) return v;
+    }
 
     bool nonfinite = false;
     for (int i = 0; i < nf; ++i) {

@@ -184,3 +184,18 @@ def test_batch_nonfinite_scene(ctx, torch_dev, batch_host):
     with pytest.raises(B.LlpError) as ei:
         ctx.pansharpen_batch(ds, r=R, lam=LAM, eps=EPS, max_iters=5)
     assert ei.value.status == B.E_NONFINITE
+
+
+def test_batch_timed_launches_agree(ctx, torch_dev, batch_host):
+    """With kernel timing on, the batch runs its kernels eagerly between events: same results, times counted."""
+    ds = to_dev(torch_dev, batch_host)
+    g_outs, g_reps, _ = ctx.pansharpen_batch(ds, r=R, lam=LAM, eps=EPS, max_iters=40, tol=1e-6)
+    ctx.set_profiling(True)
+    ctx.kernel_times(reset=True)
+    try:
+        outs, reps, _ = ctx.pansharpen_batch(ds, r=R, lam=LAM, eps=EPS, max_iters=40, tol=1e-6)
+        kt = ctx.kernel_times(reset=True)
+    finally:
+        ctx.set_profiling(False)
+    assert_same(torch_dev, outs, g_outs, reps, g_reps)
+    assert kt["apply_launches"] > 0 and kt["apply_ms"] > 0 and kt["dir_ms"] > 0
