@@ -115,6 +115,7 @@ llp_status llp_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params
 /* Flags of llp_pansharpen_batch. */
 #define LLP_BATCH_NO_GRAPH 1 /* enqueue the batched iteration kernels directly instead of replaying a graph */
 #define LLP_BATCH_SERIAL 2   /* solve the scenes one after another with llp_pansharpen (for comparison) */
+#define LLP_BATCH_AUTOTUNE 4 /* first run llp_autotune on one scene of every class without a tuned entry */
 
 /* Solve eq. (Z_ini_matting) for every band of S scenes of any sizes at once.  The paper solves the bands of a
  * scene independently (the parallel loop over bands of Algorithm "Fast Pansharpening", Sec. III-B); here all
@@ -138,6 +139,36 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
                                 const float* const* lrms, const float* const* pan, const float* const* kernel,
                                 const float* const* init, float* const* hrms, llp_report* rep, int flags,
                                 hipStream_t stream);
+
+/* ---- Autotuner ------------------------------------------------------------------------------------------- */
+
+typedef struct {
+  int fast;                   /* 1: kernels specialised on (c, n, r); 0: generic kernels */
+  int dir_rows;               /* LR rows per tile of the update kernel (4 or 8) */
+  int apply_variant;          /* tile shape of the operator kernel */
+  double us_per_iter;         /* measured time of one CG iteration (both kernels, all bands) with that choice */
+  double default_us_per_iter; /* the same for the untuned default choice */
+  int candidates;             /* configurations timed */
+} llp_tune_result;
+
+/* Time every launch configuration the build has for this geometry (iters CG iterations of the given scene per
+ * candidate, HIP events around the kernels, the fastest of three runs after an untimed one) and keep the
+ * fastest (the default unless another is at least 3% faster) for the geometry's class: (c, n, r) and the
+ * image area H*W in half-octaves.  Later solves of that class on this context, single or batched, use it
+ * (unless LLP_DIR_ROWS / LLP_APPLY_VARIANT override the choice).  Inputs as for llp_pansharpen; scratch:
+ * device [N][H][W] float32 written during tuning, or NULL (allocated and freed by the call);
+ * 1 <= iters <= 1000; out: host, or NULL.  Synchronises `stream`. */
+llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
+                        const float* pan, const float* kernel, float* scratch, int iters, llp_tune_result* out,
+                        hipStream_t stream);
+
+/* The tuned table: save it as JSON tagged with the device architecture (e.g. "gfx950"), merge a saved table
+ * into the context (LLP_E_UNSUPPORTED if it was made for another architecture, LLP_E_ARG if unreadable),
+ * clear it, count its entries. */
+llp_status llp_tune_save(llp_ctx* ctx, const char* path);
+llp_status llp_tune_load(llp_ctx* ctx, const char* path);
+llp_status llp_tune_clear(llp_ctx* ctx);
+int llp_tune_count(llp_ctx* ctx);
 
 /* ---- Operator entry points (the steps of the solve, exposed for parity checks) ------------------------ */
 

@@ -41,6 +41,12 @@ class KernelTimes(ctypes.Structure):
                 ("dir_ms", ctypes.c_double), ("dir_launches", ctypes.c_longlong)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("fast", ctypes.c_int), ("dir_rows", ctypes.c_int), ("apply_variant", ctypes.c_int),
+                ("us_per_iter", ctypes.c_double), ("default_us_per_iter", ctypes.c_double),
+                ("candidates", ctypes.c_int)]
+
+
 class LlpError(RuntimeError):
     def __init__(self, status: int, where: str):
         super().__init__(f"{where}: {status_str(status)} ({status})")
@@ -63,6 +69,12 @@ _SIGS = {
     "llp_get_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
     "llp_objective": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
                                      ctypes.POINTER(ctypes.c_double), _vp]),
+    "llp_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
+                                    ctypes.c_int, _vp, _vp]),
+    "llp_tune_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "llp_tune_load": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "llp_tune_clear": (ctypes.c_int, [_vp]),
+    "llp_tune_count": (ctypes.c_int, [_vp]),
     "llp_pansharpen_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(Shape), ctypes.POINTER(Params),
                                             ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                             ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(Report),
@@ -71,6 +83,7 @@ _SIGS = {
 
 BATCH_NO_GRAPH = 1
 BATCH_SERIAL = 2
+BATCH_AUTOTUNE = 4
 
 
 def lib() -> ctypes.CDLL:
@@ -197,6 +210,29 @@ class Context:
                 out_reps.append([reps[k + c].as_dict() for c in range(shapes[i].N)])
                 k += shapes[i].N
         return outs, out_reps, st
+
+    def autotune(self, lrms, pan, kernel, *, r: int, lam: float, eps: float, iters: int = 8, scratch=None,
+                 stream=None) -> dict:
+        """Time every launch configuration on this scene (llp_autotune) and keep the fastest for its class."""
+        shp = shape_of(lrms, pan, kernel)
+        prm = Params(int(r), float(lam), float(eps), int(iters), 0.0, 0)
+        res = TuneResult()
+        _check(lib().llp_autotune(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(lrms), _ptr(pan),
+                                  _ptr(kernel), _ptr(scratch), int(iters), ctypes.byref(res), _stream(stream)),
+               "llp_autotune")
+        return {k: getattr(res, k) for k, _ in res._fields_}
+
+    def tune_save(self, path: str):
+        _check(lib().llp_tune_save(self._h, os.fsencode(path)), "llp_tune_save")
+
+    def tune_load(self, path: str):
+        _check(lib().llp_tune_load(self._h, os.fsencode(path)), "llp_tune_load")
+
+    def tune_clear(self):
+        _check(lib().llp_tune_clear(self._h), "llp_tune_clear")
+
+    def tune_count(self) -> int:
+        return lib().llp_tune_count(self._h)
 
     def pan_stats(self, pan, *, N: int, c: int, n: int, r: int, eps: float, stream=None):
         import torch

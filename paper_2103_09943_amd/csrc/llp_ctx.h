@@ -1,0 +1,95 @@
+// Host-side state of a libllp context and the helpers shared by the C-ABI sources (llp_api.hip: single-scene
+// entry points; llp_batch.hip: the batched solve; llp_tune.hip: the autotuner).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "llp.h"
+#include "llp_internal.h"
+
+namespace llp {
+namespace host {
+
+constexpr int kCheckEvery = 8;  // CG iterations between convergence polls in tolerance mode (even)
+constexpr int kMaxLdsFloats = 160 * 1024 / 4;
+
+#define HIP_TRY(expr)                       \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return LLP_E_HIP; \
+  } while (0)
+
+// Tuned launch configuration of one geometry class: (c, R, r) and the image area in half-octaves.
+struct TuneEntry {
+  int c, R, r, bucket;
+  OpConfig cfg;
+  double us_per_iter;  // measured time of one CG iteration (operator + update kernels) of the whole scene
+};
+int area_bucket(const Geom& g);
+
+size_t align_up(size_t v, size_t a);
+bool aligned16(const void* p);  // image buffers are read and written with 16-byte vector accesses
+llp_status validate(const llp_shape* s, const llp_params* p, Geom* g);
+// Default launch configuration: the first shapes (in preference order) whose LDS fits.
+bool pick_config(const Geom& g, OpConfig* cfg, bool allow_fast = true, int want_dir_rows = 0,
+                 int want_apply_variant = -1);
+// The configuration a context uses for g: environment overrides, else a tuned entry, else the default.
+bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg);
+llp_status ensure_workspace(llp_ctx* ctx, const Geom& g);
+hipEvent_t timing_event(llp_ctx* ctx);
+llp_status collect_times(llp_ctx* ctx);
+llp_status check_inputs(llp_ctx* ctx, const Geom& g, const float* lrms, const float* pan, const float* kernel,
+                        hipStream_t s);
+llp_status apply_A_into(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const float* z, const float* kernel,
+                        float* q, hipStream_t s);
+// The whole single-scene solve with launch configuration cfg (the body of llp_pansharpen).
+llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const llp_params* params,
+                       const float* lrms, const float* pan, const float* kernel, const float* init, float* hrms,
+                       llp_report* rep, hipStream_t s);
+
+}  // namespace host
+}  // namespace llp
+
+struct llp_ctx {
+  int device = 0;
+  bool allow_fast = true;  // false when LLP_FORCE_GENERIC is set at creation: generic kernels only
+  int want_dir_rows = 0;   // launch-shape overrides (0: default), from LLP_DIR_ROWS / LLP_APPLY_VARIANT
+  int want_apply_variant = -1;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // views into ws
+  float *G = nullptr, *MU = nullptr, *DI = nullptr, *b = nullptr, *q = nullptr, *y = nullptr;
+  float* r[2] = {nullptr, nullptr};  // residual, alternating between iterations
+  float* p[2] = {nullptr, nullptr};  // direction, alternating between iterations
+  double* partials = nullptr;
+  llp::ChanState* st = nullptr;
+  double* results = nullptr;
+  int* flags = nullptr;
+  // pinned host mirrors
+  llp::ChanState* h_st = nullptr;
+  double* h_results = nullptr;
+  int* h_flags = nullptr;
+  int h_cap = 0;  // bands the mirrors hold
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // kernel timing (llp_set_profiling)
+  bool profiling = false;
+  std::vector<hipEvent_t> tev;  // timing events, 4 per iteration (around k_apply and around k_dir)
+  size_t tev_used = 0;
+  llp_kernel_times times = {0.0, 0, 0.0, 0};
+  // llp_pansharpen_batch: own stream, workspace, pinned mirrors and the cached graph of an iteration chunk
+  hipStream_t bstream = nullptr;
+  hipEvent_t bev_in = nullptr;
+  void* bws = nullptr;
+  size_t bws_bytes = 0;
+  llp::ChanState* h_bst[2] = {nullptr, nullptr};
+  double* h_bres = nullptr;
+  int* h_bflags = nullptr;
+  llp::SceneDesc* h_table = nullptr;
+  int hb_bands = 0, hb_scenes = 0;  // capacities of the batch mirrors
+  hipGraphExec_t gexec = nullptr;
+  std::vector<long long> gkey;  // what the cached graph was captured for
+  // launch configurations chosen by the autotuner (llp_autotune), by geometry class
+  std::vector<llp::host::TuneEntry> tuned;
+};

@@ -1,0 +1,246 @@
+// Autotuner of the launch configuration of the two CG iteration kernels (tile shapes of k_apply, rows per tile
+// of k_dir, specialised or generic kernels), per geometry class: (c, R, r) and the image area in half-octaves.
+// Every candidate runs a few CG iterations of the caller's scene under HIP-event timing; the fastest is kept in
+// the context and used by later solves of that class.  The table can be saved to and loaded from a small JSON
+// file tagged with the device architecture.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "llp_ctx.h"
+
+using namespace llp;
+using namespace llp::host;
+
+namespace llp {
+namespace host {
+
+int area_bucket(const Geom& g) { return (int)floor(2.0 * log2((double)g.H * (double)g.W)); }
+
+}  // namespace host
+}  // namespace llp
+
+namespace {
+
+constexpr int kRuns = 3;            // timed runs per candidate
+constexpr double kMargin = 0.97;    // a candidate replaces the default only if at least 3% faster
+
+// Every launch configuration that fits this build's kernels and the LDS: the specialised kernels' shapes when
+// (c, R, r) has them, otherwise the generic kernels' shapes.
+std::vector<OpConfig> candidates(const Geom& g, bool allow_fast) {
+  std::vector<OpConfig> out;
+  if (allow_fast && fast_path_available(g.c, g.R, g.r)) {
+    for (int v : {1, 0})
+      for (int rows : {4, 8}) {
+        const int f = fast_apply_lds_floats(g.c, g.R, g.r, v);
+        if (f > 0 && f <= kMaxLdsFloats && fast_path_fits(g, rows, v)) out.push_back(OpConfig{1, rows, v});
+      }
+    if (!out.empty()) return out;
+  }
+  for (int rows : {8, 4}) {
+    if (dir_lds_floats(g.c, rows, g.R, nullptr) > kMaxLdsFloats) continue;
+    for (int v = 0; v < kApplyVariants; ++v) {
+      int TH = 0, TW = 0;
+      if (apply_tile(g.c, v, &TH, &TW) != 0) continue;
+      if (apply_lds_floats(g.c, TH, TW, g.R, g.r, nullptr, nullptr, nullptr, nullptr) > kMaxLdsFloats) continue;
+      out.push_back(OpConfig{0, rows, v});
+    }
+  }
+  return out;
+}
+
+bool same(const OpConfig& a, const OpConfig& b) {
+  return a.fast == b.fast && a.dir_rows == b.dir_rows && a.apply_variant == b.apply_variant;
+}
+
+// Microseconds per CG iteration of the scene with configuration cfg (the fastest of kRuns timed runs after
+// one untimed run).
+llp_status time_config(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const llp_params* params,
+                       const float* lrms, const float* pan, const float* kernel, float* scratch, int iters,
+                       hipStream_t s, double* us) {
+  llp_params p = *params;
+  p.max_iters = iters;
+  p.tol = 0.0f;
+  p.init_mode = 0;
+  double best = 0.0;
+  for (int run = 0; run <= kRuns; ++run) {
+    ctx->times = llp_kernel_times{0.0, 0, 0.0, 0};
+    const llp_status st = solve_scene(ctx, g, cfg, &p, lrms, pan, kernel, nullptr, scratch, nullptr, s);
+    if (st < 0 && st != LLP_E_BREAKDOWN && st != LLP_E_NONFINITE) return st;
+    const long long n = ctx->times.apply_launches;
+    const double us = n > 0 ? (ctx->times.apply_ms + ctx->times.dir_ms) * 1e3 / (double)n : 0.0;
+    if (run > 0 && (best == 0.0 || us < best)) best = us;
+  }
+  *us = best;
+  return LLP_OK;
+}
+
+std::string device_arch(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+// Value of "key": <number> inside [b, e) of a JSON text, or false.
+bool json_number(const std::string& t, size_t b, size_t e, const char* key, double* out) {
+  const std::string k = std::string("\"") + key + "\"";
+  const size_t at = t.find(k, b);
+  if (at == std::string::npos || at >= e) return false;
+  size_t c = t.find(':', at + k.size());
+  if (c == std::string::npos || c >= e) return false;
+  const char* s = t.c_str() + c + 1;
+  char* end = nullptr;
+  const double v = strtod(s, &end);
+  if (end == s) return false;
+  *out = v;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
+                        const float* pan, const float* kernel, float* scratch, int iters, llp_tune_result* out,
+                        hipStream_t stream) {
+  if (!ctx || !params || !lrms || !pan || !kernel || iters < 1 || iters > 1000) return LLP_E_ARG;
+  if (scratch && !aligned16(scratch)) return LLP_E_ARG;
+  Geom g;
+  llp_status v = validate(shape, params, &g);
+  if (v != LLP_OK) return v;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const std::vector<OpConfig> cands = candidates(g, ctx->allow_fast);
+  if (cands.empty()) return LLP_E_UNSUPPORTED;
+  OpConfig def;
+  if (!pick_config(g, &def, ctx->allow_fast)) return LLP_E_UNSUPPORTED;
+  float* own = nullptr;
+  if (!scratch) {
+    if (hipMalloc((void**)&own, sizeof(float) * (size_t)g.N * g.H * g.W) != hipSuccess) return LLP_E_OOM;
+    scratch = own;
+  }
+  // Timing uses the context's event machinery; its accumulated kernel times are kept aside meanwhile.
+  const bool prof = ctx->profiling;
+  const llp_kernel_times saved = ctx->times;
+  ctx->profiling = true;
+  double best_us = 0.0, def_us = 0.0;
+  OpConfig best = cands[0];
+  for (const OpConfig& c : cands) {
+    double us = 0.0;
+    v = time_config(ctx, g, c, params, lrms, pan, kernel, scratch, iters, stream, &us);
+    if (v != LLP_OK) break;
+    if (same(c, def)) def_us = us;
+    if (best_us == 0.0 || us < best_us) {
+      best_us = us;
+      best = c;
+    }
+  }
+  if (v == LLP_OK && def_us > 0.0 && !(best_us < kMargin * def_us)) {  // measured gain within noise: default
+    best = def;
+    best_us = def_us;
+  }
+  ctx->profiling = prof;
+  ctx->times = saved;
+  if (own) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(own);
+  }
+  if (v != LLP_OK) return v;
+  TuneEntry e{g.c, g.R, g.r, area_bucket(g), best, best_us};
+  bool replaced = false;
+  for (TuneEntry& t : ctx->tuned)
+    if (t.c == e.c && t.R == e.R && t.r == e.r && t.bucket == e.bucket) {
+      t = e;
+      replaced = true;
+    }
+  if (!replaced) ctx->tuned.push_back(e);
+  if (out) {
+    out->fast = best.fast;
+    out->dir_rows = best.dir_rows;
+    out->apply_variant = best.apply_variant;
+    out->us_per_iter = best_us;
+    out->default_us_per_iter = def_us;
+    out->candidates = (int)cands.size();
+  }
+  return LLP_OK;
+}
+
+llp_status llp_tune_clear(llp_ctx* ctx) {
+  if (!ctx) return LLP_E_ARG;
+  ctx->tuned.clear();
+  return LLP_OK;
+}
+
+int llp_tune_count(llp_ctx* ctx) { return ctx ? (int)ctx->tuned.size() : 0; }
+
+llp_status llp_tune_save(llp_ctx* ctx, const char* path) {
+  if (!ctx || !path) return LLP_E_ARG;
+  FILE* f = fopen(path, "w");
+  if (!f) return LLP_E_ARG;
+  fprintf(f, "{\n  \"arch\": \"%s\",\n  \"entries\": [", device_arch(ctx->device).c_str());
+  for (size_t i = 0; i < ctx->tuned.size(); ++i) {
+    const TuneEntry& t = ctx->tuned[i];
+    fprintf(f,
+            "%s\n    {\"c\": %d, \"R\": %d, \"r\": %d, \"bucket\": %d, \"fast\": %d, \"dir_rows\": %d, "
+            "\"apply_variant\": %d, \"us_per_iter\": %.2f}",
+            i ? "," : "", t.c, t.R, t.r, t.bucket, t.cfg.fast, t.cfg.dir_rows, t.cfg.apply_variant, t.us_per_iter);
+  }
+  fprintf(f, "\n  ]\n}\n");
+  return fclose(f) == 0 ? LLP_OK : LLP_E_ARG;
+}
+
+llp_status llp_tune_load(llp_ctx* ctx, const char* path) {
+  if (!ctx || !path) return LLP_E_ARG;
+  FILE* f = fopen(path, "r");
+  if (!f) return LLP_E_ARG;
+  std::string t;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof(buf), f)) > 0) t.append(buf, n);
+  fclose(f);
+  // "arch": "<name>" must name this device's architecture.
+  const size_t a = t.find("\"arch\"");
+  if (a == std::string::npos) return LLP_E_ARG;
+  const size_t q0 = t.find('"', t.find(':', a) + 1);
+  const size_t q1 = q0 == std::string::npos ? q0 : t.find('"', q0 + 1);
+  if (q1 == std::string::npos) return LLP_E_ARG;
+  if (t.substr(q0 + 1, q1 - q0 - 1) != device_arch(ctx->device)) return LLP_E_UNSUPPORTED;
+  std::vector<TuneEntry> entries;
+  size_t pos = t.find("\"entries\"");
+  if (pos == std::string::npos) return LLP_E_ARG;
+  while (true) {
+    const size_t b = t.find('{', pos);
+    if (b == std::string::npos) break;
+    const size_t e = t.find('}', b);
+    if (e == std::string::npos) return LLP_E_ARG;
+    double c, R, r, bucket, fast, rows, var, us = 0.0;
+    if (!json_number(t, b, e, "c", &c) || !json_number(t, b, e, "R", &R) || !json_number(t, b, e, "r", &r) ||
+        !json_number(t, b, e, "bucket", &bucket) || !json_number(t, b, e, "fast", &fast) ||
+        !json_number(t, b, e, "dir_rows", &rows) || !json_number(t, b, e, "apply_variant", &var))
+      return LLP_E_ARG;
+    json_number(t, b, e, "us_per_iter", &us);
+    const OpConfig cfg{(int)fast, (int)rows, (int)var};
+    if ((cfg.fast != 0 && cfg.fast != 1) || (cfg.dir_rows != 4 && cfg.dir_rows != 8) || cfg.apply_variant < 0 ||
+        cfg.apply_variant >= kApplyVariants)
+      return LLP_E_ARG;
+    entries.push_back(TuneEntry{(int)c, (int)R, (int)r, (int)bucket, cfg, us});
+    pos = e + 1;
+  }
+  for (const TuneEntry& e : entries) {
+    bool replaced = false;
+    for (TuneEntry& t2 : ctx->tuned)
+      if (t2.c == e.c && t2.R == e.R && t2.r == e.r && t2.bucket == e.bucket) {
+        t2 = e;
+        replaced = true;
+      }
+    if (!replaced) ctx->tuned.push_back(e);
+  }
+  return LLP_OK;
+}
+
+}  // extern "C"

@@ -52,6 +52,12 @@ def test_null_context_is_rejected(lib):
     assert lib.llp_create(None, 0) == B.E_ARG
     assert lib.llp_pansharpen_batch(None, 1, ctypes.byref(shp), ctypes.byref(prm), None, None, None, None, None,
                                     None, 0, None) == B.E_ARG
+    assert lib.llp_autotune(None, ctypes.byref(shp), ctypes.byref(prm), None, None, None, None, 8, None,
+                            None) == B.E_ARG
+    assert lib.llp_tune_save(None, b"/tmp/x.json") == B.E_ARG
+    assert lib.llp_tune_load(None, b"/tmp/x.json") == B.E_ARG
+    assert lib.llp_tune_clear(None) == B.E_ARG
+    assert lib.llp_tune_count(None) == 0
 
 
 GOOD = dict(N=4, h=64, w=64, c=4, n=9)
