@@ -204,3 +204,16 @@ def random_problem(rng: np.random.Generator, N: int, H: int, W: int, c: int, n: 
     u = (u / u.sum()).astype(np.float32)
     P = rng.standard_normal((N, H, W)).astype(np.float32)
     return X, Y, u, P
+
+
+def cnn_init_params(rng: np.random.Generator, layers=(2, 32, 32, 32, 32, 1), last_std: float = 1e-3):
+    """Random initial weights of the warm-start network, flat float32 in the library's layout (per layer its
+    W [out][in][3][3] then its b [out]): He-normal weights for the ReLU layers, a small normal last layer
+    (the untrained network starts close to the plain upsampled band), zero biases."""
+    out = []
+    for k in range(len(layers) - 1):
+        cin, cout = layers[k], layers[k + 1]
+        std = last_std if k == len(layers) - 2 else math.sqrt(2.0 / (9 * cin))
+        out.append(rng.normal(0.0, std, size=cout * cin * 9))
+        out.append(np.zeros(cout))
+    return np.concatenate(out).astype(np.float32)
