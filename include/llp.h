@@ -70,7 +70,9 @@ typedef struct {
   int max_iters; /* CG iteration cap, >= 0 */
   float tol;     /* > 0: stop a band when ||r_k|| <= tol * ||b|| (r_k the CG residual, b = B^T D^T X_i);
                     <= 0: run exactly max_iters iterations */
-  int init_mode; /* 0: start from Z = 0; 1: start from the caller's `init` */
+  int init_mode; /* 0: start from Z = 0; 1: start from the caller's `init`; 2: start from the warm-start
+                    network's estimate (llp_cnn_set_weights first), band by band only where it is closer
+                    than Z = 0 (||b - A Z0|| < ||b||), else from Z = 0 */
 } llp_params;
 
 typedef struct {
@@ -79,6 +81,8 @@ typedef struct {
   double rel_residual;      /* ||r_k|| / ||b|| of the CG recursion at exit */
   double true_rel_residual; /* ||b - A Z|| / ||b|| recomputed from the returned Z */
   double objective;         /* eq. (initialize_z_fast) at the returned Z */
+  int init;                 /* how the band started: 0 Z = 0, 1 the caller's init, 2 the network's estimate,
+                               3 the network's estimate was rejected (no better than Z = 0) and Z = 0 used */
 } llp_report;
 
 typedef struct llp_ctx llp_ctx;
@@ -169,6 +173,37 @@ llp_status llp_tune_save(llp_ctx* ctx, const char* path);
 llp_status llp_tune_load(llp_ctx* ctx, const char* path);
 llp_status llp_tune_clear(llp_ctx* ctx);
 int llp_tune_count(llp_ctx* ctx);
+
+/* ---- Warm-start network -------------------------------------------------------------------------------- */
+/* Not in the paper, which leaves the initial guess of the CG solve open (Sec. III-B).  For band i:
+ *     z0 = x_up + s * net([(x_up - m)/s, (Y - m_Y)/s_Y])
+ * x_up the periodic bicubic upsampling of X_i (Keys, a = -1/2; HR pixel c*m on LR pixel m), m and s the mean
+ * and population std of X_i (s = 1 if 0), m_Y and s_Y those of Y; net: five 3x3 convolutions
+ * (2 -> 32 -> 32 -> 32 -> 32 -> 1 channels, cross-correlation, periodic padding), ReLU after the first four.
+ * Layer inputs and weights are rounded to bfloat16, products accumulate in FP32 (matrix cores); biases FP32.
+ * Parameters: LLP_CNN_PARAMS floats, per layer W [cout][cin][3][3] then b [cout]. */
+#define LLP_CNN_PARAMS 28641
+
+/* Load the network's parameters (host FP32 array of `count` == LLP_CNN_PARAMS) into the context; resets the
+ * optimiser state.  LLP_E_NONFINITE if any parameter is NaN or Inf.  Synchronises the device. */
+llp_status llp_cnn_set_weights(llp_ctx* ctx, const float* params, int count);
+/* Copy the current (possibly trained) parameters to a host array.  Synchronises the device. */
+llp_status llp_cnn_get_weights(llp_ctx* ctx, float* params, int count);
+/* The network's estimate for every band of a scene: z0 [N][H][W] device (may be NULL), and the raw network
+ * output [N][H][W] device (may be NULL; not both NULL).  Asynchronous on `stream`. */
+llp_status llp_cnn_warm_start(llp_ctx* ctx, const llp_shape* shape, const float* lrms, const float* pan,
+                              float* z0, float* net_out, hipStream_t stream);
+/* Training loss of one scene against the plain solver's HRMS `target` [N][H][W] (device): the mean over all
+ * pixels of all bands of (net - t)^2, t = (target - x_up)/s, into *loss (host, may be NULL), and its gradient
+ * with respect to every parameter into `grads` (host array of LLP_CNN_PARAMS, may be NULL).  In the backward
+ * pass each layer's output gradient is rounded to bfloat16 before its products.  Synchronises `stream`. */
+llp_status llp_cnn_loss_grad(llp_ctx* ctx, const llp_shape* shape, const float* lrms, const float* pan,
+                             const float* target, double* loss, float* grads, hipStream_t stream);
+/* One training step on one scene: the gradient above, then an Adam update (beta1 0.9, beta2 0.999, eps 1e-8,
+ * step size lr > 0) of the FP32 parameters.  *loss (host, may be NULL) receives the loss before the update;
+ * with loss == NULL the call is asynchronous on `stream`. */
+llp_status llp_cnn_train_step(llp_ctx* ctx, const llp_shape* shape, const float* lrms, const float* pan,
+                              const float* target, float lr, double* loss, hipStream_t stream);
 
 /* ---- Operator entry points (the steps of the solve, exposed for parity checks) ------------------------ */
 

@@ -30,7 +30,7 @@ class Params(ctypes.Structure):
 
 class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("true_rel_residual", ctypes.c_double), ("objective", ctypes.c_double)]
+                ("true_rel_residual", ctypes.c_double), ("objective", ctypes.c_double), ("init", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +75,13 @@ _SIGS = {
     "llp_tune_load": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "llp_tune_clear": (ctypes.c_int, [_vp]),
     "llp_tune_count": (ctypes.c_int, [_vp]),
+    "llp_cnn_set_weights": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]),
+    "llp_cnn_get_weights": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]),
+    "llp_cnn_warm_start": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), _vp, _vp, _vp, _vp, _vp]),
+    "llp_cnn_loss_grad": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_float), _vp]),
+    "llp_cnn_train_step": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), _vp, _vp, _vp, ctypes.c_float,
+                                          ctypes.POINTER(ctypes.c_double), _vp]),
     "llp_pansharpen_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(Shape), ctypes.POINTER(Params),
                                             ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                             ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(Report),
@@ -84,6 +91,8 @@ _SIGS = {
 BATCH_NO_GRAPH = 1
 BATCH_SERIAL = 2
 BATCH_AUTOTUNE = 4
+CNN_PARAMS = 28641
+INIT_ZERO, INIT_USER, INIT_NET, INIT_NET_REJECTED = 0, 1, 2, 3
 
 
 def lib() -> ctypes.CDLL:
@@ -171,7 +180,10 @@ class Context:
         H, W = pan.shape
         if out is None:
             out = torch.empty((shp.N, H, W), dtype=torch.float32, device=lrms.device)
-        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), 1 if init is not None else 0)
+        mode = 2 if isinstance(init, str) and init == "cnn" else (1 if init is not None else 0)
+        if mode == 2:
+            init = None
+        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), mode)
         reps = (Report * shp.N)() if report else None
         st = lib().llp_pansharpen(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(lrms), _ptr(pan), _ptr(kernel),
                                   _ptr(init), _ptr(out), reps, _stream(stream))
@@ -194,7 +206,10 @@ class Context:
             outs = [torch.empty((X.shape[0], Y.shape[0], Y.shape[1]), dtype=torch.float32, device=X.device)
                     for X, Y, u in scenes]
         arr = lambda ts: (_vp * max(S, 1))(*[_ptr(t) for t in ts])  # noqa: E731
-        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), 1 if inits is not None else 0)
+        mode = 2 if isinstance(inits, str) and inits == "cnn" else (1 if inits is not None else 0)
+        if mode == 2:
+            inits = None
+        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), mode)
         nb = sum(shapes[i].N for i in range(S))
         reps = (Report * max(nb, 1))() if report else None
         st = lib().llp_pansharpen_batch(self._h, S, shapes, ctypes.byref(prm), arr([s[0] for s in scenes]),
@@ -221,6 +236,56 @@ class Context:
                                   _ptr(kernel), _ptr(scratch), int(iters), ctypes.byref(res), _stream(stream)),
                "llp_autotune")
         return {k: getattr(res, k) for k, _ in res._fields_}
+
+    # ---- warm-start network
+    def cnn_set_weights(self, params):
+        """Load the network's parameters (CNN_PARAMS float32 values, per layer W then b)."""
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != CNN_PARAMS:
+            raise ValueError(f"expected {CNN_PARAMS} parameters, got {a.size}")
+        _check(lib().llp_cnn_set_weights(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+               "llp_cnn_set_weights")
+
+    def cnn_get_weights(self):
+        import numpy as np
+        a = np.empty(CNN_PARAMS, dtype=np.float32)
+        _check(lib().llp_cnn_get_weights(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+               "llp_cnn_get_weights")
+        return a
+
+    def cnn_warm_start(self, lrms, pan, c: int, *, z0=True, net_out=False, stream=None):
+        """The network's estimate z0 and/or its raw output, each [N][H][W] (None where not asked for)."""
+        import torch
+        N, h, w = lrms.shape
+        shp = Shape(N, h, w, c, 1)
+        H, W = pan.shape
+        z = torch.empty((N, H, W), dtype=torch.float32, device=lrms.device) if z0 else None
+        o = torch.empty((N, H, W), dtype=torch.float32, device=lrms.device) if net_out else None
+        _check(lib().llp_cnn_warm_start(self._h, ctypes.byref(shp), _ptr(lrms), _ptr(pan), _ptr(z), _ptr(o),
+                                        _stream(stream)), "llp_cnn_warm_start")
+        return z, o
+
+    def cnn_loss_grad(self, lrms, pan, target, c: int, stream=None):
+        """(loss, gradient as a CNN_PARAMS float32 array) of one scene against the target HRMS."""
+        import numpy as np
+        N, h, w = lrms.shape
+        shp = Shape(N, h, w, c, 1)
+        loss = ctypes.c_double()
+        g = np.empty(CNN_PARAMS, dtype=np.float32)
+        _check(lib().llp_cnn_loss_grad(self._h, ctypes.byref(shp), _ptr(lrms), _ptr(pan), _ptr(target),
+                                       ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                       _stream(stream)), "llp_cnn_loss_grad")
+        return loss.value, g
+
+    def cnn_train_step(self, lrms, pan, target, c: int, lr: float, want_loss: bool = True, stream=None):
+        N, h, w = lrms.shape
+        shp = Shape(N, h, w, c, 1)
+        loss = ctypes.c_double()
+        _check(lib().llp_cnn_train_step(self._h, ctypes.byref(shp), _ptr(lrms), _ptr(pan), _ptr(target), float(lr),
+                                        ctypes.byref(loss) if want_loss else None, _stream(stream)),
+               "llp_cnn_train_step")
+        return loss.value if want_loss else None
 
     def tune_save(self, path: str):
         _check(lib().llp_tune_save(self._h, os.fsencode(path)), "llp_tune_save")

@@ -49,7 +49,7 @@ llp_status validate(const llp_shape* s, const llp_params* p, Geom* g) {
     if (!isfinite(p->lambda) || p->lambda < 0.0f) return LLP_E_ARG;
     if (!isfinite(p->eps) || p->eps < 0.0f) return LLP_E_ARG;
     if (p->max_iters < 0 || !isfinite(p->tol)) return LLP_E_ARG;
-    if (p->init_mode != 0 && p->init_mode != 1) return LLP_E_ARG;
+    if (p->init_mode < 0 || p->init_mode > 2) return LLP_E_ARG;
     g->r = p->r;
     g->lam = p->lambda;
     g->eps = p->eps;
@@ -230,13 +230,22 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
   // Per scene: the statistics that define M_LY, then the right-hand sides and ||b||.
   HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, s));
   HIP_TRY(launch_rhs(g, lrms, kernel, ctx->b, ctx->partials, ctx->st, s));
-  const int from_init = params->init_mode == 1;
+  const int from_init = params->init_mode != 0;
+  if (params->init_mode == 1 && init != hrms)
+    HIP_TRY(hipMemcpyAsync(hrms, init, NHW * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (params->init_mode == 2) {  // the network's estimate, kept only for bands it brings closer than Z = 0
+    v = cnn_warm_start(ctx, g, lrms, pan, hrms, nullptr, s);
+    if (v != LLP_OK) return v;
+  }
   if (from_init) {
-    if (init != hrms) HIP_TRY(hipMemcpyAsync(hrms, init, NHW * sizeof(float), hipMemcpyDeviceToDevice, s));
     v = apply_A_into(ctx, g, cfg, hrms, kernel, ctx->q, s);
     if (v != LLP_OK) return v;
   }
   HIP_TRY(launch_init(g, from_init, ctx->b, ctx->q, ctx->r[0], hrms, ctx->st, s));
+  if (params->init_mode == 2) {
+    HIP_TRY(launch_residual_norm(g, ctx->b, ctx->q, ctx->partials, ctx->st, ctx->results, s));
+    HIP_TRY(launch_fallback(g, ctx->results, ctx->st, ctx->b, ctx->r[0], hrms, s));
+  }
 
   // CG.  k_dir(k) produces x_k, r_k, p_k and y = D B p_k; k_apply(k) produces q_k = A p_k, alpha_k, beta_k.
   // Residual and direction alternate between two buffers so that no tile reads a neighbour's new values.
@@ -309,6 +318,7 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
     if (rep) {
       llp_report& R = rep[i];
       R.iters = cs.iters;
+      R.init = cs.init;
       R.status = st;
       const double bn2 = cs.bnorm2;
       R.rel_residual = bn2 > 0 ? sqrt(cs.rho / bn2) : sqrt(cs.rho);
@@ -393,6 +403,7 @@ void llp_destroy(llp_ctx* ctx) {
   if (ctx->h_table) (void)hipHostFree(ctx->h_table);
   if (ctx->bev_in) (void)hipEventDestroy(ctx->bev_in);
   if (ctx->bstream) (void)hipStreamDestroy(ctx->bstream);
+  cnn_free(ctx->cnn);
   delete ctx;
 }
 
@@ -462,6 +473,7 @@ llp_status llp_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params
                           hipStream_t stream) {
   if (!ctx || !params || !lrms || !pan || !kernel || !hrms) return LLP_E_ARG;
   if (params->init_mode == 1 && !init) return LLP_E_ARG;
+  if (params->init_mode == 2 && !ctx->cnn) return LLP_E_ARG;
   if (!aligned16(hrms) || (params->init_mode == 1 && !aligned16(init))) return LLP_E_ARG;
   Geom g;
   llp_status v = validate(shape, params, &g);

@@ -106,8 +106,9 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
   if (!ctx || !params || S < 0 || (flags & ~(LLP_BATCH_NO_GRAPH | LLP_BATCH_SERIAL | LLP_BATCH_AUTOTUNE)) != 0) return LLP_E_ARG;
   if (S == 0) return LLP_OK;
   if (!shapes || !lrms || !pan || !kernel || !hrms) return LLP_E_ARG;
-  const bool from_init = params->init_mode == 1;
-  if (from_init && !init) return LLP_E_ARG;
+  const bool from_init = params->init_mode == 1;  // caller's starts
+  const bool net_init = params->init_mode == 2;   // network starts
+  if ((from_init && !init) || (net_init && !ctx->cnn)) return LLP_E_ARG;
   // Host-side planning: validate every scene, tune the classes not yet tuned (if asked), pick every scene's
   // kernels, group the specialised ones into classes.
   std::vector<Geom> geoms(S);
@@ -279,11 +280,22 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         const float* z0 = init[fast[i].idx];
         if (z0 != d.x)
           HIP_TRY(hipMemcpyAsync(d.x, z0, (size_t)g.N * g.H * g.W * sizeof(float), hipMemcpyDeviceToDevice, s));
+      }
+      if (net_init) {
+        v = cnn_warm_start(ctx, g, d.X, d.Y, d.x, nullptr, s);
+        if (v != LLP_OK) return v;
+      }
+      if (from_init || net_init) {
         HIP_TRY(launch_dir(g, cfg, 0, 0, 0, d.x, nullptr, nullptr, nullptr, nullptr, nullptr, d.y, d.u, d.partials,
                            sst, 0, 0.0f, s));
         HIP_TRY(launch_apply(g, cfg, 0, d.x, nullptr, d.y, d.u, d.G, d.MU, d.DI, d.q, d.partials, sst, s));
       }
-      HIP_TRY(launch_init(g, from_init, d.b, d.q, d.r[0], d.x, sst, s));
+      HIP_TRY(launch_init(g, from_init || net_init, d.b, d.q, d.r[0], d.x, sst, s));
+      if (net_init) {
+        double* sres = results + (size_t)d.band0 * kResultSlots;
+        HIP_TRY(launch_residual_norm(g, d.b, d.q, d.partials, sst, sres, s));
+        HIP_TRY(launch_fallback(g, sres, sst, d.b, d.r[0], d.x, s));
+      }
       HIP_TRY(launch_dir(g, cfg, 1, 0, 0, d.r[0], nullptr, nullptr, nullptr, d.p[0], d.x, d.y, d.u, d.partials,
                          sst, max_iters, tol, s));
       HIP_TRY(launch_finalize(g, kFinDir, d.partials, d.dir_ntiles, sst, nullptr, 0, 0, max_iters, tol, s));
@@ -390,6 +402,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
           llp_report& R = rep[fast[i].rep0 + c];
           const double* res = ctx->h_bres + (size_t)(d.band0 + c) * kResultSlots;
           R.iters = cs.iters;
+          R.init = cs.init;
           R.status = bst;
           const double bn2 = cs.bnorm2;
           R.rel_residual = bn2 > 0 ? sqrt(cs.rho / bn2) : sqrt(cs.rho);

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "llp.h"
+#include "llp_cnn.h"
 #include "llp_internal.h"
 
 namespace llp {
@@ -44,6 +45,22 @@ llp_status check_inputs(llp_ctx* ctx, const Geom& g, const float* lrms, const fl
                         hipStream_t s);
 llp_status apply_A_into(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const float* z, const float* kernel,
                         float* q, hipStream_t s);
+// Warm-start network state of a context (llp_cnn_set_weights).
+struct CnnState {
+  void* mem = nullptr;  // one allocation: master weights, Adam moments, gradient, MFMA weight operands
+  float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+  void* fwd[kCnnLayers] = {};  // forward operands of each layer
+  void* bwd[kCnnLayers] = {};  // transposed, flipped operands (input gradients)
+  int steps = 0;               // Adam steps taken
+  void* ws = nullptr;          // activations and scratch, grown on demand
+  size_t ws_bytes = 0;
+  double* h_loss = nullptr;    // pinned
+};
+void cnn_free(CnnState* c);
+// z0 (and the raw network output, if netout) for every band of a scene; the context must hold weights.
+llp_status cnn_warm_start(llp_ctx* ctx, const Geom& g, const float* X, const float* Y, float* z0, float* netout,
+                          hipStream_t s);
+
 // The whole single-scene solve with launch configuration cfg (the body of llp_pansharpen).
 llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const llp_params* params,
                        const float* lrms, const float* pan, const float* kernel, const float* init, float* hrms,
@@ -92,4 +109,5 @@ struct llp_ctx {
   std::vector<long long> gkey;  // what the cached graph was captured for
   // launch configurations chosen by the autotuner (llp_autotune), by geometry class
   std::vector<llp::host::TuneEntry> tuned;
+  llp::host::CnnState* cnn = nullptr;  // warm-start network (llp_cnn_set_weights)
 };

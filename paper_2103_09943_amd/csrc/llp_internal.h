@@ -22,8 +22,10 @@ struct ChanState {
   int iters;      // index of the current iterate x_k
   int active;     // 1 while the band still iterates
   int status;     // llp_status of the band
-  int pad;
+  int init;       // how the band started: kInitZero, kInitUser, kInitNet, kInitNetRejected
 };
+
+enum InitKind { kInitZero = 0, kInitUser = 1, kInitNet = 2, kInitNetRejected = 3 };
 
 // What k_finalize does with a band's summed partials.
 enum FinOp { kFinBnorm = 0, kFinResult = 1, kFinDir = 2, kFinApply = 3 };
@@ -74,6 +76,9 @@ hipError_t launch_apply(const Geom& g, const OpConfig& cfg, int mode, const floa
                         double* partials, ChanState* st, hipStream_t s);
 int dir_ntiles(const Geom& g, const OpConfig& cfg);
 int apply_ntiles(const Geom& g, const OpConfig& cfg);
+// After a network start: bands whose start is no better than zero restart from zero (see k_fallback).
+hipError_t launch_fallback(const Geom& g, const double* results, ChanState* st, const float* b, float* r, float* x,
+                           hipStream_t s);
 hipError_t launch_residual_norm(const Geom& g, const float* b, const float* q, double* partials, ChanState* st,
                                 double* results, hipStream_t s);
 hipError_t launch_objective(const Geom& g, const float* z, const float* X, const float* u, const float* G,

@@ -242,6 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Geom g, int from_init, const fl
     s.iters = 0;
     s.active = 1;
     s.status = 0;
+    s.init = from_init ? kInitUser : kInitZero;
   }
 }
 
@@ -250,6 +251,34 @@ hipError_t launch_init(const Geom& g, int from_init, const float* b, const float
   const size_t HW = (size_t)g.H * g.W;
   const int nblk = (int)((HW + kChunk - 1) / kChunk);
   hipLaunchKernelGGL(k_init, dim3(nblk, g.N), dim3(kBlock), 0, s, g, from_init, b, q, r, x, st);
+  return hipGetLastError();
+}
+
+// Check of a network start z0 (x = z0, r = b - A z0, results[kSlotTrueRes] = ||r||^2): a band whose start is no
+// better than Z = 0 (||r||^2 >= ||b||^2) restarts from Z = 0.  Records the band's start in its state.
+__global__ __launch_bounds__(kBlock) void k_fallback(Geom g, const double* __restrict__ results,
+                                                     ChanState* __restrict__ st, const float* __restrict__ b,
+                                                     float* __restrict__ r, float* __restrict__ x) {
+  const int ch = blockIdx.y;
+  const bool reject = !(results[ch * kResultSlots + kSlotTrueRes] < st[ch].bnorm2);
+  const size_t HW = (size_t)g.H * g.W;
+  const size_t base = (size_t)ch * HW;
+  const size_t e0 = (size_t)blockIdx.x * kChunk;
+  const size_t e1 = e0 + kChunk < HW ? e0 + kChunk : HW;
+  if (reject) {
+    for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+      x[base + e] = 0.0f;
+      r[base + e] = b[base + e];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st[ch].init = reject ? kInitNetRejected : kInitNet;
+}
+
+hipError_t launch_fallback(const Geom& g, const double* results, ChanState* st, const float* b, float* r, float* x,
+                           hipStream_t s) {
+  const size_t HW = (size_t)g.H * g.W;
+  const int nblk = (int)((HW + kChunk - 1) / kChunk);
+  hipLaunchKernelGGL(k_fallback, dim3(nblk, g.N), dim3(kBlock), 0, s, g, results, st, b, r, x);
   return hipGetLastError();
 }
 

@@ -58,6 +58,11 @@ def test_null_context_is_rejected(lib):
     assert lib.llp_tune_load(None, b"/tmp/x.json") == B.E_ARG
     assert lib.llp_tune_clear(None) == B.E_ARG
     assert lib.llp_tune_count(None) == 0
+    assert lib.llp_cnn_set_weights(None, None, B.CNN_PARAMS) == B.E_ARG
+    assert lib.llp_cnn_get_weights(None, None, B.CNN_PARAMS) == B.E_ARG
+    assert lib.llp_cnn_warm_start(None, ctypes.byref(shp), None, None, None, None, None) == B.E_ARG
+    assert lib.llp_cnn_loss_grad(None, ctypes.byref(shp), None, None, None, None, None, None) == B.E_ARG
+    assert lib.llp_cnn_train_step(None, ctypes.byref(shp), None, None, None, 1e-3, None, None) == B.E_ARG
 
 
 GOOD = dict(N=4, h=64, w=64, c=4, n=9)
@@ -79,7 +84,7 @@ GOODP = dict(r=1, lam=1e-2, eps=1e-3, max_iters=50, tol=0.0, init_mode=0)
     ({}, {"lam": float("nan")}, B.E_ARG),
     ({}, {"max_iters": -1}, B.E_ARG),
     ({}, {"tol": float("inf")}, B.E_ARG),
-    ({}, {"init_mode": 2}, B.E_ARG),
+    ({}, {"init_mode": 3}, B.E_ARG),
     ({"N": 1, "h": 3, "w": 5, "c": 1, "n": 3}, {"r": 1}, B.OK),  # ragged, c = 1
     ({"N": 16, "h": 1024, "w": 1024, "c": 4, "n": 17}, {"r": 2}, B.OK),  # the largest measured scene
     ({"N": 200, "h": 1024, "w": 1024, "c": 4, "n": 17}, {"r": 2}, B.E_UNSUPPORTED),  # > 2^31 pixels
