@@ -7,7 +7,9 @@ the objective of the result.  The workload is the 8-band scene with a 2048 x 204
 (x4), a 17 x 17 anisotropic Gaussian blur, window radius 2, lambda 1e-2, eps 1e-3.
 With --workload batch, one step is one batched call (llp_pansharpen_batch) on 64 scenes of uneven sizes (PAN
 side from {256, 384, ..., 1024}, 4 or 8 bands, 9..17-tap Gaussian blurs, r 1, tol 1e-6); the line also
-carries the same scenes solved one after another (`serial_value`).
+carries the same scenes solved one after another (`serial_value`).  With --workload warmstart (500 held-out
+8-band 512^2 scenes) or large (4 scenes of 16 bands at 4096^2, r 2), the batched solve starts from the trained
+network's estimate and the line carries the same solve from Z = 0 (`plain_cold_value`).
 
 Prints one JSON line.  `value` is HRMS Mpixel*bands per second (N*H*W / time per step).  `roofline` is the
 dominant kernel's algorithmic HBM bytes over its measured launch time (HIP events on the solver's stream around
@@ -56,8 +58,8 @@ def parse():
     ap.add_argument("--side", type=int, default=None, help="PAN side override (same recipe, smaller scene)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["scene", "batch"], default="scene")
-    ap.add_argument("--scenes", type=int, default=64, help="batch workload: number of scenes")
+    ap.add_argument("--workload", choices=["scene", "batch", "warmstart", "large"], default="scene")
+    ap.add_argument("--scenes", type=int, default=0, help="batched workloads: use only the first scenes")
     return ap.parse_args()
 
 
@@ -106,9 +108,10 @@ def load_tuning(ctx):
     return f"{os.path.relpath(DEFAULT_PATH, ROOT)} ({ctx.tune_count()} classes)"
 
 
-def _batch_scene(s):
+def _gen_scene(args):
     from paper_2103_09943_amd import scenes
-    sc, st = scenes.config_scene(2, s)
+    config, s = args
+    sc, st = scenes.config_scene(config, s)
     return sc.X, sc.Y, sc.u, sc.c
 
 
@@ -122,12 +125,14 @@ def apply_bytes_model(HW, c, band_iters, busy_launches):
             (28.0 + 4.0 / c2) * HW * band_iters)
 
 
-def cpu_baseline_batch(host, settings, reps, budget_s):
-    """FP64 oracle on the host, on a sample of the batch: the setup and CG iterations of the first scenes that
-    fit the budget; the per-pixel setup cost and per-pixel-band iteration cost extrapolated to the whole batch
-    at the GPU's iteration counts."""
+def cpu_baseline_batch(host, settings, reps, budget_s, weights=None):
+    """FP64 oracle on the host, on a sample of the workload: the setup and two CG iterations of the first scenes
+    that fit the budget (and, for network starts, the oracle network on a 64 x 64 crop of one band); per-pixel
+    setup, per-pixel-band network and per-pixel-band iteration costs extrapolated to the whole workload at the
+    GPU's iteration counts."""
     import numpy as np
     import oracle
+    from oracle import cnn
     from oracle.llp import Problem
 
     t_setup = t_iter = 0.0
@@ -148,60 +153,100 @@ def cpu_baseline_batch(host, settings, reps, budget_s):
         used += 1
         if t_setup + 2 * t_iter > budget_s / 2:
             break
-    setup_per_px = t_setup / px
-    iter_per_pxb = t_iter / pxb
+    t_net_px = 0.0
+    if weights is not None:
+        X, Y, u, c = host[0]
+        crop = 64
+        t0 = time.perf_counter()
+        cnn.warm_start(cnn.unflatten(weights), X[:1, :crop // c, :crop // c], Y[:crop, :crop], c)
+        t_net_px = (time.perf_counter() - t0) / (crop * crop)
     total_px = sum(Y.size for _, Y, _, _ in host)
     total_pxb_it = sum(r["iters"] * Y.size for (X, Y, u, c), rs in zip(host, reps) for r in rs)
     total_pxb = sum(X.shape[0] * Y.size for X, Y, u, c in host)
-    t_solve = setup_per_px * total_px + iter_per_pxb * total_pxb_it
+    t_solve = t_setup / px * total_px + t_iter / pxb * total_pxb_it + t_net_px * total_pxb
+    net = " plus the network start (oracle forward timed on a 64x64 crop)" if weights is not None else ""
     return {
         "value": total_pxb / t_solve / 1e6,
         "unit": "Mpixel*bands/s",
         "cores": os.cpu_count(),
         "kind": "oracle",
         "sample": f"setup + 2 CG iterations of every band of the first {used} scene(s), FP64 numpy/scipy.fft "
-                  f"(fft workers = all cores); per-pixel setup and per-pixel-band iteration costs extrapolated "
-                  f"to all {len(host)} scenes at the GPU's iteration counts",
+                  f"(fft workers = all cores){net}; per-pixel costs extrapolated to all {len(host)} scenes at "
+                  f"the GPU's iteration counts",
     }
+
+
+WEIGHTS = os.path.join(ROOT, "paper_2103_09943_amd", "weights", "cnn_warm_start.npy")
+
+# workload -> (generator config, scene ids, start of the timed solve, comparison leg)
+BATCH_WORKLOADS = {
+    "batch": (2, range(64), None, "serial"),
+    "warmstart": (3, range(2000, 2500), "cnn", "cold"),
+    "large": (4, range(4), "cnn", "cold"),
+}
+
+
+def describe(name, host, st, pxb):
+    if name == "batch":
+        return (f"batched plain LLP solve (cold start, one call), {len(host)} scenes, PAN side 256..1024, 4 or 8 "
+                f"bands, 9..17-tap Gaussian blurs, x4, r={st.r}, lambda={st.lam}, eps={st.eps}, tol={st.tol}; "
+                f"{pxb / 1e6:.1f} Mpixel*bands")
+    X, Y, u, c = host[0]
+    taps = sorted({h[2].shape[0] for h in host})
+    return (f"batched LLP solve from the trained network's start (one call), {len(host)} held-out scenes of "
+            f"{X.shape[0]} bands, PAN {Y.shape[0]}x{Y.shape[1]}, x{c}, Gaussian blurs of {taps} taps, r={st.r}, "
+            f"lambda={st.lam}, eps={st.eps}, tol={st.tol}; {pxb / 1e6:.1f} Mpixel*bands")
 
 
 def main_batch(args):
     from concurrent.futures import ProcessPoolExecutor
 
+    import numpy as np
     import torch
 
     from paper_2103_09943_amd import binding as B
     from paper_2103_09943_amd import scenes
 
-    with ProcessPoolExecutor(min(8, os.cpu_count() or 1)) as ex:
-        host = list(ex.map(_batch_scene, range(args.scenes)))
-    _, st = scenes.config_scene(2, 0, side=256)
+    config, ids, init, compare = BATCH_WORKLOADS[args.workload]
+    ids = list(ids)[: args.scenes] if args.scenes else list(ids)
+    workers = max(1, min(8, os.cpu_count() or 1, len(ids)))
+    with ProcessPoolExecutor(workers) as ex:
+        host = list(ex.map(_gen_scene, [(config, s) for s in ids]))
+    _, st = scenes.config_scene(config, ids[0], side=256)
     ds = [(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), torch.from_numpy(u).cuda()) for X, Y, u, _ in host]
     outs = [torch.empty((X.shape[0],) + Y.shape, dtype=torch.float32, device="cuda") for X, Y, u, _ in host]
     pxb = sum(X.shape[0] * Y.size for X, Y, u, _ in host)
     ctx = B.Context(0)
     tuned = load_tuning(ctx)
+    weights = None
+    if init == "cnn":
+        if not os.path.exists(WEIGHTS):
+            raise SystemExit(f"{WEIGHTS} is missing: train it with `python -m paper_2103_09943_amd.train_cnn`")
+        weights = np.load(WEIGHTS)
+        ctx.cnn_set_weights(weights)
     kw = dict(r=st.r, lam=st.lam, eps=st.eps, max_iters=st.max_iters, tol=st.tol, outs=outs)
     # classes missing from the table are tuned by the first call (warm-up)
-    ctx.pansharpen_batch(ds, flags=B.BATCH_AUTOTUNE, **kw)
+    ctx.pansharpen_batch(ds, flags=B.BATCH_AUTOTUNE, inits=init, **kw)
     for _ in range(max(args.warmup - 1, 0)):
-        ctx.pansharpen_batch(ds, **kw)
+        ctx.pansharpen_batch(ds, inits=init, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, reps, status = ctx.pansharpen_batch(ds, **kw)
+        _, reps, status = ctx.pansharpen_batch(ds, inits=init, **kw)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    # the same scenes one after another (single-scene solves), one timed call
+    # comparison leg, one timed call after one untimed: the same scenes one after another, or from Z = 0
+    cflags, cinit = (B.BATCH_SERIAL, init) if compare == "serial" else (0, None)
+    ctx.pansharpen_batch(ds, flags=cflags, inits=cinit, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.pansharpen_batch(ds, flags=B.BATCH_SERIAL, **kw)
+    _, creps, _ = ctx.pansharpen_batch(ds, flags=cflags, inits=cinit, **kw)
     torch.cuda.synchronize()
-    serial_s = time.perf_counter() - t1
-    # one timed call with events around every class launch (eager launches of the same kernels)
+    cmp_s = time.perf_counter() - t1
+    # one call with events around every class launch (eager launches of the same kernels)
     ctx.set_profiling(True)
     ctx.kernel_times(reset=True)
-    _, preps, _ = ctx.pansharpen_batch(ds, **kw)
+    _, preps, _ = ctx.pansharpen_batch(ds, inits=init, **kw)
     kt = ctx.kernel_times(reset=True)
     ctx.set_profiling(False)
     ctx.close()
@@ -217,7 +262,25 @@ def main_batch(args):
     dom = dict(k_apply=(apply_gbs, kt["apply_ms"], kt["apply_launches"]),
                k_dir=(dir_gbs, kt["dir_ms"], kt["dir_launches"]))[dominant]
     iters = [r["iters"] for rs in reps for r in rs]
+    citers = [r["iters"] for rs in creps for r in rs]
     value = pxb / (elapsed / args.steps) / 1e6
+    cfg = {
+        "workload": describe(args.workload, host, st, pxb),
+        "status": status,
+        "tuning": tuned,
+        "iters_min_mean_max": [min(iters), round(sum(iters) / len(iters), 1), max(iters)],
+        "k_apply_gbs": round(apply_gbs, 1),
+        "k_dir_gbs": round(dir_gbs, 1),
+    }
+    if compare == "serial":
+        cfg["serial_value"] = round(pxb / cmp_s / 1e6, 3)
+        cfg["batch_over_serial"] = round(cmp_s / (elapsed / args.steps), 3)
+    else:
+        cfg["plain_cold_value"] = round(pxb / cmp_s / 1e6, 3)
+        cfg["warm_over_cold"] = round(cmp_s / (elapsed / args.steps), 3)
+        cfg["cold_iters_min_mean_max"] = [min(citers), round(sum(citers) / len(citers), 1), max(citers)]
+        cfg["network_starts_rejected"] = sum(r["init"] == B.INIT_NET_REJECTED for rs in reps for r in rs)
+        cfg["weights"] = os.path.relpath(WEIGHTS, ROOT)
     line = {
         "metric": "HRMS Mpixel·channels/s at fixed residual tol, plain vs CNN warm-start",
         "value": round(value, 3),
@@ -229,20 +292,9 @@ def main_batch(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if init is None else "f32 (network: bf16 products, f32 accumulation)",
         "data": "synthetic",
-        "config": {
-            "workload": f"batched plain LLP solve (cold start, one call), {len(host)} scenes, PAN side 256..1024, "
-                        f"4 or 8 bands, 9..17-tap Gaussian blurs, x4, r={st.r}, lambda={st.lam}, eps={st.eps}, "
-                        f"tol={st.tol}; {pxb / 1e6:.1f} Mpixel*bands",
-            "status": status,
-            "tuning": tuned,
-            "iters_min_mean_max": [min(iters), round(sum(iters) / len(iters), 1), max(iters)],
-            "serial_value": round(pxb / serial_s / 1e6, 3),
-            "batch_over_serial": round(serial_s / (elapsed / args.steps), 3),
-            "k_apply_gbs": round(apply_gbs, 1),
-            "k_dir_gbs": round(dir_gbs, 1),
-        },
+        "config": cfg,
         "roofline": {
             "bound": "hbm",
             "kernel": dominant + " (all kernel classes of the batch, eager launches with events)",
@@ -255,7 +307,7 @@ def main_batch(args):
         },
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_batch(host, st, reps, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline_batch(host, st, reps, args.cpu_seconds, weights)
     print(json.dumps(line), flush=True)
 
 
@@ -265,7 +317,7 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the per-band solves would shard "
               "across GPUs with no communication, but this build runs on one device.", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "batch":
+    if args.workload != "scene":
         return main_batch(args)
     import numpy as np
     import torch
