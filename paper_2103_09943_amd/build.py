@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libllp.so")
-SOURCES = ["llp_kernels.hip", "llp_operator.hip", "llp_fast.hip", "llp_api.hip", "llp_batch.hip", "llp_tune.hip", "llp_cnn.hip",
+SOURCES = ["llp_kernels.hip", "llp_operator.hip", "llp_fast.hip", "llp_sweep.hip", "llp_api.hip", "llp_batch.hip", "llp_tune.hip", "llp_cnn.hip",
            "llp_cnn_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

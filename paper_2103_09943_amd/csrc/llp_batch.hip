@@ -26,7 +26,8 @@ struct BatchScene {
 };
 
 long long class_key(const Geom& g, const OpConfig& cfg) {
-  return ((((long long)g.c * 64 + g.R) * 16 + g.r) * 16 + cfg.dir_rows) * 16 + cfg.apply_variant;
+  const long long seg = cfg.apply_variant == kSweepVariant ? cfg.seg_rows : 0;
+  return (((((long long)g.c * 64 + g.R) * 16 + g.r) * 16 + cfg.dir_rows) * 16 + cfg.apply_variant) * 8192 + seg;
 }
 
 // One batched launch per class and kernel: scenes [first, first + count) of the table.
@@ -34,6 +35,7 @@ struct BatchClass {
   int C, R, r, dir_rows, variant;
   int first, count;
   int dir_blocks, apply_blocks;
+  int data_blocks;  // split variant: k_data workgroups
 };
 
 llp_status ensure_batch_mirrors(llp_ctx* ctx, int bands, int scenes) {
@@ -80,8 +82,12 @@ llp_status enqueue_batch_iters(const std::vector<BatchClass>& classes, const Sce
     for (size_t c = 0; c < classes.size(); ++c) {
       const BatchClass& k = classes[c];
       if (prof) HIP_TRY(hipEventRecord(ev[4 * c], s));
-      HIP_TRY(launch_apply_fast_batch(d_table + k.first, k.count, k.apply_blocks, k.C, k.R, k.r, k.variant, par, st,
-                                      s));
+      if (k.variant == kSweepVariant)
+        HIP_TRY(launch_apply_sweep_batch(d_table + k.first, k.count, k.data_blocks, k.apply_blocks, k.C, k.R, k.r,
+                                         par, st, s));
+      else
+        HIP_TRY(launch_apply_fast_batch(d_table + k.first, k.count, k.apply_blocks, k.C, k.R, k.r, k.variant, par,
+                                        st, s));
       if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 1], s));
     }
     HIP_TRY(launch_finalize_batch(kFinApply, d_table, nscenes, nbands, st, max_iters, tol, s));
@@ -253,14 +259,22 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         k.count = 0;
         k.dir_blocks = 0;
         k.apply_blocks = 0;
+        k.data_blocks = 0;
         classes.push_back(k);
       }
       BatchClass& k = classes.back();
       // Scenes start on multiples of 8 workgroups, so that the XCD-aware tile order holds within each scene.
       d.dir_block0 = k.dir_blocks;
       d.apply_block0 = k.apply_blocks;
+      d.data_block0 = k.data_blocks;
+      d.seg_rows = bs.cfg.seg_rows;
       k.dir_blocks += (int)align_up((size_t)d.dir_ntiles * g.N, 8);
-      k.apply_blocks += (int)align_up((size_t)d.apply_ntiles * g.N, 8);
+      if (bs.cfg.apply_variant == kSweepVariant) {  // four bands per k_llp workgroup
+        k.apply_blocks += (int)align_up((size_t)d.apply_ntiles * ((g.N + 3) / 4), 8);
+        k.data_blocks += sweep_data_blocks(g);
+      } else {
+        k.apply_blocks += (int)align_up((size_t)d.apply_ntiles * g.N, 8);
+      }
       k.count += 1;
     }
     HIP_TRY(hipMemcpyAsync(d_table, tab, sizeof(SceneDesc) * nf, hipMemcpyHostToDevice, s));
@@ -313,7 +327,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       for (const BatchClass& k : classes)
         for (long long x : {(long long)k.C, (long long)k.R, (long long)k.r, (long long)k.dir_rows,
                             (long long)k.variant, (long long)k.first, (long long)k.count, (long long)k.dir_blocks,
-                            (long long)k.apply_blocks})
+                            (long long)k.apply_blocks, (long long)k.data_blocks})
           key.push_back(x);
       if (!ctx->gexec || key != ctx->gkey) {
         if (ctx->gexec) {
@@ -323,7 +337,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
           ctx->gkey.clear();
         }
         for (const BatchClass& k : classes) {  // LDS limits are set outside the capture
-          HIP_TRY(launch_apply_fast_batch(d_table, k.count, 0, k.C, k.R, k.r, k.variant, 0, st, s));
+          if (k.variant != kSweepVariant)
+            HIP_TRY(launch_apply_fast_batch(d_table, k.count, 0, k.C, k.R, k.r, k.variant, 0, st, s));
           HIP_TRY(launch_dir_fast_batch(d_table, k.count, 0, k.C, k.R, k.dir_rows, 0, st, s));
         }
         hipStream_t cs = nullptr;

@@ -15,6 +15,7 @@ namespace host {
 
 constexpr int kCheckEvery = 8;  // CG iterations between convergence polls in tolerance mode (even)
 constexpr int kMaxLdsFloats = 160 * 1024 / 4;
+constexpr int kDefaultSegRows = 64;  // rows per segment of the column sweep (split variant)
 
 #define HIP_TRY(expr)                       \
   do {                                      \

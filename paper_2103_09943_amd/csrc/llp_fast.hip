@@ -10,27 +10,13 @@
 // about (K + 2r)/K times instead of 2r+1 times.  B^T D^T y is evaluated per LR cell: a thread holds the
 // (2 floor(R/C) + 1)^2 neighbourhood of y in registers and forms the C x C outputs of its cell from it; the
 // cell's q is then written with one vector store per row.
-#include "llp_device.h"
+#include "llp_fast_util.h"
 
 #include <math.h>
 
 namespace llp {
 using namespace dev;
 
-namespace {
-
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int cfdiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-constexpr int cpmod(int a, int b) { return a - cfdiv(a, b) * b; }
-constexpr int odd(int v) { return v | 1; }
-constexpr int al4(int v) { return (v + 3) & ~3; }
-constexpr int pad_to(int v, int want) { return v + ((want - v % 64) + 64) % 64; }
-
-// Periodic index for -n <= i < 2n (the host routes a geometry here only when every tile region overhangs the
-// image by less than one period; see fast_path_fits).
-__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-}  // namespace
 
 // ==================================================================================== k_dir_fast ===
 
@@ -222,31 +208,6 @@ __device__ __forceinline__ void window_sums(const float (&v)[K + WN - 1], float 
   for (int t = 1; t < K; ++t) {
     s += v[t + WN - 1] - v[t - 1];
     out[t] = s;
-  }
-}
-
-// B^T D^T y for output rows [F0, F0+CR) of one LR cell: yv is the cell's y neighbourhood (rows/cols
-// I - YL .. I + YR), qd[f][j] accumulates output (F0 + f, j).
-template <int C, int R, int YK, int YL, int F0, int CR>
-__device__ __forceinline__ void cell_data_term(const float (&yv)[YK][YK], const float* __restrict__ u,
-                                               float (&qd)[CR][C]) {
-  constexpr int n = 2 * R + 1;
-#pragma unroll
-  for (int f = 0; f < CR; ++f) {
-#pragma unroll
-    for (int fj = 0; fj < C; ++fj) {
-      const int fi = F0 + f;
-      float s = 0.0f;
-#pragma unroll
-      for (int a = cpmod(R - fi, C); a < n; a += C) {
-#pragma unroll
-        for (int b = cpmod(R - fj, C); b < n; b += C) {
-          const int dy = YL + (fi + a - R) / C, dx = YL + (fj + b - R) / C;
-          s = fmaf(u[a * n + b], yv[dy][dx], s);
-        }
-      }
-      qd[f][fj] = s;
-    }
   }
 }
 
@@ -719,8 +680,6 @@ hipError_t run_apply_fast(const Geom& g, ApplyArgs A, const float* u, hipStream_
 // The specialised (C, R, r) triples: the measured workloads (C = 4, n = 9..17, r = 1, 2), C = 2 with the same
 // kernels, and the paper's 29 x 29 kernel at C = 4.  (At C = 2 a 29 x 29 kernel would need a 15 x 15
 // neighbourhood of y per thread; it stays on the generic kernels.)
-#define LLP_FAST_R_LIST4(X, r) X(4, 4, r) X(4, 5, r) X(4, 6, r) X(4, 7, r) X(4, 8, r) X(4, 14, r)
-#define LLP_FAST_R_LIST2(X, r) X(2, 4, r) X(2, 5, r) X(2, 6, r) X(2, 7, r) X(2, 8, r)
 
 }  // namespace
 
@@ -731,6 +690,7 @@ bool fast_path_fits(const Geom& g, int dir_rows, int apply_variant) {
   const int k0_last = ((g.w - 1) / 64) * 64, m0_last = ((g.h - 1) / dir_rows) * dir_rows;
   if (C * HYR > g.W || C * HYR > g.H) return false;
   if (C * (k0_last + 64 + HYR) > 2 * g.W || C * (m0_last + dir_rows + HYR) > 2 * g.H) return false;
+  if (apply_variant == kSweepVariant) return sweep_fits(g, kMinSegRows);
   const int TH = apply_variant == 0 ? 32 : 16, TW = 64, E = 2 * r + 2;
   const int i0_last = ((g.H - 1) / TH) * TH, j0_last = ((g.W - 1) / TW) * TW;
   if (E > g.H || E > g.W || i0_last + TH + E > 2 * g.H || j0_last + TW + E > 2 * g.W) return false;
@@ -748,6 +708,7 @@ bool fast_path_available(int C, int R, int r) {
 }
 
 int fast_apply_lds_floats(int C, int R, int r, int variant) {
+  if (variant == kSweepVariant) return fast_path_available(C, R, r) ? 1 : -1;  // no LDS tiles
 #define LLP_LDS_CASE(CC, RR, rr)                                                           \
   if (C == CC && R == RR && r == rr)                                                       \
     return variant == 0 ? ApplyShape<CC, RR, rr, 32, 64>::total : ApplyShape<CC, RR, rr, 16, 64>::total;

@@ -38,8 +38,11 @@ struct OpConfig {
   int fast;           // 1: kernels specialised on (c, R, r) (fast_path_available), 0: generic kernels
   int dir_rows;       // generic k_dir: LR rows per tile, 4 or 8 (64 LR columns)
   int apply_variant;  // k_apply tile shape index: generic 0 .. kApplyVariants-1 (apply_tile()); fast 0: 32x64,
-                      // 1: 16x64
+                      // 1: 16x64, 2: split (k_data + the column sweep k_llp, see llp_sweep.hip)
+  int seg_rows;       // split variant: rows per sweep segment
 };
+constexpr int kSweepVariant = 2;
+constexpr int kMinSegRows = 32;  // shortest sweep segment the partial-sum buffers are sized for
 bool fast_path_available(int C, int R, int r);
 bool fast_path_fits(const Geom& g, int dir_rows, int apply_variant);
 int fast_apply_lds_floats(int C, int R, int r, int variant);
@@ -104,7 +107,21 @@ struct SceneDesc {
   int band0;                  // first band of the scene in the batch's band-state array
   int dir_ntiles, apply_ntiles;
   int dir_block0, apply_block0;  // first workgroup of the scene in its class's k_dir / k_apply launch
+  int data_block0;               // split variant: first workgroup of the scene in its class's k_data launch
+  int seg_rows;                  // split variant: rows per sweep segment
 };
+
+// Split variant of q = A p (llp_sweep.hip): q_D = B^T D^T y (k_data), then q = q_D + lambda L^T M L p and, in
+// mode 1, the dot products (k_llp); apply_ntiles() partials per band.
+bool sweep_fits(const Geom& g, int seg_rows);
+int sweep_ntiles(const Geom& g, int seg_rows);
+int sweep_data_blocks(const Geom& g);
+int sweep_out_width(int r);
+hipError_t launch_apply_sweep(const Geom& g, int seg_rows, int mode, const float* p, const float* rres,
+                              const float* y, const float* u, const float* G, const float* mu, const float* dinv,
+                              float* q, double* partials, ChanState* st, hipStream_t s);
+hipError_t launch_apply_sweep_batch(const SceneDesc* table, int count, int data_blocks, int llp_blocks, int C,
+                                    int R, int r, int parity, ChanState* st, hipStream_t s);
 
 // k_finalize (kFinDir / kFinApply) for all `bands` bands of the `count` scenes of a table; kFinDir advances each
 // active band's iteration count on the device.

@@ -442,6 +442,7 @@ int dir_ntiles(const Geom& g, const OpConfig& cfg) {
 }
 
 int apply_ntiles(const Geom& g, const OpConfig& cfg) {
+  if (cfg.fast && cfg.apply_variant == kSweepVariant) return sweep_ntiles(g, cfg.seg_rows);
   int TH = 16, TW = 64;
   if (cfg.fast) TH = cfg.apply_variant == 0 ? 32 : 16;
   else if (apply_tile(g.c, cfg.apply_variant, &TH, &TW) != 0) return 0;
@@ -482,6 +483,8 @@ hipError_t launch_apply(const Geom& g, const OpConfig& cfg, int mode, const floa
   A.partials = partials;
   A.st = st;
   A.pstride = (int)max_partials_per_band(g);
+  if (cfg.fast && cfg.apply_variant == kSweepVariant)
+    return launch_apply_sweep(g, cfg.seg_rows, mode, p, r, y, u, G, mu, dinv, q, partials, st, s);
   return launch_apply_kernel(g, cfg, A, u, s);
 }
 
@@ -510,6 +513,9 @@ size_t max_partials_per_band(const Geom& g) {
     const size_t t = (size_t)((g.H + TH - 1) / TH) * ((g.W + TW - 1) / TW);
     if (t > m) m = t;
   }
+  // column sweep: strips of at least 52 columns, segments of at least kMinSegRows rows
+  const size_t sw = (size_t)((g.W + 51) / 52) * ((g.H + kMinSegRows - 1) / kMinSegRows);
+  if (sw > m) m = sw;
   return m;
 }
 

@@ -34,10 +34,16 @@ constexpr double kMargin = 0.97;    // a candidate replaces the default only if 
 std::vector<OpConfig> candidates(const Geom& g, bool allow_fast) {
   std::vector<OpConfig> out;
   if (allow_fast && fast_path_available(g.c, g.R, g.r)) {
-    for (int v : {1, 0})
+    for (int v : {kSweepVariant, 1, 0})
       for (int rows : {4, 8}) {
         const int f = fast_apply_lds_floats(g.c, g.R, g.r, v);
-        if (f > 0 && f <= kMaxLdsFloats && fast_path_fits(g, rows, v)) out.push_back(OpConfig{1, rows, v});
+        if (!(f > 0 && f <= kMaxLdsFloats && fast_path_fits(g, rows, v))) continue;
+        if (v == kSweepVariant) {
+          for (int seg : {32, 64, 128})
+            if (seg >= kMinSegRows) out.push_back(OpConfig{1, rows, v, seg});
+        } else {
+          out.push_back(OpConfig{1, rows, v, kDefaultSegRows});
+        }
       }
     if (!out.empty()) return out;
   }
@@ -47,14 +53,15 @@ std::vector<OpConfig> candidates(const Geom& g, bool allow_fast) {
       int TH = 0, TW = 0;
       if (apply_tile(g.c, v, &TH, &TW) != 0) continue;
       if (apply_lds_floats(g.c, TH, TW, g.R, g.r, nullptr, nullptr, nullptr, nullptr) > kMaxLdsFloats) continue;
-      out.push_back(OpConfig{0, rows, v});
+      out.push_back(OpConfig{0, rows, v, kDefaultSegRows});
     }
   }
   return out;
 }
 
 bool same(const OpConfig& a, const OpConfig& b) {
-  return a.fast == b.fast && a.dir_rows == b.dir_rows && a.apply_variant == b.apply_variant;
+  return a.fast == b.fast && a.dir_rows == b.dir_rows && a.apply_variant == b.apply_variant &&
+         (a.apply_variant != kSweepVariant || a.seg_rows == b.seg_rows);
 }
 
 // Microseconds per CG iteration of the scene with configuration cfg (the fastest of kRuns timed runs after
@@ -187,8 +194,9 @@ llp_status llp_tune_save(llp_ctx* ctx, const char* path) {
     const TuneEntry& t = ctx->tuned[i];
     fprintf(f,
             "%s\n    {\"c\": %d, \"R\": %d, \"r\": %d, \"bucket\": %d, \"fast\": %d, \"dir_rows\": %d, "
-            "\"apply_variant\": %d, \"us_per_iter\": %.2f}",
-            i ? "," : "", t.c, t.R, t.r, t.bucket, t.cfg.fast, t.cfg.dir_rows, t.cfg.apply_variant, t.us_per_iter);
+            "\"apply_variant\": %d, \"seg_rows\": %d, \"us_per_iter\": %.2f}",
+            i ? "," : "", t.c, t.R, t.r, t.bucket, t.cfg.fast, t.cfg.dir_rows, t.cfg.apply_variant, t.cfg.seg_rows,
+            t.us_per_iter);
   }
   fprintf(f, "\n  ]\n}\n");
   return fclose(f) == 0 ? LLP_OK : LLP_E_ARG;
@@ -224,9 +232,11 @@ llp_status llp_tune_load(llp_ctx* ctx, const char* path) {
         !json_number(t, b, e, "dir_rows", &rows) || !json_number(t, b, e, "apply_variant", &var))
       return LLP_E_ARG;
     json_number(t, b, e, "us_per_iter", &us);
-    const OpConfig cfg{(int)fast, (int)rows, (int)var};
+    double seg = kDefaultSegRows;
+    json_number(t, b, e, "seg_rows", &seg);
+    const OpConfig cfg{(int)fast, (int)rows, (int)var, (int)seg};
     if ((cfg.fast != 0 && cfg.fast != 1) || (cfg.dir_rows != 4 && cfg.dir_rows != 8) || cfg.apply_variant < 0 ||
-        cfg.apply_variant >= kApplyVariants)
+        cfg.apply_variant >= kApplyVariants || cfg.seg_rows < kMinSegRows || cfg.seg_rows > 4096)
       return LLP_E_ARG;
     entries.push_back(TuneEntry{(int)c, (int)R, (int)r, (int)bucket, cfg, us});
     pos = e + 1;
