@@ -89,7 +89,10 @@ typedef struct llp_ctx llp_ctx;
 
 /* Create a context bound to HIP device `device`.  *out receives the handle.  If the environment variable
  * LLP_FORCE_GENERIC is set (and not "0") at creation, the context uses only the generic kernels (no
- * specialisation on kernel size, scale and window radius); results agree to rounding. */
+ * specialisation on kernel size, scale and window radius); results agree to rounding.  LLP_DIR_ROWS (4, 8),
+ * LLP_APPLY_VARIANT (0: 32x64 tiles, 1: 16x64 tiles, 2: split data term + column sweep) and LLP_SEG_ROWS
+ * (rows per sweep segment, >= 32) force a launch configuration of the specialised kernels instead of the
+ * tuned or default one. */
 llp_status llp_create(llp_ctx** out, int device);
 
 /* Release a context and all its workspaces.  NULL is accepted. */
@@ -149,7 +152,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
 typedef struct {
   int fast;                   /* 1: kernels specialised on (c, n, r); 0: generic kernels */
   int dir_rows;               /* LR rows per tile of the update kernel (4 or 8) */
-  int apply_variant;          /* tile shape of the operator kernel */
+  int apply_variant;          /* operator kernel: 0 32x64 tiles, 1 16x64 tiles, 2 split (data term + sweep) */
+  int seg_rows;               /* rows per sweep segment (apply_variant 2) */
   double us_per_iter;         /* measured time of one CG iteration (both kernels, all bands) with that choice */
   double default_us_per_iter; /* the same for the untuned default choice */
   int candidates;             /* configurations timed */
@@ -159,8 +163,9 @@ typedef struct {
  * candidate, HIP events around the kernels, the fastest of three runs after an untimed one) and keep the
  * fastest (the default unless another is at least 3% faster) for the geometry's class: (c, n, r) and the
  * image area H*W in half-octaves.  Later solves of that class on this context, single or batched, use it
- * (unless LLP_DIR_ROWS / LLP_APPLY_VARIANT override the choice).  Inputs as for llp_pansharpen; scratch:
- * device [N][H][W] float32 written during tuning, or NULL (allocated and freed by the call);
+ * (unless LLP_DIR_ROWS / LLP_APPLY_VARIANT / LLP_SEG_ROWS override the choice).  Inputs as for
+ * llp_pansharpen; scratch: device [N][H][W] float32 written during tuning, or NULL (allocated and freed by the
+ * call);
  * 1 <= iters <= 1000; out: host, or NULL.  Synchronises `stream`. */
 llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
                         const float* pan, const float* kernel, float* scratch, int iters, llp_tune_result* out,

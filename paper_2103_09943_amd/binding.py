@@ -43,7 +43,7 @@ class KernelTimes(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("fast", ctypes.c_int), ("dir_rows", ctypes.c_int), ("apply_variant", ctypes.c_int),
-                ("us_per_iter", ctypes.c_double), ("default_us_per_iter", ctypes.c_double),
+                ("seg_rows", ctypes.c_int), ("us_per_iter", ctypes.c_double), ("default_us_per_iter", ctypes.c_double),
                 ("candidates", ctypes.c_int)]
 
 

@@ -59,9 +59,13 @@ llp_status validate(const llp_shape* s, const llp_params* p, Geom* g) {
 
 bool pick_config(const Geom& g, OpConfig* cfg, bool allow_fast, int want_dir_rows, int want_apply_variant) {
   cfg->fast = 0;
-  cfg->seg_rows = kDefaultSegRows;
+  // Untuned defaults, from the autotuner's measurements on gfx950: the column sweep needs enough segments to
+  // fill the chip, so small images keep the 16 x 64 tiles; short segments suit r = 1, longer ones r = 2.
+  cfg->seg_rows = g.r == 1 ? kMinSegRows : (g.H >= 1024 ? 4 * kMinSegRows : 2 * kMinSegRows);
+  const bool big = (size_t)g.H * g.W >= (size_t)600 * 600;
   if (allow_fast && fast_path_available(g.c, g.R, g.r)) {
-    for (int v : {kSweepVariant, 1, 0}) {  // preference order (measured on the 2048^2 scene)
+    const int order_big[3] = {kSweepVariant, 1, 0}, order_small[3] = {1, kSweepVariant, 0};
+    for (int v : big ? order_big : order_small) {
       if (want_apply_variant >= 0 && v != want_apply_variant) continue;
       const int f = fast_apply_lds_floats(g.c, g.R, g.r, v);
       const int rows = want_dir_rows == 8 ? 8 : 4;
@@ -94,7 +98,7 @@ bool pick_config(const Geom& g, OpConfig* cfg, bool allow_fast, int want_dir_row
 
 llp_status ensure_workspace(llp_ctx* ctx, const Geom& g) {
   const size_t HW = (size_t)g.H * g.W;
-  const size_t planes = 3 * HW + 6 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w;
+  const size_t planes = 7 * HW + 6 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w;
   const size_t pstride = max_partials_per_band(g);
   size_t off = 0;
   const size_t o_planes = off;
@@ -123,11 +127,12 @@ llp_status ensure_workspace(llp_ctx* ctx, const Geom& g) {
   }
   char* base = (char*)ctx->ws;
   float* pl = (float*)(base + o_planes);
-  ctx->G = pl;
-  ctx->MU = pl + HW;
-  ctx->DI = pl + 2 * HW;
+  ctx->GMD = (float4*)pl;  // first: 16-byte aligned
+  ctx->G = pl + 4 * HW;
+  ctx->MU = pl + 5 * HW;
+  ctx->DI = pl + 6 * HW;
   const size_t NHW = (size_t)g.N * HW;
-  ctx->b = pl + 3 * HW;
+  ctx->b = pl + 7 * HW;
   ctx->r[0] = ctx->b + NHW;
   ctx->r[1] = ctx->r[0] + NHW;
   ctx->p[0] = ctx->r[1] + NHW;
@@ -194,14 +199,14 @@ llp_status apply_A_into(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const 
                         float* q, hipStream_t s) {
   HIP_TRY(launch_dir(g, cfg, 0, 0, 0, z, nullptr, nullptr, nullptr, nullptr, nullptr, ctx->y, kernel, ctx->partials,
                      ctx->st, 0, 0.0f, s));
-  HIP_TRY(launch_apply(g, cfg, 0, z, nullptr, ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, q, ctx->partials,
+  HIP_TRY(launch_apply(g, cfg, 0, z, nullptr, ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, ctx->GMD, q, ctx->partials,
                        ctx->st, s));
   return LLP_OK;
 }
 
 
 bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg) {
-  if (ctx->want_dir_rows == 0 && ctx->want_apply_variant < 0) {
+  if (ctx->want_dir_rows == 0 && ctx->want_apply_variant < 0 && ctx->want_seg_rows == 0) {
     const int bucket = area_bucket(g);
     for (const TuneEntry& t : ctx->tuned) {
       if (t.c != g.c || t.R != g.R || t.r != g.r || t.bucket != bucket) continue;
@@ -212,7 +217,9 @@ bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg) {
       return true;
     }
   }
-  return pick_config(g, cfg, ctx->allow_fast, ctx->want_dir_rows, ctx->want_apply_variant);
+  if (!pick_config(g, cfg, ctx->allow_fast, ctx->want_dir_rows, ctx->want_apply_variant)) return false;
+  if (ctx->want_seg_rows >= kMinSegRows) cfg->seg_rows = ctx->want_seg_rows;
+  return true;
 }
 
 llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const llp_params* params,
@@ -229,7 +236,7 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
   v = check_inputs(ctx, g, lrms, pan, kernel, s);
   if (v != LLP_OK) return v;
   // Per scene: the statistics that define M_LY, then the right-hand sides and ||b||.
-  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, s));
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, ctx->GMD, s));
   HIP_TRY(launch_rhs(g, lrms, kernel, ctx->b, ctx->partials, ctx->st, s));
   const int from_init = params->init_mode != 0;
   if (params->init_mode == 1 && init != hrms)
@@ -267,7 +274,8 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
           if (!(ev = timing_event(ctx))) return LLP_E_HIP;
         HIP_TRY(hipEventRecord(e[0], s));
       }
-      HIP_TRY(launch_apply(g, cfg, 1, ctx->p[prev], ctx->r[prev], ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, ctx->q,
+      HIP_TRY(launch_apply(g, cfg, 1, ctx->p[prev], ctx->r[prev], ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, ctx->GMD,
+                           ctx->q,
                            ctx->partials, ctx->st, s));
       if (ctx->profiling) HIP_TRY(hipEventRecord(e[1], s));
       HIP_TRY(launch_finalize(g, kFinApply, ctx->partials, nb_apply, ctx->st, nullptr, 0, 0, 0, 0.0f, s));
@@ -374,6 +382,7 @@ llp_status llp_create(llp_ctx** out, int device) {
   ctx->allow_fast = !(fg && fg[0] && fg[0] != '0');
   if (const char* e = getenv("LLP_DIR_ROWS")) ctx->want_dir_rows = atoi(e);
   if (const char* e = getenv("LLP_APPLY_VARIANT")) ctx->want_apply_variant = atoi(e);
+  if (const char* e = getenv("LLP_SEG_ROWS")) ctx->want_seg_rows = atoi(e);
   for (auto& e : ctx->ev) {
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       llp_destroy(ctx);
@@ -415,7 +424,7 @@ llp_status llp_pan_stats(llp_ctx* ctx, const llp_shape* shape, const llp_params*
   llp_status v = validate(shape, params, &g);
   if (v != LLP_OK) return v;
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(launch_pan_stats(g, pan, G, mu, dinv, stream));
+  HIP_TRY(launch_pan_stats(g, pan, G, mu, dinv, nullptr, stream));
   return LLP_OK;
 }
 
@@ -444,7 +453,7 @@ llp_status llp_apply_A(llp_ctx* ctx, const llp_shape* shape, const llp_params* p
   HIP_TRY(hipSetDevice(ctx->device));
   v = ensure_workspace(ctx, g);
   if (v != LLP_OK) return v;
-  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, ctx->GMD, stream));
   return apply_A_into(ctx, g, cfg, z, kernel, Az, stream);
 }
 
@@ -457,7 +466,7 @@ llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params*
   HIP_TRY(hipSetDevice(ctx->device));
   v = ensure_workspace(ctx, g);
   if (v != LLP_OK) return v;
-  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, ctx->GMD, stream));
   HIP_TRY(launch_objective(g, z, lrms, kernel, ctx->G, ctx->MU, ctx->DI, ctx->partials, ctx->st, ctx->results,
                            stream));
   HIP_TRY(hipMemcpyAsync(ctx->h_results, ctx->results, sizeof(double) * kResultSlots * g.N, hipMemcpyDeviceToHost,

@@ -15,7 +15,6 @@ namespace host {
 
 constexpr int kCheckEvery = 8;  // CG iterations between convergence polls in tolerance mode (even)
 constexpr int kMaxLdsFloats = 160 * 1024 / 4;
-constexpr int kDefaultSegRows = 64;  // rows per segment of the column sweep (split variant)
 
 #define HIP_TRY(expr)                       \
   do {                                      \
@@ -75,10 +74,12 @@ struct llp_ctx {
   bool allow_fast = true;  // false when LLP_FORCE_GENERIC is set at creation: generic kernels only
   int want_dir_rows = 0;   // launch-shape overrides (0: default), from LLP_DIR_ROWS / LLP_APPLY_VARIANT
   int want_apply_variant = -1;
+  int want_seg_rows = 0;  // LLP_SEG_ROWS: rows per sweep segment of the split variant (>= kMinSegRows)
   void* ws = nullptr;
   size_t ws_bytes = 0;
   // views into ws
   float *G = nullptr, *MU = nullptr, *DI = nullptr, *b = nullptr, *q = nullptr, *y = nullptr;
+  float4* GMD = nullptr;  // (G, mu, dinv, 0) interleaved, for the column sweep
   float* r[2] = {nullptr, nullptr};  // residual, alternating between iterations
   float* p[2] = {nullptr, nullptr};  // direction, alternating between iterations
   double* partials = nullptr;

@@ -56,7 +56,9 @@ int apply_tile(int C, int variant, int* TH, int* TW);
 
 // Kernel launchers.  All enqueue on `s` and return the launch status.  Reductions leave their partial sums in
 // `partials` and finish with a k_finalize launch.
-hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, hipStream_t s);
+// G, mu, dinv as planes and, if gmd is not NULL, interleaved as (G, mu, dinv, 0) per pixel (16-byte aligned).
+hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, float4* gmd,
+                            hipStream_t s);
 hipError_t launch_check_finite(const float* a, size_t count, int* flag, hipStream_t s);
 hipError_t launch_finalize(const Geom& g, int op, const double* partials, int nblk, ChanState* st,
                            double* results, int slot, int k_iter, int max_iters, float tol, hipStream_t s);
@@ -74,9 +76,10 @@ hipError_t launch_dir(const Geom& g, const OpConfig& cfg, int mode, int final_st
                       const float* u, double* partials, ChanState* st, int max_iters, float tol, hipStream_t s);
 // mode 0: q = A z (z = p, y = D B z).  mode 1: q = A p_k and partials of the dot products; followed by
 // launch_finalize(kFinApply, nblk = apply_ntiles) for alpha_k, beta_k.
+// gmd: the interleaved statistics (launch_pan_stats), required by the split variant, otherwise unused.
 hipError_t launch_apply(const Geom& g, const OpConfig& cfg, int mode, const float* p, const float* r,
-                        const float* y, const float* u, const float* G, const float* mu, const float* dinv, float* q,
-                        double* partials, ChanState* st, hipStream_t s);
+                        const float* y, const float* u, const float* G, const float* mu, const float* dinv,
+                        const float4* gmd, float* q, double* partials, ChanState* st, hipStream_t s);
 int dir_ntiles(const Geom& g, const OpConfig& cfg);
 int apply_ntiles(const Geom& g, const OpConfig& cfg);
 // After a network start: bands whose start is no better than zero restart from zero (see k_fallback).
@@ -100,6 +103,7 @@ struct SceneDesc {
   const float* u;  // kernel [n][n]
   float* x;        // HRMS [N][H][W] (the iterate)
   float *G, *MU, *DI, *b, *q, *y;
+  float4* GMD;  // (G, mu, dinv, 0) interleaved
   float* r[2];
   float* p[2];
   double* partials;  // [N][pstride][3]
@@ -118,8 +122,8 @@ int sweep_ntiles(const Geom& g, int seg_rows);
 int sweep_data_blocks(const Geom& g);
 int sweep_out_width(int r);
 hipError_t launch_apply_sweep(const Geom& g, int seg_rows, int mode, const float* p, const float* rres,
-                              const float* y, const float* u, const float* G, const float* mu, const float* dinv,
-                              float* q, double* partials, ChanState* st, hipStream_t s);
+                              const float* y, const float* u, const float4* gmd, float* q, double* partials,
+                              ChanState* st, hipStream_t s);
 hipError_t launch_apply_sweep_batch(const SceneDesc* table, int count, int data_blocks, int llp_blocks, int C,
                                     int R, int r, int parity, ChanState* st, hipStream_t s);
 

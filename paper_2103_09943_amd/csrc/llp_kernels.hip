@@ -44,7 +44,8 @@ __device__ __forceinline__ double lap64(const float* __restrict__ Y, int i, int 
 }
 
 __global__ __launch_bounds__(kBlock) void k_pan_stats(Geom g, const float* __restrict__ Y, float* __restrict__ G,
-                                                      float* __restrict__ MU, float* __restrict__ DI) {
+                                                      float* __restrict__ MU, float* __restrict__ DI,
+                                                      float4* __restrict__ GMD) {
   const size_t HW = (size_t)g.H * g.W;
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= HW) return;
@@ -63,15 +64,19 @@ __global__ __launch_bounds__(kBlock) void k_pan_stats(Geom g, const float* __res
   const double mu = s1 / nw;
   const double var = s2 / nw - mu * mu;
   const double den = (double)g.eps / nw + var;
-  G[idx] = (float)lap64(Y, ki, kj, g.H, g.W);
-  MU[idx] = (float)mu;
-  DI[idx] = den != 0.0 ? (float)(1.0 / den) : 0.0f;
+  const float gv = (float)lap64(Y, ki, kj, g.H, g.W), mv = (float)mu;
+  const float dv = den != 0.0 ? (float)(1.0 / den) : 0.0f;
+  G[idx] = gv;
+  MU[idx] = mv;
+  DI[idx] = dv;
+  if (GMD) GMD[idx] = make_float4(gv, mv, dv, 0.0f);
 }
 
-hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, hipStream_t s) {
+hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, float4* gmd,
+                            hipStream_t s) {
   const size_t HW = (size_t)g.H * g.W;
   hipLaunchKernelGGL(k_pan_stats, dim3((unsigned)((HW + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g, Y, G, mu,
-                     dinv);
+                     dinv, gmd);
   return hipGetLastError();
 }
 

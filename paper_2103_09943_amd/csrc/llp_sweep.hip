@@ -95,11 +95,9 @@ __global__ __launch_bounds__(kBlock) void k_data(Geom g, const float* __restrict
 struct SweepArgs {
   int mode;          // 0: q = A p; 1: also the partial dot products, inactive bands skipped
   const float* p;
-  const float* r;    // residual (mode 1)
-  const float* G;
-  const float* MU;
-  const float* DI;
-  float* q;          // in: q_D (k_data); out: q
+  const float* r;      // residual (mode 1)
+  const float4* GMD;   // (G, mu, dinv, 0) per pixel
+  float* q;            // in: q_D (k_data); out: q
   double* partials;  // [N][pstride][3]
   ChanState* st;
   int pstride;
@@ -135,47 +133,40 @@ __device__ __forceinline__ void llp_body(const Geom& g, const SweepArgs& A, int 
   const float* __restrict__ pb = A.p + (size_t)band * HW;
   const float* __restrict__ rb = A.r + (size_t)band * HW;
   float* __restrict__ qb = A.q + (size_t)band * HW;
-  const float* __restrict__ Gp = A.G;
-  const float* __restrict__ MUp = A.MU;
-  const float* __restrict__ DIp = A.DI;
   const float lam = g.lam;
-  float pr[P], gr[P], lr[P], h1[P], h2[P], ha[P], hb[P], mr[P];
+  float pr[P], gr[P], mur[P], dir[P], lr[P], h1[P], h2[P], ha[P], hb[P], mr[P];
 #pragma unroll
-  for (int k = 0; k < P; ++k) pr[k] = gr[k] = lr[k] = h1[k] = h2[k] = ha[k] = hb[k] = mr[k] = 0.0f;
+  for (int k = 0; k < P; ++k) pr[k] = gr[k] = mur[k] = dir[k] = lr[k] = h1[k] = h2[k] = ha[k] = hb[k] = mr[k] = 0.0f;
+  float p_old = 0.0f;  // p of row t-P-1 = t-E (the value evicted from the p ring one step earlier)
   double dsum[3] = {0.0, 0.0, 0.0};
-  // Global values step t uses: p row t, G row t-1, mu and dinv row t-1-r, q_D (and p, r) row t-E.  They are
-  // loaded one unrolled block (P steps) ahead into alternating buffers, so a block computes while the next
-  // block's loads are in flight.
+  // Global values step t uses: p row t, the statistics (G, mu, dinv) of row t-1, and q_D (and r) of row t-E;
+  // G, mu, dinv are kept in rings until rows t-P and t-1-r need them.  They are loaded one unrolled block
+  // (P steps) ahead into alternating buffers, so a block computes while the next block's loads are in flight.
   struct In {
-    float p, g, mu, di, qd, pc, rc;
+    float p, qd, rc;
+    float4 s;
   };
   // Loads and stores go through buffer resources over one plane each: the row is a scalar byte offset, the
   // lane's column a fixed vector byte offset, so no per-access address arithmetic is left in the loop.
   const unsigned gc4 = gc * 4u, W4 = (unsigned)W * 4u, plane = (unsigned)(HW * 4);
-  auto rsrc = [&](const float* base) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)plane, 0x00020000);
+  auto rsrc = [&](const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
   };
-  const __amdgpu_buffer_rsrc_t Rp = rsrc(pb), Rq = rsrc(qb), RG = rsrc(Gp), RM = rsrc(MUp), RD = rsrc(DIp);
-  const __amdgpu_buffer_rsrc_t Rr = rsrc(MODE == 1 ? rb : pb);
+  const __amdgpu_buffer_rsrc_t Rp = rsrc(pb, plane), Rq = rsrc(qb, plane), Rs = rsrc(A.GMD, plane * 4u);
+  const __amdgpu_buffer_rsrc_t Rr = rsrc(MODE == 1 ? rb : pb, plane);
   auto ld = [&](__amdgpu_buffer_rsrc_t R, unsigned off) -> float {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(R, gc4, off, 0));
   };
   const int tstart = i0 - E;
   unsigned o0 = (unsigned)wrap_row(tstart, H) * W4, o1 = (unsigned)wrap_row(tstart - 1, H) * W4,
-           o2 = (unsigned)wrap_row(tstart - 1 - r, H) * W4, o3 = (unsigned)wrap_row(tstart - E, H) * W4;
+           o3 = (unsigned)wrap_row(tstart - E, H) * W4;
   auto load = [&](In& v) {
     v.p = ld(Rp, o0);
-    v.g = ld(RG, o1);
-    v.mu = ld(RM, o2);
-    v.di = ld(RD, o2);
+    v.s = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(Rs, gc4 * 4u, o1 * 4u, 0));
     v.qd = ld(Rq, o3);
-    if (MODE == 1) {
-      v.pc = ld(Rp, o3);
-      v.rc = ld(Rr, o3);
-    }
+    if (MODE == 1) v.rc = ld(Rr, o3);
     o0 = o0 + W4 == plane ? 0u : o0 + W4;
     o1 = o1 + W4 == plane ? 0u : o1 + W4;
-    o2 = o2 + W4 == plane ? 0u : o2 + W4;
     o3 = o3 + W4 == plane ? 0u : o3 + W4;
   };
   // P steps from row tb with the values in cv; the slot of row x in every ring is (x - tb) mod P
@@ -185,14 +176,18 @@ __device__ __forceinline__ void llp_body(const Geom& g, const SweepArgs& A, int 
     for (int k = 0; k < P; ++k) {
       const int t = tb + k;
       const int km1 = (k + P - 1) % P, km2 = (k + P - 2) % P, kr = (k + r) % P;
+      const float p_c3 = p_old;  // p of row t-E
+      p_old = pr[k];
       pr[k] = cv[k].p;
       // l of row t-1
       const float pc = pr[km1];
       const float l = 4.0f * pc - pr[km2] - pr[k] - from_left(pc) - from_right(pc);
       lr[km1] = l;
-      gr[km1] = cv[k].g;
+      gr[km1] = cv[k].s.x;
+      mur[km1] = cv[k].s.y;
+      dir[km1] = cv[k].s.z;
       h1[km1] = hbox<r>(l);
-      h2[km1] = hbox<r>(cv[k].g * l);
+      h2[km1] = hbox<r>(cv[k].s.x * l);
       // window sums centred on row t-1-r, and that window's a, b
       float sl = 0.0f, sg = 0.0f;
 #pragma unroll
@@ -200,7 +195,7 @@ __device__ __forceinline__ void llp_body(const Geom& g, const SweepArgs& A, int 
         sl += h1[s];
         sg += h2[s];
       }
-      const float mu = cv[k].mu, di = cv[k].di;
+      const float mu = mur[kr], di = dir[kr];
       const float m1 = sl * inv_nw, m2 = sg * inv_nw;
       const float av = (m2 - mu * m1) * di;
       const float bv = m1 - av * mu;
@@ -223,7 +218,7 @@ __device__ __forceinline__ void llp_body(const Geom& g, const SweepArgs& A, int 
           const float qv = cv[k].qd + ql;
           __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(qv), Rq, gc4, (unsigned)c3 * W4, 0);
           if (MODE == 1) {
-            dacc[0] = fmaf(cv[k].pc, qv, dacc[0]);
+            dacc[0] = fmaf(p_c3, qv, dacc[0]);
             dacc[1] = fmaf(cv[k].rc, qv, dacc[1]);
             dacc[2] = fmaf(qv, qv, dacc[2]);
           }
@@ -302,9 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_llp_batch(const SceneDesc* __restric
   A.mode = 1;
   A.p = d.p[parity];
   A.r = d.r[parity];
-  A.G = d.G;
-  A.MU = d.MU;
-  A.DI = d.DI;
+  A.GMD = d.GMD;
   A.q = d.q;
   A.partials = d.partials;
   A.st = st + d.band0;
@@ -324,7 +317,7 @@ int sweep_out_width(int r) { return 64 - 2 * (2 * r + 2); }
 bool sweep_fits(const Geom& g, int seg_rows) {
   const int E = 2 * g.r + 2;
   if (g.r != 1 && g.r != 2) return false;
-  if ((size_t)g.H * g.W * 4 >= ((size_t)1 << 31)) return false;  // byte offsets of a plane fit a buffer resource
+  if ((size_t)g.H * g.W * 16 >= ((size_t)1 << 31)) return false;  // byte offsets fit a buffer resource
   if (seg_rows < 1 || g.H < 3 * E) return false;  // rows wrap at most once
   const int YL = g.R / g.c, YR = (g.c - 1 + g.R) / g.c;
   return YL <= g.h && YR <= g.h && YL <= g.w && YR <= g.w;
@@ -359,17 +352,15 @@ hipError_t launch_data(const Geom& g, const float* y, const float* u, float* q, 
 
 // q = A p by the split kernels (mode 0: q only; mode 1: CG step with dot products, inactive bands skipped).
 hipError_t launch_apply_sweep(const Geom& g, int seg_rows, int mode, const float* p, const float* rres,
-                              const float* y, const float* u, const float* G, const float* mu, const float* dinv,
-                              float* q, double* partials, ChanState* st, hipStream_t s) {
+                              const float* y, const float* u, const float4* gmd, float* q, double* partials,
+                              ChanState* st, hipStream_t s) {
   hipError_t e = launch_data(g, y, u, q, mode == 1 ? st : nullptr, s);
   if (e != hipSuccess) return e;
   SweepArgs A{};
   A.mode = mode;
   A.p = p;
   A.r = rres;
-  A.G = G;
-  A.MU = mu;
-  A.DI = dinv;
+  A.GMD = gmd;
   A.q = q;
   A.partials = partials;
   A.st = st;

@@ -39,10 +39,10 @@ std::vector<OpConfig> candidates(const Geom& g, bool allow_fast) {
         const int f = fast_apply_lds_floats(g.c, g.R, g.r, v);
         if (!(f > 0 && f <= kMaxLdsFloats && fast_path_fits(g, rows, v))) continue;
         if (v == kSweepVariant) {
-          for (int seg : {32, 64, 128})
+          for (int seg : {32, 64, 128, 256})
             if (seg >= kMinSegRows) out.push_back(OpConfig{1, rows, v, seg});
         } else {
-          out.push_back(OpConfig{1, rows, v, kDefaultSegRows});
+          out.push_back(OpConfig{1, rows, v, 2 * kMinSegRows});
         }
       }
     if (!out.empty()) return out;
@@ -53,7 +53,7 @@ std::vector<OpConfig> candidates(const Geom& g, bool allow_fast) {
       int TH = 0, TW = 0;
       if (apply_tile(g.c, v, &TH, &TW) != 0) continue;
       if (apply_lds_floats(g.c, TH, TW, g.R, g.r, nullptr, nullptr, nullptr, nullptr) > kMaxLdsFloats) continue;
-      out.push_back(OpConfig{0, rows, v, kDefaultSegRows});
+      out.push_back(OpConfig{0, rows, v, 2 * kMinSegRows});
     }
   }
   return out;
@@ -170,6 +170,7 @@ llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* 
     out->fast = best.fast;
     out->dir_rows = best.dir_rows;
     out->apply_variant = best.apply_variant;
+    out->seg_rows = best.seg_rows;
     out->us_per_iter = best_us;
     out->default_us_per_iter = def_us;
     out->candidates = (int)cands.size();
@@ -232,7 +233,7 @@ llp_status llp_tune_load(llp_ctx* ctx, const char* path) {
         !json_number(t, b, e, "dir_rows", &rows) || !json_number(t, b, e, "apply_variant", &var))
       return LLP_E_ARG;
     json_number(t, b, e, "us_per_iter", &us);
-    double seg = kDefaultSegRows;
+    double seg = 2 * kMinSegRows;
     json_number(t, b, e, "seg_rows", &seg);
     const OpConfig cfg{(int)fast, (int)rows, (int)var, (int)seg};
     if ((cfg.fast != 0 && cfg.fast != 1) || (cfg.dir_rows != 4 && cfg.dir_rows != 8) || cfg.apply_variant < 0 ||

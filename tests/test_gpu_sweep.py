@@ -1,0 +1,118 @@
+"""GPU: the split operator variant (data term per LR cell + column sweep of the LLP term) against the oracle.
+
+The variant is forced with LLP_APPLY_VARIANT=2 (and segment lengths with LLP_SEG_ROWS) so that it is exercised
+on small, ragged shapes too: strips of 52 (r = 2) or 56 (r = 1) output columns and segments of 32..96 rows,
+neither dividing the image, plus images only a few segments tall.  Bars as in the other parity tests: the
+operator to relative L2 <= 1e-5 per band, the CG iterate after a fixed count to 1e-5, and bit-identical results
+between the single-scene and the batched launches of the same kernels.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.llp import Problem
+from paper_2103_09943_amd import binding as B
+from paper_2103_09943_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def make_ctx(seg_rows):
+    os.environ["LLP_APPLY_VARIANT"] = "2"
+    os.environ["LLP_SEG_ROWS"] = str(seg_rows)
+    try:
+        return B.Context(0)
+    finally:
+        del os.environ["LLP_APPLY_VARIANT"]
+        del os.environ["LLP_SEG_ROWS"]
+
+
+@pytest.fixture(scope="module", params=[32, 96])
+def sweep_ctx(request, torch_dev):
+    c = make_ctx(request.param)
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_l2(got, want):
+    got = got.reshape(got.shape[0], -1)
+    want = want.reshape(want.shape[0], -1)
+    return np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+
+
+SHAPES = [  # N, h, w, c, n, r  (H = c h >= 3 (2r + 2) rows)
+    (2, 20, 18, 2, 9, 1),
+    (1, 16, 40, 2, 17, 2),
+    (3, 24, 24, 4, 11, 2),
+    (1, 9, 33, 4, 15, 1),     # W = 132: 3 strips, the last one ragged
+    (5, 40, 16, 4, 17, 2),    # five bands: two waves of a workgroup idle
+    (2, 64, 64, 4, 9, 1),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_sweep_apply_matches_oracle(sweep_ctx, torch_dev, shape):
+    N, h, w, c, n, r = shape
+    rng = np.random.default_rng(np.random.SeedSequence([61, *shape]))
+    X, Y, u, P = scenes.random_problem(rng, N, h * c, w * c, c, n)
+    lam, eps = 0.05, 1e-3
+    got = sweep_ctx.apply_A(dev(torch_dev, P), dev(torch_dev, Y), dev(torch_dev, u), c=c, r=r, lam=lam, eps=eps)
+    prob = Problem(u=u, c=c, Y=Y, r=r, lam=f32(lam), eps=f32(eps))
+    err = rel_l2(host(got), oracle.apply_A(P, prob))
+    assert np.all(err < 1e-5), err
+
+
+@pytest.mark.parametrize("shape", SHAPES[:4])
+def test_sweep_cg_matches_oracle(sweep_ctx, torch_dev, shape):
+    N, h, w, c, n, r = shape
+    rng = np.random.default_rng(np.random.SeedSequence([62, *shape]))
+    X, Y, u, _ = scenes.random_problem(rng, N, h * c, w * c, c, n)
+    lam, eps = 0.05, 1e-2
+    Z, rep, status = sweep_ctx.pansharpen(dev(torch_dev, X), dev(torch_dev, Y), dev(torch_dev, u), r=r, lam=lam,
+                                          eps=eps, max_iters=20, tol=0.0)
+    prob = Problem(u=u, c=c, Y=Y, r=r, lam=f32(lam), eps=f32(eps))
+    want, _ = oracle.cg(prob, oracle.rhs(X, prob), max_iters=20)
+    assert np.all(rel_l2(host(Z), want) < 1e-5)
+
+
+def test_sweep_parity_scene_50_iterations(torch_dev):
+    """The 256^2 x 4 parity scene after exactly 50 iterations, on the split kernels."""
+    sc, st = scenes.config_scene(0, 0)
+    prob = Problem(u=sc.u, c=sc.c, Y=sc.Y, r=st.r, lam=f32(st.lam), eps=f32(st.eps))
+    with make_ctx(64) as ctx:
+        Z, rep, status = ctx.pansharpen(dev(torch_dev, sc.X), dev(torch_dev, sc.Y), dev(torch_dev, sc.u), r=st.r,
+                                        lam=st.lam, eps=st.eps, max_iters=50, tol=0.0)
+    want, _ = oracle.cg(prob, oracle.rhs(sc.X, prob), max_iters=50)
+    assert status == B.OK and np.all(rel_l2(host(Z), want) < 1e-5)
+
+
+def test_sweep_batch_matches_single(torch_dev):
+    host_sc = [scenes.config_scene(2, s, side=side)[0] for s, side in enumerate([96, 128, 160, 104])]
+    ds = [tuple(dev(torch_dev, a) for a in (sc.X, sc.Y, sc.u)) for sc in host_sc]
+    kw = dict(r=1, lam=1e-2, eps=1e-3, max_iters=300, tol=1e-6)
+    with make_ctx(32) as ctx:
+        outs, reps, _ = ctx.pansharpen_batch(ds, **kw)
+        for (X, Y, u), Z, rs in zip(ds, outs, reps):
+            Zs, rs_s, _ = ctx.pansharpen(X, Y, u, **kw)
+            assert torch_dev.equal(Z, Zs) and rs == rs_s

@@ -46,7 +46,7 @@ def test_autotune_choice_and_parity(torch_dev, scene, tmp_path):
         assert ctx.tune_count() == 0
         res = ctx.autotune(X, Y, u, r=st.r, lam=st.lam, eps=st.eps, iters=6)
         assert res["candidates"] >= 1 and res["fast"] == 1
-        assert res["dir_rows"] in (4, 8) and res["apply_variant"] in (0, 1)
+        assert res["dir_rows"] in (4, 8) and res["apply_variant"] in (0, 1, 2) and res["seg_rows"] >= 32
         assert 0 < res["us_per_iter"] <= res["default_us_per_iter"]
         assert ctx.tune_count() == 1
         Z, rep, _ = ctx.pansharpen(X, Y, u, r=st.r, lam=st.lam, eps=st.eps, max_iters=40, tol=0.0)
