@@ -31,9 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_8x2048.json")
 
 
-def measured_traffic(kernel_prefix):
-    """HBM bytes per launch of the kernel from the committed counter record, or None if the kernel sources have
-    changed since the counters were taken (or there is no record for it)."""
+def measured_traffic(prefixes):
+    """HBM bytes per launch of the kernels whose names start with one of `prefixes` (summed: the operator step
+    may be two launches) from the committed counter record, or None if the kernel sources have changed since
+    the counters were taken (or there is no record for them)."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_RECORD))
@@ -42,12 +43,14 @@ def measured_traffic(kernel_prefix):
             h.update(open(os.path.join(ROOT, f), "rb").read())
         if h.hexdigest()[:16] != rec["source_hash"]:
             return None
+        total, found = 0.0, False
         for name, v in rec["kernels"].items():
-            if name.startswith(kernel_prefix):
-                return v["traffic_bytes"]
+            if any(name.startswith(p) for p in prefixes):
+                total += v["traffic_bytes"]
+                found = True
+        return total if found else None
     except (OSError, KeyError, ValueError):
         return None
-    return None
 
 
 def parse():
@@ -369,10 +372,11 @@ def main():
     # counter-measured HBM bytes per launch (8 x 2048^2 workload, all bands active) for the specialised kernels
     traffic = None
     if args.side is None:
-        traffic = measured_traffic("llp::k_apply_fast<4, 8, 2, 16, 64, 1>" if dominant == "k_apply"
-                                   else "llp::k_dir_fast<4, 8, 4, 2>")
+        traffic = measured_traffic(("llp::k_data<4, 8>", "llp::k_llp<2, 1>") if dominant == "k_apply"
+                                   else ("llp::k_dir_fast<4, 8, 4, 2>",))
     dom = {
-        "k_apply": dict(kernel="k_apply (q = A p: B^T D^T y + lambda L^T M L p; p^T q, r^T q, q^T q)",
+        "k_apply": dict(kernel="k_apply (q = A p: k_data B^T D^T y, then k_llp + lambda L^T M L p; p^T q, r^T q, "
+                               "q^T q)",
                         achieved=apply_gbs, ms=kt["apply_ms"], n=launches),
         "k_dir": dict(kernel="k_dir (x, r update; p = r + beta p; y = D B p; r^T r)", achieved=dir_gbs,
                       ms=kt["dir_ms"], n=kt["dir_launches"]),
