@@ -72,8 +72,8 @@ llp_status ensure_batch_mirrors(llp_ctx* ctx, int bands, int scenes) {
 // Enqueues `count` CG iterations of every class; the first reads the buffers of `parity`.  With `prof` set,
 // every class launch is bracketed by timing events of that context.
 llp_status enqueue_batch_iters(const std::vector<BatchClass>& classes, const SceneDesc* d_table, int nscenes,
-                               int nbands, ChanState* st, int count, int parity, int max_iters, float tol,
-                               hipStream_t s, llp_ctx* prof) {
+                               int nbands, ChanState* st, char* ws, const float* taps, int count, int parity,
+                               int max_iters, float tol, hipStream_t s, llp_ctx* prof) {
   std::vector<hipEvent_t> ev(prof ? 4 * classes.size() : 0);
   for (int j = 0; j < count; ++j) {
     const int par = (parity + j) & 1;
@@ -84,20 +84,21 @@ llp_status enqueue_batch_iters(const std::vector<BatchClass>& classes, const Sce
       if (prof) HIP_TRY(hipEventRecord(ev[4 * c], s));
       if (k.variant == kSweepVariant)
         HIP_TRY(launch_apply_sweep_batch(d_table + k.first, k.count, k.data_blocks, k.apply_blocks, k.C, k.R, k.r,
-                                         par, st, s));
+                                         par, st, ws, taps, s));
       else
         HIP_TRY(launch_apply_fast_batch(d_table + k.first, k.count, k.apply_blocks, k.C, k.R, k.r, k.variant, par,
-                                        st, s));
+                                        st, ws, taps, s));
       if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 1], s));
     }
-    HIP_TRY(launch_finalize_batch(kFinApply, d_table, nscenes, nbands, st, max_iters, tol, s));
+    HIP_TRY(launch_finalize_batch(kFinApply, d_table, nscenes, nbands, st, ws, max_iters, tol, s));
     for (size_t c = 0; c < classes.size(); ++c) {
       const BatchClass& k = classes[c];
       if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 2], s));
-      HIP_TRY(launch_dir_fast_batch(d_table + k.first, k.count, k.dir_blocks, k.C, k.R, k.dir_rows, par, st, s));
+      HIP_TRY(launch_dir_fast_batch(d_table + k.first, k.count, k.dir_blocks, k.C, k.R, k.dir_rows, par, st, ws,
+                                    taps, s));
       if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 3], s));
     }
-    HIP_TRY(launch_finalize_batch(kFinDir, d_table, nscenes, nbands, st, max_iters, tol, s));
+    HIP_TRY(launch_finalize_batch(kFinDir, d_table, nscenes, nbands, st, ws, max_iters, tol, s));
   }
   return LLP_OK;
 }
@@ -179,7 +180,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       const Geom& g = fast[i].g;
       const size_t HW = (size_t)g.H * g.W;
       o_pl[i] = off;
-      off = align_up(off + (7 * HW + 6 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w) * sizeof(float), 256);
+      // the statistics (7 planes), b, r (2), p (2), q, the iterate x, and y
+      off = align_up(off + (7 * HW + 7 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w) * sizeof(float), 256);
       o_part[i] = off;
       off = align_up(off + (size_t)g.N * max_partials_per_band(g) * 3 * sizeof(double), 256);
       nbands += g.N;
@@ -192,6 +194,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     off = align_up(off + (size_t)nf * sizeof(int), 256);
     const size_t o_table = off;
     off = align_up(off + (size_t)nf * sizeof(SceneDesc), 256);
+    const size_t o_taps = off;
+    off = align_up(off + (size_t)nf * kTapStride * sizeof(float), 256);
     if (off > ctx->bws_bytes) {
       if (ctx->bws) {
         HIP_TRY(hipStreamSynchronize(s));
@@ -217,6 +221,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     double* results = (double*)(base + o_res);
     int* bflags = (int*)(base + o_flags);
     SceneDesc* d_table = (SceneDesc*)(base + o_table);
+    float* d_taps = (float*)(base + o_taps);
     SceneDesc* tab = ctx->h_table;
     std::vector<BatchClass> classes;
     int band = 0;
@@ -230,7 +235,6 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       d.X = lrms[bs.idx];
       d.Y = pan[bs.idx];
       d.u = kernel[bs.idx];
-      d.x = hrms[bs.idx];
       float* pl = (float*)(base + o_pl[i]);
       d.GMD = (float4*)pl;
       d.G = pl + 4 * HW;
@@ -242,8 +246,23 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       d.p[0] = d.r[1] + NHW;
       d.p[1] = d.p[0] + NHW;
       d.q = d.p[1] + NHW;
-      d.y = d.q + NHW;
+      d.x = d.q + NHW;  // the iterate lives in the workspace during the solve; copied to hrms at the end
+      d.y = d.x + NHW;
       d.partials = (double*)(base + o_part[i]);
+      auto rel = [base](const void* ptr) { return (size_t)((const char*)ptr - base); };
+      d.o_x = rel(d.x);
+      d.o_r[0] = rel(d.r[0]);
+      d.o_r[1] = rel(d.r[1]);
+      d.o_p[0] = rel(d.p[0]);
+      d.o_p[1] = rel(d.p[1]);
+      d.o_q = rel(d.q);
+      d.o_y = rel(d.y);
+      d.o_G = rel(d.G);
+      d.o_MU = rel(d.MU);
+      d.o_DI = rel(d.DI);
+      d.o_GMD = rel(d.GMD);
+      d.o_partials = rel(d.partials);
+      d.taps_index = i;
       d.pstride = (int)max_partials_per_band(g);
       d.band0 = band;
       d.dir_ntiles = dir_ntiles(g, bs.cfg);
@@ -279,6 +298,9 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       k.count += 1;
     }
     HIP_TRY(hipMemcpyAsync(d_table, tab, sizeof(SceneDesc) * nf, hipMemcpyHostToDevice, s));
+    for (int i = 0; i < nf; ++i)
+      HIP_TRY(hipMemcpyAsync(d_taps + (size_t)i * kTapStride, tab[i].u, sizeof(float) * tab[i].g.n * tab[i].g.n,
+                             hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemsetAsync(bflags, 0, sizeof(int) * nf, s));
     // Per scene: input checks, PAN statistics, right-hand side, start of CG (x_0, r_0, p_0, rho_0).
     for (int i = 0; i < nf; ++i) {
@@ -339,8 +361,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         }
         for (const BatchClass& k : classes) {  // LDS limits are set outside the capture
           if (k.variant != kSweepVariant)
-            HIP_TRY(launch_apply_fast_batch(d_table, k.count, 0, k.C, k.R, k.r, k.variant, 0, st, s));
-          HIP_TRY(launch_dir_fast_batch(d_table, k.count, 0, k.C, k.R, k.dir_rows, 0, st, s));
+            HIP_TRY(launch_apply_fast_batch(d_table, k.count, 0, k.C, k.R, k.r, k.variant, 0, st, base, d_taps, s));
+          HIP_TRY(launch_dir_fast_batch(d_table, k.count, 0, k.C, k.R, k.dir_rows, 0, st, base, d_taps, s));
         }
         hipStream_t cs = nullptr;
         HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -348,7 +370,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         llp_status cv = LLP_OK;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) cv = LLP_E_HIP;
         if (cv == LLP_OK)
-          cv = enqueue_batch_iters(classes, d_table, nf, nbands, st, kCheckEvery, 0, max_iters, tol, cs, nullptr);
+          cv = enqueue_batch_iters(classes, d_table, nf, nbands, st, base, d_taps, kCheckEvery, 0, max_iters, tol, cs,
+                                   nullptr);
         if (hipStreamEndCapture(cs, &graph) != hipSuccess && cv == LLP_OK) cv = LLP_E_HIP;
         (void)hipStreamDestroy(cs);
         if (cv == LLP_OK && hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -364,7 +387,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     for (int k = 1; k <= max_iters; k += kCheckEvery) {
       if (use_graph) HIP_TRY(hipGraphLaunch(ctx->gexec, s));
       else {
-        v = enqueue_batch_iters(classes, d_table, nf, nbands, st, kCheckEvery, 0, max_iters, tol, s, prof);
+        v = enqueue_batch_iters(classes, d_table, nf, nbands, st, base, d_taps, kCheckEvery, 0, max_iters, tol, s,
+                                prof);
         if (v != LLP_OK) return v;
       }
       if (!tol_mode) continue;
@@ -399,6 +423,9 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     }
     HIP_TRY(hipMemcpyAsync(ctx->h_bst[0], st, sizeof(ChanState) * nbands, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(ctx->h_bflags, bflags, sizeof(int) * nf, hipMemcpyDeviceToHost, s));
+    for (int i = 0; i < nf; ++i)  // the iterates to the caller's HRMS buffers
+      HIP_TRY(hipMemcpyAsync(hrms[fast[i].idx], tab[i].x, sizeof(float) * tab[i].g.N * tab[i].g.H * tab[i].g.W,
+                             hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (prof) {
       v = collect_times(ctx);

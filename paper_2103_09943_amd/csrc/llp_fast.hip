@@ -576,51 +576,53 @@ __device__ __forceinline__ int find_scene(const SceneDesc* __restrict__ t, int c
 // Batched CG iteration kernels (mode 2 / mode 1 of the single-scene kernels) over a table of scenes.
 template <int C, int R, int TYL>
 __global__ __launch_bounds__(kBlock) void k_dir_fast_batch(const SceneDesc* __restrict__ t, int count, int parity,
-                                                           ChanState* __restrict__ st) {
+                                                           ChanState* __restrict__ st, char* __restrict__ ws,
+                                                           const float* __restrict__ taps) {
   const int si = find_scene<true>(t, count, blockIdx.x);
   const SceneDesc& d = t[si];
   const int local = blockIdx.x - d.dir_block0;  // scenes start on multiples of 8 workgroups (one per XCD)
   if (local >= d.dir_ntiles * d.g.N) return;
   DirArgs A{};
   A.mode = 2;
-  A.rin = d.r[parity];
-  A.qin = d.q;
-  A.pin = d.p[parity];
-  A.rout = d.r[1 - parity];
-  A.pout = d.p[1 - parity];
-  A.x = d.x;
-  A.y = d.y;
-  A.partials = d.partials;
+  A.rin = (const float*)(ws + d.o_r[parity]);
+  A.qin = (const float*)(ws + d.o_q);
+  A.pin = (const float*)(ws + d.o_p[parity]);
+  A.rout = (float*)(ws + d.o_r[1 - parity]);
+  A.pout = (float*)(ws + d.o_p[1 - parity]);
+  A.x = (float*)(ws + d.o_x);
+  A.y = (float*)(ws + d.o_y);
+  A.partials = (double*)(ws + d.o_partials);
   A.st = st + d.band0;
   A.pstride = d.pstride;
   A.tiles_x = (d.g.w + DirShape<C, R, TYL>::TXL - 1) / DirShape<C, R, TYL>::TXL;
   A.ntiles = d.dir_ntiles;
   A.PS = DirShape<C, R, TYL>::PS;
-  dir_fast_body<C, R, TYL, 2>(d.g, A, d.u, local);
+  dir_fast_body<C, R, TYL, 2>(d.g, A, taps + (size_t)d.taps_index * kTapStride, local);
 }
 
 template <int C, int R, int r, int TH, int TW>
 __global__ __launch_bounds__(kBlock) void k_apply_fast_batch(const SceneDesc* __restrict__ t, int count, int parity,
-                                                             ChanState* __restrict__ st) {
+                                                             ChanState* __restrict__ st, char* __restrict__ ws,
+                                                             const float* __restrict__ taps) {
   const int si = find_scene<false>(t, count, blockIdx.x);
   const SceneDesc& d = t[si];
   const int local = blockIdx.x - d.apply_block0;
   if (local >= d.apply_ntiles * d.g.N) return;
   ApplyArgs A{};
   A.mode = 1;
-  A.p = d.p[parity];
-  A.r = d.r[parity];
-  A.y = d.y;
-  A.G = d.G;
-  A.MU = d.MU;
-  A.DI = d.DI;
-  A.q = d.q;
-  A.partials = d.partials;
+  A.p = (const float*)(ws + d.o_p[parity]);
+  A.r = (const float*)(ws + d.o_r[parity]);
+  A.y = (const float*)(ws + d.o_y);
+  A.G = (const float*)(ws + d.o_G);
+  A.MU = (const float*)(ws + d.o_MU);
+  A.DI = (const float*)(ws + d.o_DI);
+  A.q = (float*)(ws + d.o_q);
+  A.partials = (double*)(ws + d.o_partials);
   A.st = st + d.band0;
   A.pstride = d.pstride;
   A.tiles_x = (d.g.W + TW - 1) / TW;
   A.ntiles = d.apply_ntiles;
-  apply_fast_body<C, R, r, TH, TW, 1>(d.g, A, d.u, local);
+  apply_fast_body<C, R, r, TH, TW, 1>(d.g, A, taps + (size_t)d.taps_index * kTapStride, local);
 }
 
 // ===================================================================================== dispatch ===
@@ -744,34 +746,37 @@ hipError_t launch_apply_fast(const Geom& g, int variant, ApplyArgs A, const floa
 namespace {
 
 template <int C, int R, int TYL>
-hipError_t run_dir_batch(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, hipStream_t s) {
+hipError_t run_dir_batch(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, char* ws,
+                         const float* taps, hipStream_t s) {
   const size_t bytes = (size_t)DirShape<C, R, TYL>::LDS * sizeof(float);
   hipError_t e = set_lds_fast(k_dir_fast_batch<C, R, TYL>, bytes);
   if (e != hipSuccess) return e;
   if (blocks == 0) return hipSuccess;  // prepare only (before a graph capture)
-  hipLaunchKernelGGL((k_dir_fast_batch<C, R, TYL>), dim3(blocks), dim3(kBlock), bytes, s, t, count, parity, st);
+  hipLaunchKernelGGL((k_dir_fast_batch<C, R, TYL>), dim3(blocks), dim3(kBlock), bytes, s, t, count, parity, st, ws,
+                     taps);
   return hipGetLastError();
 }
 
 template <int C, int R, int r, int TH, int TW>
-hipError_t run_apply_batch(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, hipStream_t s) {
+hipError_t run_apply_batch(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, char* ws,
+                           const float* taps, hipStream_t s) {
   const size_t bytes = (size_t)ApplyShape<C, R, r, TH, TW>::total * sizeof(float);
   hipError_t e = set_lds_fast(k_apply_fast_batch<C, R, r, TH, TW>, bytes);
   if (e != hipSuccess) return e;
   if (blocks == 0) return hipSuccess;  // prepare only (before a graph capture)
   hipLaunchKernelGGL((k_apply_fast_batch<C, R, r, TH, TW>), dim3(blocks), dim3(kBlock), bytes, s, t, count, parity,
-                     st);
+                     st, ws, taps);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_dir_fast_batch(const SceneDesc* table, int count, int total_blocks, int C, int R, int tyl,
-                                 int parity, ChanState* st, hipStream_t s) {
+                                 int parity, ChanState* st, char* ws, const float* taps, hipStream_t s) {
 #define LLP_DIRB_CASE(CC, RR, rr)                                                                     \
   if (C == CC && R == RR)                                                                             \
-    return tyl == 8 ? run_dir_batch<CC, RR, 8>(table, count, total_blocks, parity, st, s)             \
-                    : run_dir_batch<CC, RR, 4>(table, count, total_blocks, parity, st, s);
+    return tyl == 8 ? run_dir_batch<CC, RR, 8>(table, count, total_blocks, parity, st, ws, taps, s) \
+                    : run_dir_batch<CC, RR, 4>(table, count, total_blocks, parity, st, ws, taps, s);
   LLP_FAST_R_LIST2(LLP_DIRB_CASE, 0)
   LLP_FAST_R_LIST4(LLP_DIRB_CASE, 0)
 #undef LLP_DIRB_CASE
@@ -779,11 +784,13 @@ hipError_t launch_dir_fast_batch(const SceneDesc* table, int count, int total_bl
 }
 
 hipError_t launch_apply_fast_batch(const SceneDesc* table, int count, int total_blocks, int C, int R, int r,
-                                   int variant, int parity, ChanState* st, hipStream_t s) {
+                                   int variant, int parity, ChanState* st, char* ws, const float* taps,
+                                   hipStream_t s) {
 #define LLP_APPLYB_CASE(CC, RR, rr)                                                                   \
   if (C == CC && R == RR && r == rr)                                                                  \
-    return variant == 0 ? run_apply_batch<CC, RR, rr, 32, 64>(table, count, total_blocks, parity, st, s) \
-                        : run_apply_batch<CC, RR, rr, 16, 64>(table, count, total_blocks, parity, st, s);
+    return variant == 0                                                                                 \
+               ? run_apply_batch<CC, RR, rr, 32, 64>(table, count, total_blocks, parity, st, ws, taps, s)   \
+               : run_apply_batch<CC, RR, rr, 16, 64>(table, count, total_blocks, parity, st, ws, taps, s);
   LLP_FAST_R_LIST2(LLP_APPLYB_CASE, 1)
   LLP_FAST_R_LIST2(LLP_APPLYB_CASE, 2)
   LLP_FAST_R_LIST4(LLP_APPLYB_CASE, 1)

@@ -113,7 +113,12 @@ struct SceneDesc {
   int dir_block0, apply_block0;  // first workgroup of the scene in its class's k_dir / k_apply launch
   int data_block0;               // split variant: first workgroup of the scene in its class's k_data launch
   int seg_rows;                  // split variant: rows per sweep segment
+  // The same device buffers as byte offsets from the batch workspace base: the batched kernels form their
+  // pointers from the workspace base (a kernel argument, hence known to be global memory) and these offsets.
+  size_t o_x, o_r[2], o_p[2], o_q, o_y, o_G, o_MU, o_DI, o_GMD, o_partials;
+  int taps_index;                // the scene's kernel taps: taps table + taps_index * kTapStride
 };
+constexpr int kTapStride = 1024;  // floats per scene in the batch's kernel-tap table (n <= 31)
 
 // Split variant of q = A p (llp_sweep.hip): q_D = B^T D^T y (k_data), then q = q_D + lambda L^T M L p and, in
 // mode 1, the dot products (k_llp); apply_ntiles() partials per band.
@@ -125,19 +130,21 @@ hipError_t launch_apply_sweep(const Geom& g, int seg_rows, int mode, const float
                               const float* y, const float* u, const float4* gmd, float* q, double* partials,
                               ChanState* st, hipStream_t s);
 hipError_t launch_apply_sweep_batch(const SceneDesc* table, int count, int data_blocks, int llp_blocks, int C,
-                                    int R, int r, int parity, ChanState* st, hipStream_t s);
+                                    int R, int r, int parity, ChanState* st, char* ws, const float* taps,
+                                    hipStream_t s);
 
 // k_finalize (kFinDir / kFinApply) for all `bands` bands of the `count` scenes of a table; kFinDir advances each
 // active band's iteration count on the device.
 hipError_t launch_finalize_batch(int op, const SceneDesc* table, int count, int bands, ChanState* st,
-                                 int max_iters, float tol, hipStream_t s);
+                                 const char* ws, int max_iters, float tol, hipStream_t s);
 // Batched CG launches over the scenes [first, first+count) of a class table (all of one (c, R, r) class and one
 // launch configuration): every workgroup finds its scene by binary search on the block offsets.  parity selects
 // the residual/direction buffers: iteration k reads r[parity], p[parity] and writes r[1-parity], p[1-parity].
 // total_blocks == 0 only prepares the kernel (its LDS limit) without launching it.
 hipError_t launch_dir_fast_batch(const SceneDesc* table, int count, int total_blocks, int C, int R, int tyl,
-                                 int parity, ChanState* st, hipStream_t s);
+                                 int parity, ChanState* st, char* ws, const float* taps, hipStream_t s);
 hipError_t launch_apply_fast_batch(const SceneDesc* table, int count, int total_blocks, int C, int R, int r,
-                                   int variant, int parity, ChanState* st, hipStream_t s);
+                                   int variant, int parity, ChanState* st, char* ws, const float* taps,
+                                   hipStream_t s);
 
 }  // namespace llp

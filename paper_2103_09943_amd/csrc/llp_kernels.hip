@@ -143,7 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int op, const double* __res
 // Batched finalisation (kFinDir / kFinApply) over every band of a scene table; one workgroup per band.  The
 // iteration index lives on the device: kFinDir advances a band from x_{k-1} to x_k.
 __global__ __launch_bounds__(kBlock) void k_finalize_batch(int op, const SceneDesc* __restrict__ t, int count,
-                                                           ChanState* __restrict__ st, int max_iters, float tol) {
+                                                           ChanState* __restrict__ st, const char* __restrict__ ws,
+                                                           int max_iters, float tol) {
   __shared__ double red[3 * kWaves];
   const int band = blockIdx.x;
   if (!st[band].active) return;
@@ -157,15 +158,16 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(int op, const SceneDe
   const int ch = band - d.band0;
   const int nblk = op == kFinApply ? d.apply_ntiles : d.dir_ntiles;
   double s[3];
-  sum_partials(d.partials + (size_t)ch * d.pstride * 3, nblk, op == kFinApply ? 3 : 1, s, red);
+  sum_partials((const double*)(ws + d.o_partials) + (size_t)ch * d.pstride * 3, nblk, op == kFinApply ? 3 : 1, s,
+               red);
   if (threadIdx.x != 0) return;
   ChanState& c = st[band];
   finish_band(op, s, c, c.iters + 1, max_iters, tol);
 }
 
 hipError_t launch_finalize_batch(int op, const SceneDesc* table, int count, int bands, ChanState* st,
-                                 int max_iters, float tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_batch, dim3(bands), dim3(kBlock), 0, s, op, table, count, st, max_iters, tol);
+                                 const char* ws, int max_iters, float tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_batch, dim3(bands), dim3(kBlock), 0, s, op, table, count, st, ws, max_iters, tol);
   return hipGetLastError();
 }
 

@@ -273,7 +273,8 @@ __device__ __forceinline__ int find_scene_split(const SceneDesc* __restrict__ t,
 
 template <int C, int R>
 __global__ __launch_bounds__(kBlock) void k_data_batch(const SceneDesc* __restrict__ t, int count,
-                                                       const ChanState* __restrict__ st) {
+                                                       const ChanState* __restrict__ st, char* __restrict__ ws,
+                                                       const float* __restrict__ taps) {
   const int si = find_scene_split<true>(t, count, blockIdx.x);
   const SceneDesc& d = t[si];
   const int local = blockIdx.x - d.data_block0;
@@ -281,12 +282,13 @@ __global__ __launch_bounds__(kBlock) void k_data_batch(const SceneDesc* __restri
   if (local >= bx_n * by_n * d.g.N) return;
   const int band = local / (bx_n * by_n), rem = local % (bx_n * by_n);
   if (!st[d.band0 + band].active) return;
-  data_body<C, R>(d.g, d.y, d.u, d.q, rem % bx_n, rem / bx_n, band);
+  data_body<C, R>(d.g, (const float*)(ws + d.o_y), taps + (size_t)d.taps_index * kTapStride,
+                  (float*)(ws + d.o_q), rem % bx_n, rem / bx_n, band);
 }
 
 template <int r>
 __global__ __launch_bounds__(kBlock) void k_llp_batch(const SceneDesc* __restrict__ t, int count, int parity,
-                                                      ChanState* __restrict__ st) {
+                                                      ChanState* __restrict__ st, char* __restrict__ ws) {
   const int si = find_scene_split<false>(t, count, blockIdx.x);
   const SceneDesc& d = t[si];
   const int local = blockIdx.x - d.apply_block0;
@@ -295,11 +297,11 @@ __global__ __launch_bounds__(kBlock) void k_llp_batch(const SceneDesc* __restric
   if (local >= d.apply_ntiles * ((d.g.N + 3) / 4)) return;
   SweepArgs A{};
   A.mode = 1;
-  A.p = d.p[parity];
-  A.r = d.r[parity];
-  A.GMD = d.GMD;
-  A.q = d.q;
-  A.partials = d.partials;
+  A.p = (const float*)(ws + d.o_p[parity]);
+  A.r = (const float*)(ws + d.o_r[parity]);
+  A.GMD = (const float4*)(ws + d.o_GMD);
+  A.q = (float*)(ws + d.o_q);
+  A.partials = (double*)(ws + d.o_partials);
   A.st = st + d.band0;
   A.pstride = d.pstride;
   A.nstrips = nstrips;
@@ -381,28 +383,31 @@ hipError_t launch_apply_sweep(const Geom& g, int seg_rows, int mode, const float
 namespace {
 
 template <int C, int R>
-hipError_t run_data_batch(const SceneDesc* table, int count, int blocks, const ChanState* st, hipStream_t s) {
-  hipLaunchKernelGGL((k_data_batch<C, R>), dim3(blocks), dim3(kBlock), 0, s, table, count, st);
+hipError_t run_data_batch(const SceneDesc* table, int count, int blocks, const ChanState* st, char* ws,
+                          const float* taps, hipStream_t s) {
+  hipLaunchKernelGGL((k_data_batch<C, R>), dim3(blocks), dim3(kBlock), 0, s, table, count, st, ws, taps);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_apply_sweep_batch(const SceneDesc* table, int count, int data_blocks, int llp_blocks, int C,
-                                    int R, int r, int parity, ChanState* st, hipStream_t s) {
+                                    int R, int r, int parity, ChanState* st, char* ws, const float* taps,
+                                    hipStream_t s) {
   if (data_blocks > 0) {
     hipError_t e = hipErrorInvalidValue;
 #define LLP_DATAB_CASE(CC, RR, rr) \
-  if (C == CC && R == RR) e = run_data_batch<CC, RR>(table, count, data_blocks, st, s);
+  if (C == CC && R == RR) e = run_data_batch<CC, RR>(table, count, data_blocks, st, ws, taps, s);
     LLP_FAST_R_LIST2(LLP_DATAB_CASE, 0)
     LLP_FAST_R_LIST4(LLP_DATAB_CASE, 0)
 #undef LLP_DATAB_CASE
     if (e != hipSuccess) return e;
   }
   if (llp_blocks > 0) {
-    if (r == 1) hipLaunchKernelGGL((k_llp_batch<1>), dim3(llp_blocks), dim3(kBlock), 0, s, table, count, parity, st);
+    if (r == 1)
+      hipLaunchKernelGGL((k_llp_batch<1>), dim3(llp_blocks), dim3(kBlock), 0, s, table, count, parity, st, ws);
     else if (r == 2)
-      hipLaunchKernelGGL((k_llp_batch<2>), dim3(llp_blocks), dim3(kBlock), 0, s, table, count, parity, st);
+      hipLaunchKernelGGL((k_llp_batch<2>), dim3(llp_blocks), dim3(kBlock), 0, s, table, count, parity, st, ws);
     else return hipErrorInvalidValue;
   }
   return hipGetLastError();
