@@ -22,8 +22,11 @@ int cnn_wgrad_parts();           // maximum workgroups (partial sums) of a weigh
 size_t cnn_wgrad_part_floats();
 size_t cnn_loss_parts(const CnnGeom& g);
 
-// Mean and std (1 where 0) of `count` arrays: out[2k], out[2k+1].
-hipError_t cnn_launch_stats(const float* src, size_t stride, size_t len, int count, float* out, hipStream_t s);
+// Mean and std (1 where 0) of `count` arrays: out[2k], out[2k+1]; part: count * cnn_stats_parts(len) * 2
+// doubles of scratch.
+size_t cnn_stats_parts(size_t len);
+hipError_t cnn_launch_stats(const float* src, size_t stride, size_t len, int count, double* part, float* out,
+                            hipStream_t s);
 // x_up and the padded 32-channel bfloat16 input planes; stats: per band (m, s), statsY: (m_Y, s_Y).
 hipError_t cnn_launch_input(const CnnGeom& g, const float* X, const float* Y, const float* stats,
                             const float* statsY, float* xup, uint16_t* in0, hipStream_t s);

@@ -46,17 +46,34 @@ __device__ __forceinline__ uint32_t pack2(float a, float b) { return (uint32_t)f
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // ------------------------------------------------------------------------------------- band statistics ---
-// Mean and population standard deviation (1 where it is 0) of each of `count` arrays of `len` floats,
-// array k at src + k * stride.  One workgroup per array; FP64 sums in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_stats(const float* __restrict__ src, size_t stride, size_t len,
-                                                  float* __restrict__ out) {
+// Mean and population standard deviation (1 where it is 0) of each of `count` arrays of `len` floats, array k
+// at src + k * stride.  Two steps, deterministic: every workgroup sums a chunk in FP64 (part[k][chunk][2]),
+// then one workgroup per array adds the chunks in order.
+constexpr int kStatChunk = kBlock * 16;
+
+__global__ __launch_bounds__(kBlock) void k_stats_part(const float* __restrict__ src, size_t stride, size_t len,
+                                                       int nchunk, double* __restrict__ part) {
   __shared__ double red[2 * kWaves];
-  const float* a = src + (size_t)blockIdx.x * stride;
+  const float* a = src + (size_t)blockIdx.y * stride;
+  const size_t e0 = (size_t)blockIdx.x * kStatChunk;
+  const size_t e1 = e0 + kStatChunk < len ? e0 + kStatChunk : len;
   double s[2] = {0.0, 0.0};
-  for (size_t i = threadIdx.x; i < len; i += kBlock) {
+  for (size_t i = e0 + threadIdx.x; i < e1; i += kBlock) {
     const double v = a[i];
     s[0] += v;
     s[1] += v * v;
+  }
+  block_partials<2>(s, red, part + ((size_t)blockIdx.y * nchunk + blockIdx.x) * 2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_stats_final(const double* __restrict__ part, int nchunk, size_t len,
+                                                        float* __restrict__ out) {
+  __shared__ double red[2 * kWaves];
+  const double* p = part + (size_t)blockIdx.x * nchunk * 2;
+  double s[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < nchunk; i += kBlock) {
+    s[0] += p[2 * i];
+    s[1] += p[2 * i + 1];
   }
   block_sums<2>(s, red);
   if (threadIdx.x == 0) {
@@ -134,24 +151,32 @@ __global__ __launch_bounds__(kBlock) void k_conv(CnnGeom g, const uint16_t* __re
                                                  uint16_t* __restrict__ out, const uint16_t* __restrict__ mask,
                                                  float* __restrict__ netout, float* __restrict__ z0,
                                                  const float* __restrict__ xup, const float* __restrict__ stats) {
+  // The workgroup's input tile (its 4 rows and 64 columns plus a 1-pixel periodic halo, all 32 channels) is
+  // staged in LDS once; the 9 taps of the 4 waves then read their MFMA B operands from there.
+  __shared__ __align__(16) uint16_t tile[kTileRows + 2][kTileW + 2][kCh];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = blockIdx.y * kTileRows + wave;
+  const int row0 = blockIdx.y * kTileRows, row = row0 + wave;
   const int band = blockIdx.z;
-  if (row >= g.H) return;  // no barriers in this kernel
   const int H = g.H, W = g.W;
   const size_t HW = (size_t)H * W;
   const int col0 = blockIdx.x * kTileW;
   const int kq = lane >> 4, n16 = lane & 15;
   const uint16_t* inb = in + (size_t)band * HW * kCh;
+  for (int k = threadIdx.x; k < (kTileRows + 2) * (kTileW + 2) * 4; k += kBlock) {
+    const int pix = k >> 2, part = k & 3;
+    const int lr = pix / (kTileW + 2), lc = pix % (kTileW + 2);
+    const int sr = pos_mod(row0 + lr - 1, H), sc = pos_mod(col0 + lc - 1, W);
+    *(u32x4*)&tile[lr][lc][part * 8] = *(const u32x4*)(inb + ((size_t)sr * W + sc) * kCh + part * 8);
+  }
+  __syncthreads();
+  if (row >= H) return;  // the only barrier is behind
   f32x4 acc[COB][4];
 #pragma unroll
   for (int cb = 0; cb < COB; ++cb)
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[cb][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
+#pragma unroll
   for (int dy = 0; dy < 3; ++dy) {
-    const int sr = wrapc(row + dy - 1, H);
-    const uint16_t* rowp = inb + (size_t)sr * W * kCh + kq * 8;
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
       const int tap = dy * 3 + dx;
@@ -160,11 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_conv(CnnGeom g, const uint16_t* __re
       for (int cb = 0; cb < COB; ++cb) a[cb] = __builtin_bit_cast(bf16x8, wt[(tap * COB + cb) * 64 + lane]);
       bf16x8 b[4];
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        // in range for every stored column; columns past the image (not stored) only need an in-bounds load
-        const int sc = min(wrapc(col0 + nb * 16 + n16 + dx - 1, W), W - 1);
-        b[nb] = __builtin_bit_cast(bf16x8, *(const u32x4*)(rowp + (size_t)sc * kCh));
-      }
+      for (int nb = 0; nb < 4; ++nb)
+        b[nb] = __builtin_bit_cast(bf16x8, *(const u32x4*)&tile[wave + dy][nb * 16 + n16 + dx][kq * 8]);
 #pragma unroll
       for (int cb = 0; cb < COB; ++cb)
 #pragma unroll
@@ -434,8 +456,15 @@ size_t cnn_tile_bytes(int cob) { return (size_t)kTaps * cob * 64 * 16; }
 int cnn_wgrad_parts() { return 512; }
 size_t cnn_wgrad_part_floats() { return kGradPart; }
 
-hipError_t cnn_launch_stats(const float* src, size_t stride, size_t len, int count, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_stats, dim3(count), dim3(kBlock), 0, s, src, stride, len, out);
+size_t cnn_stats_parts(size_t len) { return (len + kStatChunk - 1) / kStatChunk; }
+
+hipError_t cnn_launch_stats(const float* src, size_t stride, size_t len, int count, double* part, float* out,
+                            hipStream_t s) {
+  const int nchunk = (int)cnn_stats_parts(len);
+  hipLaunchKernelGGL(k_stats_part, dim3(nchunk, count), dim3(kBlock), 0, s, src, stride, len, nchunk, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stats_final, dim3(count), dim3(kBlock), 0, s, part, nchunk, len, out);
   return hipGetLastError();
 }
 

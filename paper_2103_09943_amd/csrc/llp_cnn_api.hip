@@ -33,6 +33,7 @@ llp_status prep_all(CnnState* c, hipStream_t s) {
 // Workspace views for `nb` bands of HW pixels; train: all five activations and the gradient buffers.
 struct CnnViews {
   float *stats, *xup, *net;
+  double* spart;  // partial sums of the band statistics
   uint16_t* act[kCnnLayers];
   uint16_t* gbuf[2];
   float* wpart;
@@ -45,6 +46,8 @@ llp_status cnn_workspace(CnnState* c, int N, int nb, size_t HW, bool train, CnnV
   size_t off = 0;
   const size_t o_stats = off;
   off = align_up(off + sizeof(float) * 2 * (N + 1), 256);
+  const size_t o_spart = off;  // chunks of the band statistics: N LRMS bands and the PAN image
+  off = align_up(off + sizeof(double) * 2 * ((size_t)N * cnn_stats_parts(HW / 1) + cnn_stats_parts(HW)), 256);
   const size_t o_xup = off;
   off = align_up(off + sizeof(float) * nb * HW, 256);
   const size_t o_net = off;
@@ -73,6 +76,7 @@ llp_status cnn_workspace(CnnState* c, int N, int nb, size_t HW, bool train, CnnV
   }
   char* base = (char*)c->ws;
   v->stats = (float*)(base + o_stats);
+  v->spart = (double*)(base + o_spart);
   v->xup = (float*)(base + o_xup);
   v->net = (float*)(base + o_net);
   for (int l = 0; l < kCnnLayers; ++l) v->act[l] = l < nact ? (uint16_t*)(base + o_act + act * l) : nullptr;
@@ -95,8 +99,8 @@ llp_status loss_grad(llp_ctx* ctx, const Geom& g, const float* X, const float* Y
   llp_status st = cnn_workspace(c, g.N, g.N, HW, true, &v);
   if (st != LLP_OK) return st;
   const CnnGeom cg = cnn_geom(g, g.N);
-  HIP_TRY(cnn_launch_stats(X, (size_t)g.h * g.w, (size_t)g.h * g.w, g.N, v.stats, s));
-  HIP_TRY(cnn_launch_stats(Y, 0, HW, 1, v.stats + 2 * g.N, s));
+  HIP_TRY(cnn_launch_stats(X, (size_t)g.h * g.w, (size_t)g.h * g.w, g.N, v.spart, v.stats, s));
+  HIP_TRY(cnn_launch_stats(Y, 0, HW, 1, v.spart, v.stats + 2 * g.N, s));
   HIP_TRY(cnn_launch_input(cg, X, Y, v.stats, v.stats + 2 * g.N, v.xup, v.act[0], s));
   for (int l = 0; l < kCnnLayers - 1; ++l)
     HIP_TRY(cnn_launch_conv(cg, 2, 0, v.act[l], c->fwd[l], bias_of(c, l), v.act[l + 1], nullptr, nullptr, nullptr,
@@ -143,8 +147,8 @@ llp_status cnn_warm_start(llp_ctx* ctx, const Geom& g, const float* X, const flo
   CnnViews v;
   llp_status st = cnn_workspace(c, g.N, (int)nb, HW, false, &v);
   if (st != LLP_OK) return st;
-  HIP_TRY(cnn_launch_stats(X, (size_t)g.h * g.w, (size_t)g.h * g.w, g.N, v.stats, s));
-  HIP_TRY(cnn_launch_stats(Y, 0, HW, 1, v.stats + 2 * g.N, s));
+  HIP_TRY(cnn_launch_stats(X, (size_t)g.h * g.w, (size_t)g.h * g.w, g.N, v.spart, v.stats, s));
+  HIP_TRY(cnn_launch_stats(Y, 0, HW, 1, v.spart, v.stats + 2 * g.N, s));
   for (int b0 = 0; b0 < g.N; b0 += (int)nb) {
     const int n = g.N - b0 < (int)nb ? g.N - b0 : (int)nb;
     const CnnGeom cg = cnn_geom(g, n);
