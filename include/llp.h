@@ -91,8 +91,8 @@ typedef struct llp_ctx llp_ctx;
  * LLP_FORCE_GENERIC is set (and not "0") at creation, the context uses only the generic kernels (no
  * specialisation on kernel size, scale and window radius); results agree to rounding.  LLP_DIR_ROWS (4, 8),
  * LLP_APPLY_VARIANT (0: 32x64 tiles, 1: 16x64 tiles, 2: split data term + column sweep) and LLP_SEG_ROWS
- * (rows per sweep segment, >= 32) force a launch configuration of the specialised kernels instead of the
- * tuned or default one. */
+ * (rows per sweep segment, >= 32, rounded down to a multiple of 4) force a launch configuration of the
+ * specialised kernels instead of the tuned or default one. */
 llp_status llp_create(llp_ctx** out, int device);
 
 /* Release a context and all its workspaces.  NULL is accepted. */

@@ -218,7 +218,7 @@ bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg) {
     }
   }
   if (!pick_config(g, cfg, ctx->allow_fast, ctx->want_dir_rows, ctx->want_apply_variant)) return false;
-  if (ctx->want_seg_rows >= kMinSegRows) cfg->seg_rows = ctx->want_seg_rows;
+  if (ctx->want_seg_rows >= kMinSegRows) cfg->seg_rows = ctx->want_seg_rows / 4 * 4;
   return true;
 }
 

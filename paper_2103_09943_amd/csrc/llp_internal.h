@@ -121,14 +121,16 @@ struct SceneDesc {
 constexpr int kTapStride = 1024;  // floats per scene in the batch's kernel-tap table (n <= 31)
 
 // Split variant of q = A p (llp_sweep.hip): q_D = B^T D^T y (k_data), then q = q_D + lambda L^T M L p and, in
-// mode 1, the dot products (k_llp); apply_ntiles() partials per band.
+// mode 1, the dot products (k_llp); apply_ntiles() partials per band.  For the classes of sweep_fused() the
+// sweep forms q_D itself and there is no k_data launch.  Segments are multiples of 4 rows.
+bool sweep_fused(int C, int R);
 bool sweep_fits(const Geom& g, int seg_rows);
 int sweep_ntiles(const Geom& g, int seg_rows);
 int sweep_data_blocks(const Geom& g);
 int sweep_out_width(int r);
 hipError_t launch_apply_sweep(const Geom& g, int seg_rows, int mode, const float* p, const float* rres,
-                              const float* y, const float* u, const float4* gmd, float* q, double* partials,
-                              ChanState* st, hipStream_t s);
+                              const float* y, const float* u, const float* G, const float* mu, const float* dinv,
+                              float* q, double* partials, ChanState* st, hipStream_t s);
 hipError_t launch_apply_sweep_batch(const SceneDesc* table, int count, int data_blocks, int llp_blocks, int C,
                                     int R, int r, int parity, ChanState* st, char* ws, const float* taps,
                                     hipStream_t s);

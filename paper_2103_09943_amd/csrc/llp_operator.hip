@@ -484,7 +484,7 @@ hipError_t launch_apply(const Geom& g, const OpConfig& cfg, int mode, const floa
   A.st = st;
   A.pstride = (int)max_partials_per_band(g);
   if (cfg.fast && cfg.apply_variant == kSweepVariant)
-    return launch_apply_sweep(g, cfg.seg_rows, mode, p, r, y, u, gmd, q, partials, st, s);
+    return launch_apply_sweep(g, cfg.seg_rows, mode, p, r, y, u, G, mu, dinv, q, partials, st, s);
   return launch_apply_kernel(g, cfg, A, u, s);
 }
 
