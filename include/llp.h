@@ -122,7 +122,8 @@ llp_status llp_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params
 /* Flags of llp_pansharpen_batch. */
 #define LLP_BATCH_NO_GRAPH 1 /* enqueue the batched iteration kernels directly instead of replaying a graph */
 #define LLP_BATCH_SERIAL 2   /* solve the scenes one after another with llp_pansharpen (for comparison) */
-#define LLP_BATCH_AUTOTUNE 4 /* first run llp_autotune on one scene of every class without a tuned entry */
+#define LLP_BATCH_AUTOTUNE 4 /* first tune every class without a tuned entry: llp_autotune_batch on one of its
+                                scenes (llp_autotune if S == 1 or the class has no specialised kernels) */
 
 /* Solve eq. (Z_ini_matting) for every band of S scenes of any sizes at once.  The paper solves the bands of a
  * scene independently (the parallel loop over bands of Algorithm "Fast Pansharpening", Sec. III-B); here all
@@ -158,18 +159,34 @@ typedef struct {
   double default_us_per_iter; /* the same for the untuned default choice */
   int candidates;             /* configurations timed */
 } llp_tune_result;
+/* (For llp_autotune_batch the times are per CG iteration of one scene of the batch.) */
 
 /* Time every launch configuration the build has for this geometry (iters CG iterations of the given scene per
  * candidate, HIP events around the kernels, the fastest of three runs after an untimed one) and keep the
  * fastest (the default unless another is at least 3% faster) for the geometry's class: (c, n, r) and the
- * image area H*W in half-octaves.  Later solves of that class on this context, single or batched, use it
- * (unless LLP_DIR_ROWS / LLP_APPLY_VARIANT / LLP_SEG_ROWS override the choice).  Inputs as for
+ * image area H*W in half-octaves.  Later single-scene solves of that class on this context use it, and so do
+ * batched ones unless the class has a batched entry (llp_autotune_batch); LLP_DIR_ROWS / LLP_APPLY_VARIANT /
+ * LLP_SEG_ROWS override both.  Inputs as for
  * llp_pansharpen; scratch: device [N][H][W] float32 written during tuning, or NULL (allocated and freed by the
  * call);
  * 1 <= iters <= 1000; out: host, or NULL.  Synchronises `stream`. */
 llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
                         const float* pan, const float* kernel, float* scratch, int iters, llp_tune_result* out,
                         hipStream_t stream);
+
+/* The same for batched solves (llp_pansharpen_batch with S >= 2): there each launch carries the workgroups of
+ * many scenes, which favours other shapes than a lone scene does.  Every specialised configuration is timed on
+ * a batch of `copies` copies of the given scene (0: enough copies for about 32 M pixel-bands, 2..64), as the
+ * difference of the wall time of batched solves of 2 iters and of iters iterations (the fastest of three each,
+ * after an untimed solve), and the fastest is kept as the class's batched entry, unless it is less than 3%
+ * faster than the common batched shape (column sweep, 4-row update tiles, 64-row segments at r = 1), which
+ * keeps scenes of different sizes in shared launches.  LLP_E_UNSUPPORTED if no specialised kernel fits the geometry (no specialised
+ * kernels for (c, n, r), or an image narrower or lower than their tiles): such scenes are never batched.  0 <= copies <= 256; 1 <= iters <= 1000, rounded up to a multiple of 8 (batched solves iterate in
+ * chunks of 8).  Allocates and frees copies * N*H*W floats of output
+ * scratch.  Synchronises `stream`. */
+llp_status llp_autotune_batch(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
+                              const float* pan, const float* kernel, int copies, int iters, llp_tune_result* out,
+                              hipStream_t stream);
 
 /* The tuned table: save it as JSON tagged with the device architecture (e.g. "gfx950"), merge a saved table
  * into the context (LLP_E_UNSUPPORTED if it was made for another architecture, LLP_E_ARG if unreadable),

@@ -71,6 +71,8 @@ _SIGS = {
                                      ctypes.POINTER(ctypes.c_double), _vp]),
     "llp_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
                                     ctypes.c_int, _vp, _vp]),
+    "llp_autotune_batch": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp,
+                                          ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "llp_tune_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "llp_tune_load": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "llp_tune_clear": (ctypes.c_int, [_vp]),
@@ -235,6 +237,18 @@ class Context:
         _check(lib().llp_autotune(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(lrms), _ptr(pan),
                                   _ptr(kernel), _ptr(scratch), int(iters), ctypes.byref(res), _stream(stream)),
                "llp_autotune")
+        return {k: getattr(res, k) for k, _ in res._fields_}
+
+    def autotune_batch(self, lrms, pan, kernel, *, r: int, lam: float, eps: float, iters: int = 8, copies: int = 0,
+                       stream=None) -> dict:
+        """Time every specialised launch configuration on a batch of copies of this scene
+        (llp_autotune_batch) and keep the fastest as its class's batched entry."""
+        shp = shape_of(lrms, pan, kernel)
+        prm = Params(int(r), float(lam), float(eps), int(iters), 0.0, 0)
+        res = TuneResult()
+        _check(lib().llp_autotune_batch(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(lrms), _ptr(pan),
+                                        _ptr(kernel), int(copies), int(iters), ctypes.byref(res),
+                                        _stream(stream)), "llp_autotune_batch")
         return {k: getattr(res, k) for k, _ in res._fields_}
 
     # ---- warm-start network

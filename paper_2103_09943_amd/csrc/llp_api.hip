@@ -205,16 +205,19 @@ llp_status apply_A_into(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const 
 }
 
 
-bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg) {
+bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg, bool batched) {
   if (ctx->want_dir_rows == 0 && ctx->want_apply_variant < 0 && ctx->want_seg_rows == 0) {
     const int bucket = area_bucket(g);
-    for (const TuneEntry& t : ctx->tuned) {
-      if (t.c != g.c || t.R != g.R || t.r != g.r || t.bucket != bucket) continue;
-      if (t.cfg.fast && (!ctx->allow_fast || !fast_path_available(g.c, g.R, g.r) ||
-                         !fast_path_fits(g, t.cfg.dir_rows, t.cfg.apply_variant)))
-        break;
-      *cfg = t.cfg;
-      return true;
+    for (int want : {batched ? 1 : 0, 0}) {
+      for (const TuneEntry& t : ctx->tuned) {
+        if (t.c != g.c || t.R != g.R || t.r != g.r || t.bucket != bucket || t.batched != want) continue;
+        if (t.cfg.fast && (!ctx->allow_fast || !fast_path_available(g.c, g.R, g.r) ||
+                           !fast_path_fits(g, t.cfg.dir_rows, t.cfg.apply_variant) ||
+                           (t.cfg.apply_variant == kSweepVariant && !sweep_fits(g, t.cfg.seg_rows))))
+          break;
+        *cfg = t.cfg;
+        return true;
+      }
     }
   }
   if (!pick_config(g, cfg, ctx->allow_fast, ctx->want_dir_rows, ctx->want_apply_variant)) return false;

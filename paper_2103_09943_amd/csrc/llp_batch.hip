@@ -125,15 +125,23 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     llp_status v = validate(&shapes[i], params, &geoms[i]);
     if (v != LLP_OK) return v;
   }
+  const bool batched = S > 1;  // launches carry the workgroups of several scenes
   if (flags & LLP_BATCH_AUTOTUNE) {
     for (int i = 0; i < S; ++i) {
       const Geom& g = geoms[i];
       const int bucket = area_bucket(g);
-      bool have = false;
-      for (const TuneEntry& t : ctx->tuned) have |= t.c == g.c && t.R == g.R && t.r == g.r && t.bucket == bucket;
+      bool have = false;  // an entry of the mode the planner will look up first, or a single-scene one for a
+                          // scene that is never batched
+      for (const TuneEntry& t : ctx->tuned)
+        have |= t.c == g.c && t.R == g.R && t.r == g.r && t.bucket == bucket &&
+                (t.batched == (batched ? 1 : 0) || (t.batched == 0 && !t.cfg.fast));
       if (have) continue;
-      const llp_status v = llp_autotune(ctx, &shapes[i], params, lrms[i], pan[i], kernel[i], nullptr, kTuneIters,
-                                        nullptr, stream);
+      // scenes no specialised kernel fits are solved one by one: they get a single-scene entry
+      llp_status v = LLP_E_UNSUPPORTED;
+      if (batched)
+        v = llp_autotune_batch(ctx, &shapes[i], params, lrms[i], pan[i], kernel[i], 0, kTuneIters, nullptr, stream);
+      if (v == LLP_E_UNSUPPORTED)
+        v = llp_autotune(ctx, &shapes[i], params, lrms[i], pan[i], kernel[i], nullptr, kTuneIters, nullptr, stream);
       if (v != LLP_OK) return v;
     }
   }
@@ -144,7 +152,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     b.idx = i;
     b.rep0 = total_bands;
     b.g = geoms[i];
-    if (!ctx_config(ctx, b.g, &b.cfg)) return LLP_E_UNSUPPORTED;
+    if (!ctx_config(ctx, b.g, &b.cfg, batched)) return LLP_E_UNSUPPORTED;
     b.cls = class_key(b.g, b.cfg);
     total_bands += b.g.N;
     if (b.cfg.fast && !(flags & LLP_BATCH_SERIAL)) fast.push_back(b);

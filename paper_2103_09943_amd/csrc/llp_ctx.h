@@ -22,11 +22,14 @@ constexpr int kMaxLdsFloats = 160 * 1024 / 4;
     if (e_ != hipSuccess) return LLP_E_HIP; \
   } while (0)
 
-// Tuned launch configuration of one geometry class: (c, R, r) and the image area in half-octaves.
+// Tuned launch configuration of one geometry class: (c, R, r) and the image area in half-octaves, for solves
+// of one scene (batched = 0) or for batched solves, whose launches carry the workgroups of many scenes
+// (batched = 1).
 struct TuneEntry {
   int c, R, r, bucket;
   OpConfig cfg;
-  double us_per_iter;  // measured time of one CG iteration (operator + update kernels) of the whole scene
+  double us_per_iter;  // measured time of one CG iteration (operator + update kernels) of one scene
+  int batched;
 };
 int area_bucket(const Geom& g);
 
@@ -36,8 +39,9 @@ llp_status validate(const llp_shape* s, const llp_params* p, Geom* g);
 // Default launch configuration: the first shapes (in preference order) whose LDS fits.
 bool pick_config(const Geom& g, OpConfig* cfg, bool allow_fast = true, int want_dir_rows = 0,
                  int want_apply_variant = -1);
-// The configuration a context uses for g: environment overrides, else a tuned entry, else the default.
-bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg);
+// The configuration a context uses for g: environment overrides, else a tuned entry (for batched solves the
+// batched entry of the class if there is one, then the single-scene entry), else the default.
+bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg, bool batched = false);
 llp_status ensure_workspace(llp_ctx* ctx, const Geom& g);
 hipEvent_t timing_event(llp_ctx* ctx);
 llp_status collect_times(llp_ctx* ctx);

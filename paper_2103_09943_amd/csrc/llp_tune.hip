@@ -1,13 +1,16 @@
 // Autotuner of the launch configuration of the two CG iteration kernels (tile shapes of k_apply, rows per tile
 // of k_dir, specialised or generic kernels), per geometry class: (c, R, r) and the image area in half-octaves.
 // Every candidate runs a few CG iterations of the caller's scene under HIP-event timing; the fastest is kept in
-// the context and used by later solves of that class.  The table can be saved to and loaded from a small JSON
-// file tagged with the device architecture.
+// the context and used by later solves of that class.  Batched solves have their own entries: there every
+// launch carries the workgroups of many scenes, so a shape that leaves a lone small scene's launch short of
+// workgroups can still be the fastest, and the batched tuner times candidates on a batch of copies of the
+// scene.  The table can be saved to and loaded from a small JSON file tagged with the device architecture.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -86,6 +89,47 @@ llp_status time_config(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
   return LLP_OK;
 }
 
+// Keeps e in the context's table, replacing the entry of the same class and mode.
+void keep_entry(llp_ctx* ctx, const TuneEntry& e) {
+  for (TuneEntry& t : ctx->tuned)
+    if (t.c == e.c && t.R == e.R && t.r == e.r && t.bucket == e.bucket && t.batched == e.batched) {
+      t = e;
+      return;
+    }
+  ctx->tuned.push_back(e);
+}
+
+// Wall-clock seconds of one batched solve (the call is synchronous) of `copies` copies of a scene with the
+// launch configuration forced to cfg.
+llp_status time_batch(llp_ctx* ctx, const OpConfig& cfg, const llp_shape* shape, const llp_params* params,
+                      int max_iters, const float* lrms, const float* pan, const float* kernel, float* out,
+                      int copies, hipStream_t s, double* secs) {
+  llp_params p = *params;
+  p.max_iters = max_iters;
+  p.tol = 0.0f;
+  p.init_mode = 0;
+  const size_t nhw = (size_t)shape->N * shape->c * shape->h * shape->c * shape->w;
+  std::vector<llp_shape> shapes(copies, *shape);
+  std::vector<const float*> L(copies, lrms), P(copies, pan), K(copies, kernel);
+  std::vector<float*> O(copies);
+  for (int i = 0; i < copies; ++i) O[i] = out + (size_t)i * nhw;
+  const int saved[3] = {ctx->want_dir_rows, ctx->want_apply_variant, ctx->want_seg_rows};
+  ctx->want_dir_rows = cfg.dir_rows;
+  ctx->want_apply_variant = cfg.apply_variant;
+  ctx->want_seg_rows = cfg.seg_rows;
+  HIP_TRY(hipStreamSynchronize(s));
+  const auto t0 = std::chrono::steady_clock::now();
+  llp_status v = llp_pansharpen_batch(ctx, copies, shapes.data(), &p, L.data(), P.data(), K.data(), nullptr,
+                                      O.data(), nullptr, 0, s);
+  const auto t1 = std::chrono::steady_clock::now();
+  ctx->want_dir_rows = saved[0];
+  ctx->want_apply_variant = saved[1];
+  ctx->want_seg_rows = saved[2];
+  if (v == LLP_E_BREAKDOWN || v == LLP_E_NONFINITE || v > 0) v = LLP_OK;
+  *secs = std::chrono::duration<double>(t1 - t0).count();
+  return v;
+}
+
 std::string device_arch(int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
@@ -158,14 +202,82 @@ llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* 
     (void)hipFree(own);
   }
   if (v != LLP_OK) return v;
-  TuneEntry e{g.c, g.R, g.r, area_bucket(g), best, best_us};
-  bool replaced = false;
-  for (TuneEntry& t : ctx->tuned)
-    if (t.c == e.c && t.R == e.R && t.r == e.r && t.bucket == e.bucket) {
-      t = e;
-      replaced = true;
+  keep_entry(ctx, TuneEntry{g.c, g.R, g.r, area_bucket(g), best, best_us, 0});
+  if (out) {
+    out->fast = best.fast;
+    out->dir_rows = best.dir_rows;
+    out->apply_variant = best.apply_variant;
+    out->seg_rows = best.seg_rows;
+    out->us_per_iter = best_us;
+    out->default_us_per_iter = def_us;
+    out->candidates = (int)cands.size();
+  }
+  return LLP_OK;
+}
+
+llp_status llp_autotune_batch(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
+                              const float* pan, const float* kernel, int copies, int iters, llp_tune_result* out,
+                              hipStream_t stream) {
+  if (!ctx || !params || !lrms || !pan || !kernel || iters < 1 || iters > 1000 || copies < 0 || copies > 256)
+    return LLP_E_ARG;
+  Geom g;
+  llp_status v = validate(shape, params, &g);
+  if (v != LLP_OK) return v;
+  if (!ctx->allow_fast || !fast_path_available(g.c, g.R, g.r)) return LLP_E_UNSUPPORTED;  // never batched
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::vector<OpConfig> cands;
+  for (const OpConfig& c : candidates(g, true))
+    if (c.fast) cands.push_back(c);
+  OpConfig def;
+  if (cands.empty() || !pick_config(g, &def, true)) return LLP_E_UNSUPPORTED;
+  // Reference of the batched choice: one shape for every class where it fits (the sweep, 4-row update tiles,
+  // 64-row segments for r = 1), so that scenes of different sizes share launches unless a class gains at least
+  // the margin from another shape.
+  if (def.fast && sweep_fits(g, 2 * kMinSegRows) && fast_path_fits(g, 4, kSweepVariant)) {
+    def.dir_rows = 4;
+    def.apply_variant = kSweepVariant;
+    if (g.r == 1) def.seg_rows = 2 * kMinSegRows;
+  }
+  const size_t nhw = (size_t)g.N * g.H * g.W;
+  if (copies == 0) {  // about 32 M pixel-bands in the batch
+    const size_t want = ((size_t)32 << 20) / nhw;
+    copies = (int)(want < 2 ? 2 : (want > 64 ? 64 : want));
+  }
+  float* outbuf = nullptr;
+  if (hipMalloc((void**)&outbuf, sizeof(float) * nhw * copies) != hipSuccess) return LLP_E_OOM;
+  // Batched solves run their iterations in graph-captured chunks of 8: whole chunks only.
+  iters = (iters + 7) / 8 * 8;
+  // Per candidate and iteration count (iters, 2 iters): one untimed solve (graph capture, workspace), then the
+  // fastest of kRuns solves; the difference of the two is the time of iters iterations without the set-up work.
+  double best_us = 0.0, def_us = 0.0;
+  OpConfig best = cands[0];
+  for (const OpConfig& c : cands) {
+    double t[2] = {0.0, 0.0};
+    for (int j = 0; j < 2 && v == LLP_OK; ++j) {
+      const int it = (j + 1) * iters;
+      double secs = 0.0;
+      v = time_batch(ctx, c, shape, params, it, lrms, pan, kernel, outbuf, copies, stream, &secs);
+      for (int run = 0; run < kRuns && v == LLP_OK; ++run) {
+        v = time_batch(ctx, c, shape, params, it, lrms, pan, kernel, outbuf, copies, stream, &secs);
+        if (run == 0 || secs < t[j]) t[j] = secs;
+      }
     }
-  if (!replaced) ctx->tuned.push_back(e);
+    if (v != LLP_OK) break;
+    const double t1 = t[0], t2 = t[1];
+    const double us = (t2 > t1 ? t2 - t1 : 0.0) * 1e6 / (double)iters / (double)copies;
+    if (same(c, def)) def_us = us;
+    if (best_us == 0.0 || us < best_us) {
+      best_us = us;
+      best = c;
+    }
+  }
+  (void)hipFree(outbuf);
+  if (v != LLP_OK) return v;
+  if (def_us > 0.0 && !(best_us < kMargin * def_us)) {
+    best = def;
+    best_us = def_us;
+  }
+  keep_entry(ctx, TuneEntry{g.c, g.R, g.r, area_bucket(g), best, best_us, 1});
   if (out) {
     out->fast = best.fast;
     out->dir_rows = best.dir_rows;
@@ -194,10 +306,10 @@ llp_status llp_tune_save(llp_ctx* ctx, const char* path) {
   for (size_t i = 0; i < ctx->tuned.size(); ++i) {
     const TuneEntry& t = ctx->tuned[i];
     fprintf(f,
-            "%s\n    {\"c\": %d, \"R\": %d, \"r\": %d, \"bucket\": %d, \"fast\": %d, \"dir_rows\": %d, "
-            "\"apply_variant\": %d, \"seg_rows\": %d, \"us_per_iter\": %.2f}",
-            i ? "," : "", t.c, t.R, t.r, t.bucket, t.cfg.fast, t.cfg.dir_rows, t.cfg.apply_variant, t.cfg.seg_rows,
-            t.us_per_iter);
+            "%s\n    {\"c\": %d, \"R\": %d, \"r\": %d, \"bucket\": %d, \"batched\": %d, \"fast\": %d, "
+            "\"dir_rows\": %d, \"apply_variant\": %d, \"seg_rows\": %d, \"us_per_iter\": %.2f}",
+            i ? "," : "", t.c, t.R, t.r, t.bucket, t.batched, t.cfg.fast, t.cfg.dir_rows, t.cfg.apply_variant,
+            t.cfg.seg_rows, t.us_per_iter);
   }
   fprintf(f, "\n  ]\n}\n");
   return fclose(f) == 0 ? LLP_OK : LLP_E_ARG;
@@ -233,24 +345,18 @@ llp_status llp_tune_load(llp_ctx* ctx, const char* path) {
         !json_number(t, b, e, "dir_rows", &rows) || !json_number(t, b, e, "apply_variant", &var))
       return LLP_E_ARG;
     json_number(t, b, e, "us_per_iter", &us);
-    double seg = 2 * kMinSegRows;
+    double seg = 2 * kMinSegRows, batched = 0.0;
     json_number(t, b, e, "seg_rows", &seg);
+    json_number(t, b, e, "batched", &batched);
     const OpConfig cfg{(int)fast, (int)rows, (int)var, (int)seg};
     if ((cfg.fast != 0 && cfg.fast != 1) || (cfg.dir_rows != 4 && cfg.dir_rows != 8) || cfg.apply_variant < 0 ||
-        cfg.apply_variant >= kApplyVariants || cfg.seg_rows < kMinSegRows || cfg.seg_rows > 4096)
+        cfg.apply_variant >= kApplyVariants || cfg.seg_rows < kMinSegRows || cfg.seg_rows > 4096 ||
+        (batched != 0.0 && batched != 1.0))
       return LLP_E_ARG;
-    entries.push_back(TuneEntry{(int)c, (int)R, (int)r, (int)bucket, cfg, us});
+    entries.push_back(TuneEntry{(int)c, (int)R, (int)r, (int)bucket, cfg, us, (int)batched});
     pos = e + 1;
   }
-  for (const TuneEntry& e : entries) {
-    bool replaced = false;
-    for (TuneEntry& t2 : ctx->tuned)
-      if (t2.c == e.c && t2.R == e.R && t2.r == e.r && t2.bucket == e.bucket) {
-        t2 = e;
-        replaced = true;
-      }
-    if (!replaced) ctx->tuned.push_back(e);
-  }
+  for (const TuneEntry& e : entries) keep_entry(ctx, e);
   return LLP_OK;
 }
 

@@ -3,7 +3,8 @@
     python -m paper_2103_09943_amd.tune [--out PATH]
 
 Tunes the 8-band 2048^2 scene (r 2, 17 taps) and one synthetic scene of every (PAN side, kernel size) class of
-the batch workload (sides 256..1024 in steps of 128, 9..17 taps, r 1).  The library keys the table by (c, n, r)
+the batch workload (sides 256..1024 in steps of 128, 9..17 taps, r 1), each for single-scene solves and for
+batched solves (on a batch of copies of the scene).  The library keys the table by (c, n, r)
 and the image area in half-octaves, and refuses a table made on another architecture.
 """
 from __future__ import annotations
@@ -41,8 +42,11 @@ def main():
                                                                           tol=0.0)))
     with B.Context(0) as ctx:
         for name, s, stt in jobs:
-            res = ctx.autotune(dev(s.X), dev(s.Y), dev(s.u), r=stt.r, lam=stt.lam, eps=stt.eps, iters=args.iters)
-            print(json.dumps({"scene": name, **res}), flush=True)
+            d = (dev(s.X), dev(s.Y), dev(s.u))
+            res = ctx.autotune(*d, r=stt.r, lam=stt.lam, eps=stt.eps, iters=args.iters)
+            print(json.dumps({"scene": name, "mode": "single", **res}), flush=True)
+            res = ctx.autotune_batch(*d, r=stt.r, lam=stt.lam, eps=stt.eps, iters=args.iters)
+            print(json.dumps({"scene": name, "mode": "batched", **res}), flush=True)
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         ctx.tune_save(args.out)
     print(f"saved {args.out}", flush=True)

@@ -54,6 +54,8 @@ def test_null_context_is_rejected(lib):
                                     None, 0, None) == B.E_ARG
     assert lib.llp_autotune(None, ctypes.byref(shp), ctypes.byref(prm), None, None, None, None, 8, None,
                             None) == B.E_ARG
+    assert lib.llp_autotune_batch(None, ctypes.byref(shp), ctypes.byref(prm), None, None, None, 0, 8, None,
+                                  None) == B.E_ARG
     assert lib.llp_tune_save(None, b"/tmp/x.json") == B.E_ARG
     assert lib.llp_tune_load(None, b"/tmp/x.json") == B.E_ARG
     assert lib.llp_tune_clear(None) == B.E_ARG
