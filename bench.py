@@ -372,11 +372,11 @@ def main():
     # counter-measured HBM bytes per launch (8 x 2048^2 workload, all bands active) for the specialised kernels
     traffic = None
     if args.side is None:
-        traffic = measured_traffic(("llp::k_data<4, 8>", "llp::k_llp<2, 1>") if dominant == "k_apply"
+        traffic = measured_traffic(("llp::k_llp<2, 1, 4, 8>",) if dominant == "k_apply"
                                    else ("llp::k_dir_fast<4, 8, 4, 2>",))
     dom = {
-        "k_apply": dict(kernel="k_apply (q = A p: k_data B^T D^T y, then k_llp + lambda L^T M L p; p^T q, r^T q, "
-                               "q^T q)",
+        "k_apply": dict(kernel="k_apply (q = A p: the column sweep k_llp, B^T D^T y on matrix cores + lambda "
+                               "L^T M L p; p^T q, r^T q, q^T q)",
                         achieved=apply_gbs, ms=kt["apply_ms"], n=launches),
         "k_dir": dict(kernel="k_dir (x, r update; p = r + beta p; y = D B p; r^T r)", achieved=dir_gbs,
                       ms=kt["dir_ms"], n=kt["dir_launches"]),
