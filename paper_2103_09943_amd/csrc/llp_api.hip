@@ -98,7 +98,7 @@ bool pick_config(const Geom& g, OpConfig* cfg, bool allow_fast, int want_dir_row
 
 llp_status ensure_workspace(llp_ctx* ctx, const Geom& g) {
   const size_t HW = (size_t)g.H * g.W;
-  const size_t planes = 7 * HW + 6 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w;
+  const size_t planes = 3 * HW + 6 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w;
   const size_t pstride = max_partials_per_band(g);
   size_t off = 0;
   const size_t o_planes = off;
@@ -127,12 +127,11 @@ llp_status ensure_workspace(llp_ctx* ctx, const Geom& g) {
   }
   char* base = (char*)ctx->ws;
   float* pl = (float*)(base + o_planes);
-  ctx->GMD = (float4*)pl;  // first: 16-byte aligned
-  ctx->G = pl + 4 * HW;
-  ctx->MU = pl + 5 * HW;
-  ctx->DI = pl + 6 * HW;
+  ctx->G = pl;
+  ctx->MU = pl + HW;
+  ctx->DI = pl + 2 * HW;
   const size_t NHW = (size_t)g.N * HW;
-  ctx->b = pl + 7 * HW;
+  ctx->b = pl + 3 * HW;
   ctx->r[0] = ctx->b + NHW;
   ctx->r[1] = ctx->r[0] + NHW;
   ctx->p[0] = ctx->r[1] + NHW;
@@ -199,7 +198,7 @@ llp_status apply_A_into(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const 
                         float* q, hipStream_t s) {
   HIP_TRY(launch_dir(g, cfg, 0, 0, 0, z, nullptr, nullptr, nullptr, nullptr, nullptr, ctx->y, kernel, ctx->partials,
                      ctx->st, 0, 0.0f, s));
-  HIP_TRY(launch_apply(g, cfg, 0, z, nullptr, ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, ctx->GMD, q, ctx->partials,
+  HIP_TRY(launch_apply(g, cfg, 0, z, nullptr, ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, q, ctx->partials,
                        ctx->st, s));
   return LLP_OK;
 }
@@ -239,7 +238,7 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
   v = check_inputs(ctx, g, lrms, pan, kernel, s);
   if (v != LLP_OK) return v;
   // Per scene: the statistics that define M_LY, then the right-hand sides and ||b||.
-  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, ctx->GMD, s));
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, s));
   HIP_TRY(launch_rhs(g, lrms, kernel, ctx->b, ctx->partials, ctx->st, s));
   const int from_init = params->init_mode != 0;
   if (params->init_mode == 1 && init != hrms)
@@ -277,7 +276,7 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
           if (!(ev = timing_event(ctx))) return LLP_E_HIP;
         HIP_TRY(hipEventRecord(e[0], s));
       }
-      HIP_TRY(launch_apply(g, cfg, 1, ctx->p[prev], ctx->r[prev], ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, ctx->GMD,
+      HIP_TRY(launch_apply(g, cfg, 1, ctx->p[prev], ctx->r[prev], ctx->y, kernel, ctx->G, ctx->MU, ctx->DI,
                            ctx->q,
                            ctx->partials, ctx->st, s));
       if (ctx->profiling) HIP_TRY(hipEventRecord(e[1], s));
@@ -427,7 +426,7 @@ llp_status llp_pan_stats(llp_ctx* ctx, const llp_shape* shape, const llp_params*
   llp_status v = validate(shape, params, &g);
   if (v != LLP_OK) return v;
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(launch_pan_stats(g, pan, G, mu, dinv, nullptr, stream));
+  HIP_TRY(launch_pan_stats(g, pan, G, mu, dinv, stream));
   return LLP_OK;
 }
 
@@ -456,7 +455,7 @@ llp_status llp_apply_A(llp_ctx* ctx, const llp_shape* shape, const llp_params* p
   HIP_TRY(hipSetDevice(ctx->device));
   v = ensure_workspace(ctx, g);
   if (v != LLP_OK) return v;
-  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, ctx->GMD, stream));
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
   return apply_A_into(ctx, g, cfg, z, kernel, Az, stream);
 }
 
@@ -469,7 +468,7 @@ llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params*
   HIP_TRY(hipSetDevice(ctx->device));
   v = ensure_workspace(ctx, g);
   if (v != LLP_OK) return v;
-  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, ctx->GMD, stream));
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
   HIP_TRY(launch_objective(g, z, lrms, kernel, ctx->G, ctx->MU, ctx->DI, ctx->partials, ctx->st, ctx->results,
                            stream));
   HIP_TRY(hipMemcpyAsync(ctx->h_results, ctx->results, sizeof(double) * kResultSlots * g.N, hipMemcpyDeviceToHost,

@@ -188,8 +188,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       const Geom& g = fast[i].g;
       const size_t HW = (size_t)g.H * g.W;
       o_pl[i] = off;
-      // the statistics (7 planes), b, r (2), p (2), q, the iterate x, and y
-      off = align_up(off + (7 * HW + 7 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w) * sizeof(float), 256);
+      // the statistics G, mu, dinv, b, r (2), p (2), q, the iterate x, and y
+      off = align_up(off + (3 * HW + 7 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w) * sizeof(float), 256);
       o_part[i] = off;
       off = align_up(off + (size_t)g.N * max_partials_per_band(g) * 3 * sizeof(double), 256);
       nbands += g.N;
@@ -244,11 +244,10 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       d.Y = pan[bs.idx];
       d.u = kernel[bs.idx];
       float* pl = (float*)(base + o_pl[i]);
-      d.GMD = (float4*)pl;
-      d.G = pl + 4 * HW;
-      d.MU = pl + 5 * HW;
-      d.DI = pl + 6 * HW;
-      d.b = pl + 7 * HW;
+      d.G = pl;
+      d.MU = pl + HW;
+      d.DI = pl + 2 * HW;
+      d.b = pl + 3 * HW;
       d.r[0] = d.b + NHW;
       d.r[1] = d.r[0] + NHW;
       d.p[0] = d.r[1] + NHW;
@@ -268,7 +267,6 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       d.o_G = rel(d.G);
       d.o_MU = rel(d.MU);
       d.o_DI = rel(d.DI);
-      d.o_GMD = rel(d.GMD);
       d.o_partials = rel(d.partials);
       d.taps_index = i;
       d.pstride = (int)max_partials_per_band(g);
@@ -319,7 +317,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       HIP_TRY(launch_check_finite(d.X, (size_t)g.N * g.h * g.w, bflags + i, s));
       HIP_TRY(launch_check_finite(d.Y, (size_t)g.H * g.W, bflags + i, s));
       HIP_TRY(launch_check_finite(d.u, (size_t)g.n * g.n, bflags + i, s));
-      HIP_TRY(launch_pan_stats(g, d.Y, d.G, d.MU, d.DI, d.GMD, s));
+      HIP_TRY(launch_pan_stats(g, d.Y, d.G, d.MU, d.DI, s));
       HIP_TRY(launch_rhs(g, d.X, d.u, d.b, d.partials, sst, s));
       if (from_init) {
         const float* z0 = init[fast[i].idx];
@@ -333,7 +331,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       if (from_init || net_init) {
         HIP_TRY(launch_dir(g, cfg, 0, 0, 0, d.x, nullptr, nullptr, nullptr, nullptr, nullptr, d.y, d.u, d.partials,
                            sst, 0, 0.0f, s));
-        HIP_TRY(launch_apply(g, cfg, 0, d.x, nullptr, d.y, d.u, d.G, d.MU, d.DI, d.GMD, d.q, d.partials, sst, s));
+        HIP_TRY(launch_apply(g, cfg, 0, d.x, nullptr, d.y, d.u, d.G, d.MU, d.DI, d.q, d.partials, sst, s));
       }
       HIP_TRY(launch_init(g, from_init || net_init, d.b, d.q, d.r[0], d.x, sst, s));
       if (net_init) {
@@ -422,7 +420,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         double* sres = results + (size_t)d.band0 * kResultSlots;
         HIP_TRY(launch_dir(d.g, cfg, 0, 0, 0, d.x, nullptr, nullptr, nullptr, nullptr, nullptr, d.y, d.u,
                            d.partials, sst, 0, 0.0f, s));
-        HIP_TRY(launch_apply(d.g, cfg, 0, d.x, nullptr, d.y, d.u, d.G, d.MU, d.DI, d.GMD, d.q, d.partials, sst, s));
+        HIP_TRY(launch_apply(d.g, cfg, 0, d.x, nullptr, d.y, d.u, d.G, d.MU, d.DI, d.q, d.partials, sst, s));
         HIP_TRY(launch_residual_norm(d.g, d.b, d.q, d.partials, sst, sres, s));
         HIP_TRY(launch_objective(d.g, d.x, d.X, d.u, d.G, d.MU, d.DI, d.partials, sst, sres, s));
       }

@@ -83,7 +83,6 @@ struct llp_ctx {
   size_t ws_bytes = 0;
   // views into ws
   float *G = nullptr, *MU = nullptr, *DI = nullptr, *b = nullptr, *q = nullptr, *y = nullptr;
-  float4* GMD = nullptr;  // (G, mu, dinv, 0) interleaved, for the column sweep
   float* r[2] = {nullptr, nullptr};  // residual, alternating between iterations
   float* p[2] = {nullptr, nullptr};  // direction, alternating between iterations
   double* partials = nullptr;

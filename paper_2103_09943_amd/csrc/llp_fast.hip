@@ -28,7 +28,12 @@ struct DirShape {
   static constexpr int PS = pad_to(PR * PC, (64 / C) % 64);  // consecutive phase planes 64/C banks apart
   static constexpr int RH = C * PR, RW = C * PC;
   static constexpr int LDS = C * C * PS;
+  static constexpr int LDS_ALLOC = LDS + 64;  // plus one slot per lane for the stores of lanes past the region
 };
+
+// Byte offset past every plane: buffer loads from it return 0 and stores to it are dropped (the planes of the
+// fast path hold fewer than 2^29 floats).
+constexpr unsigned kNoAccess = 0x80000000u;
 
 template <int C, int R, int TYL, int MODE>
 __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, const float* __restrict__ u, int bid) {
@@ -47,82 +52,98 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
     alpha = (float)A.st[ch].alpha;
     beta = (float)A.st[ch].beta;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wave index is uniform: rows, and the row offsets of every access, stay in scalar registers
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int row0 = C * (m0 - S::HYR), col0 = C * (k0 - S::HYR);
   constexpr int in_r0 = C * S::HYR, in_r1 = C * (S::HYR + S::TYL), in_c0 = C * S::HYR, in_c1 = C * (S::HYR + S::TXL);
-  // Per-band planes; every element offset below is a 32-bit unsigned offset from these (H W <= 2^31).
-  const float* __restrict__ rin = A.rin + (size_t)ch * HW;
-  const float* __restrict__ qin = A.qin + (size_t)ch * HW;
-  const float* __restrict__ pin = A.pin + (size_t)ch * HW;
-  float* __restrict__ rout = A.rout + (size_t)ch * HW;
-  float* __restrict__ pout = A.pout + (size_t)ch * HW;
-  float* __restrict__ xb = A.x + (size_t)ch * HW;
+  // Per-band planes through buffer resources: the row is a scalar byte offset, the lane's column a vector one;
+  // lanes past the region or outside the tile's own pixels use kNoAccess instead of branching.
+  const unsigned plane = (unsigned)(HW * 4);
+  auto rsrc = [&](const float* base) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(base + (size_t)ch * HW), (short)0, (int)plane, 0x00020000);
+  };
+  auto ld = [](__amdgpu_buffer_rsrc_t rs, unsigned vo, unsigned so) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+  };
+  auto st = [](float v, __amdgpu_buffer_rsrc_t rs, unsigned vo, unsigned so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, vo, so, 0);
+  };
+  const __amdgpu_buffer_rsrc_t Rr = rsrc(A.rin);
+  const __amdgpu_buffer_rsrc_t Rq = rsrc(MODE == 2 ? A.qin : A.rin), Rp = rsrc(MODE == 2 ? A.pin : A.rin);
+  const __amdgpu_buffer_rsrc_t Rro = rsrc(MODE == 2 ? A.rout : A.rin), Rx = rsrc(MODE == 2 ? A.x : A.rin);
+  const __amdgpu_buffer_rsrc_t Rpo = rsrc(MODE != 0 ? A.pout : A.rin);
 
-  // Column indices of this lane (the same for every row of the region).
+  // Column offsets of this lane (the same for every row of the region).
   constexpr int NCI = (S::RW + 63) / 64;
-  int gcol[NCI], lcol[NCI];
-  bool cval[NCI], cown[NCI];
+  unsigned vld[NCI], vown[NCI];
+  int lcol[NCI];
 #pragma unroll
   for (int ci = 0; ci < NCI; ++ci) {
     const int col = ci * 64 + lane;
     const int gc = col0 + col;
-    cval[ci] = col < S::RW;
-    cown[ci] = col >= in_c0 && col < in_c1 && gc < W;
-    gcol[ci] = wrap1(gc, W);
-    lcol[ci] = (col % C) * S::PS + col / C;
+    const bool valid = col < S::RW;
+    const bool own = valid && col >= in_c0 && col < in_c1 && gc < W;
+    const unsigned cb = (unsigned)wrap1(gc, W) * 4u;
+    vld[ci] = valid ? cb : kNoAccess;
+    vown[ci] = own ? cb : kNoAccess;
+    lcol[ci] = valid ? (col % C) * S::PS + col / C : -1;
   }
   double acc = 0.0;
   constexpr int RPI = 3;  // region rows per wave per iteration (their loads are in flight together)
   for (int row_b = wave; row_b < S::RH; row_b += kWaves * RPI) {
     float rv[RPI][NCI], qv[RPI][NCI], pv[RPI][NCI], xv[RPI][NCI];
-    unsigned roff[RPI];
-    bool rval[RPI], own_row[RPI];
+    unsigned so[RPI];
 #pragma unroll
     for (int j = 0; j < RPI; ++j) {
       const int row = row_b + j * kWaves;
       const int gr = row0 + row;
-      rval[j] = row < S::RH;
-      roff[j] = (unsigned)(wrap1(gr, H) * W);
-      own_row[j] = row >= in_r0 && row < in_r1 && gr < H;
+      so[j] = (unsigned)(wrap1(gr, H) * W) * 4u;
+      const bool own_row = row >= in_r0 && row < in_r1 && gr < H;
+      if (row < S::RH) {
 #pragma unroll
-      for (int ci = 0; ci < NCI; ++ci) {
-        if (rval[j] && cval[ci]) {
-          const unsigned off = roff[j] + (unsigned)gcol[ci];
-          rv[j][ci] = rin[off];
+        for (int ci = 0; ci < NCI; ++ci) {
+          rv[j][ci] = ld(Rr, vld[ci], so[j]);
           if (MODE == 2) {
-            qv[j][ci] = qin[off];
-            pv[j][ci] = pin[off];
-            if (own_row[j] && cown[ci]) xv[j][ci] = xb[off];
+            qv[j][ci] = ld(Rq, vld[ci], so[j]);
+            pv[j][ci] = ld(Rp, vld[ci], so[j]);
           }
+        }
+        if (MODE == 2 && own_row) {
+#pragma unroll
+          for (int ci = 0; ci < NCI; ++ci) xv[j][ci] = ld(Rx, vown[ci], so[j]);
         }
       }
     }
 #pragma unroll
     for (int j = 0; j < RPI; ++j) {
       const int row = row_b + j * kWaves;
+      if (row >= S::RH) continue;
+      const int gr = row0 + row;
+      const bool own_row = row >= in_r0 && row < in_r1 && gr < H;
       float* prow = smem + (row % C) * C * S::PS + (row / C) * S::PC;
+      float vv[NCI];
+#pragma unroll
+      for (int ci = 0; ci < NCI; ++ci)
+        vv[ci] = MODE == 2 ? fmaf(beta, pv[j][ci], fmaf(-alpha, qv[j][ci], rv[j][ci])) : rv[j][ci];
+      if (MODE != 0 && own_row) {
+#pragma unroll
+        for (int ci = 0; ci < NCI; ++ci) {
+          if (MODE == 1) {
+            st(vv[ci], Rpo, vown[ci], so[j]);
+            acc += (double)(vown[ci] != kNoAccess ? vv[ci] * vv[ci] : 0.0f);
+          } else {
+            const float rn = fmaf(-alpha, qv[j][ci], rv[j][ci]);
+            st(rn, Rro, vown[ci], so[j]);
+            if (!A.final_step) st(vv[ci], Rpo, vown[ci], so[j]);
+            st(fmaf(alpha, pv[j][ci], xv[j][ci]), Rx, vown[ci], so[j]);
+            acc += (double)(vown[ci] != kNoAccess ? rn * rn : 0.0f);
+          }
+        }
+      }
 #pragma unroll
       for (int ci = 0; ci < NCI; ++ci) {
-        if (rval[j] && cval[ci]) {
-          const unsigned off = roff[j] + (unsigned)gcol[ci];
-          const bool own = own_row[j] && cown[ci];
-          float v = rv[j][ci];
-          if (MODE == 1 && own) {
-            pout[off] = v;
-            acc += (double)v * v;
-          }
-          if (MODE == 2) {
-            const float rn = fmaf(-alpha, qv[j][ci], rv[j][ci]);
-            v = fmaf(beta, pv[j][ci], rn);
-            if (own) {
-              rout[off] = rn;
-              if (!A.final_step) pout[off] = v;
-              xb[off] = fmaf(alpha, pv[j][ci], xv[j][ci]);
-              acc += (double)rn * rn;
-            }
-          }
-          prow[lcol[ci]] = v;
-        }
+        float* dst = lcol[ci] >= 0 ? prow + lcol[ci] : smem + S::LDS + lane;
+        *dst = vv[ci];
       }
     }
   }
@@ -130,16 +151,16 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
 
   if (!(MODE == 2 && A.final_step)) {
     // y[m][k] = sum_{a,b} u[a][b] p[C m + R - a][C k + R - b]; rows m0 + wave and m0 + wave + 4.
-    // Kernel rows stay a loop (the row's plane and offset are scalars); the n taps of a row are unrolled, each
-    // an LDS read at an immediate offset from the row base.  Each lane computes TYL/4 LR points of one column.
+    // Every tap is one LDS read at an immediate offset from the lane's base and one FMA with the tap in a
+    // scalar register.  Each lane computes TYL/4 LR points of one column.
     constexpr int MPW = TYL / kWaves;
     const float* b0 = smem + (S::HYR + wave) * S::PC + S::HYR + lane;
     float sacc[MPW];
 #pragma unroll
     for (int m = 0; m < MPW; ++m) sacc[m] = 0.0f;
-#pragma unroll 1
+#pragma unroll
     for (int a = 0; a < n; ++a) {
-      const float* rowp = b0 + pos_mod(R - a, C) * C * S::PS + floor_div(R - a, C) * S::PC;
+      const float* rowp = b0 + cpmod(R - a, C) * C * S::PS + cfdiv(R - a, C) * S::PC;
       const float* urow = u + a * n;
 #pragma unroll
       for (int b = 0; b < n; ++b) {
@@ -150,13 +171,13 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
       }
     }
     const int k = k0 + lane;
-    float* yc = A.y + (size_t)ch * g.h * g.w;
-    if (k < g.w) {
+    const __amdgpu_buffer_rsrc_t Ry = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(A.y + (size_t)ch * g.h * g.w), (short)0, (int)((size_t)g.h * g.w * 4), 0x00020000);
+    const unsigned ko = k < g.w ? (unsigned)k * 4u : kNoAccess;
 #pragma unroll
-      for (int m = 0; m < MPW; ++m) {
-        const int mm = m0 + wave + m * kWaves;
-        if (mm < g.h) yc[(unsigned)(mm * g.w + k)] = sacc[m];
-      }
+    for (int m = 0; m < MPW; ++m) {
+      const int mm = m0 + wave + m * kWaves;
+      if (mm < g.h) st(sacc[m], Ry, ko, (unsigned)(mm * g.w) * 4u);
     }
   }
 
@@ -638,7 +659,7 @@ hipError_t set_lds_fast(Kern kern, size_t bytes) {
 template <int C, int R, int TYL, int MODE>
 hipError_t run_dir_fast_m(const Geom& g, DirArgs A, const float* u, hipStream_t s) {
   using S = DirShape<C, R, TYL>;
-  const size_t bytes = (size_t)S::LDS * sizeof(float);
+  const size_t bytes = (size_t)S::LDS_ALLOC * sizeof(float);
   hipError_t e = set_lds_fast(k_dir_fast<C, R, TYL, MODE>, bytes);
   if (e != hipSuccess) return e;
   A.PS = S::PS;
@@ -690,6 +711,7 @@ bool fast_path_fits(const Geom& g, int dir_rows, int apply_variant) {
   const int C = g.c, R = g.R, r = g.r;
   const int HYR = (R + C - 1) / C;
   const int k0_last = ((g.w - 1) / 64) * 64, m0_last = ((g.h - 1) / dir_rows) * dir_rows;
+  if ((size_t)g.H * g.W >= ((size_t)1 << 29)) return false;  // byte offsets of a plane below kNoAccess
   if (C * HYR > g.W || C * HYR > g.H) return false;
   if (C * (k0_last + 64 + HYR) > 2 * g.W || C * (m0_last + dir_rows + HYR) > 2 * g.H) return false;
   if (apply_variant == kSweepVariant) return sweep_fits(g, kMinSegRows);
@@ -748,7 +770,7 @@ namespace {
 template <int C, int R, int TYL>
 hipError_t run_dir_batch(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, char* ws,
                          const float* taps, hipStream_t s) {
-  const size_t bytes = (size_t)DirShape<C, R, TYL>::LDS * sizeof(float);
+  const size_t bytes = (size_t)DirShape<C, R, TYL>::LDS_ALLOC * sizeof(float);
   hipError_t e = set_lds_fast(k_dir_fast_batch<C, R, TYL>, bytes);
   if (e != hipSuccess) return e;
   if (blocks == 0) return hipSuccess;  // prepare only (before a graph capture)

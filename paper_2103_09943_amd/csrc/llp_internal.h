@@ -56,9 +56,8 @@ int apply_tile(int C, int variant, int* TH, int* TW);
 
 // Kernel launchers.  All enqueue on `s` and return the launch status.  Reductions leave their partial sums in
 // `partials` and finish with a k_finalize launch.
-// G, mu, dinv as planes and, if gmd is not NULL, interleaved as (G, mu, dinv, 0) per pixel (16-byte aligned).
-hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, float4* gmd,
-                            hipStream_t s);
+// G = L Y, the window means mu of G and dinv = 1 / (var + eps / |w|), as planes.
+hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, hipStream_t s);
 hipError_t launch_check_finite(const float* a, size_t count, int* flag, hipStream_t s);
 hipError_t launch_finalize(const Geom& g, int op, const double* partials, int nblk, ChanState* st,
                            double* results, int slot, int k_iter, int max_iters, float tol, hipStream_t s);
@@ -76,10 +75,9 @@ hipError_t launch_dir(const Geom& g, const OpConfig& cfg, int mode, int final_st
                       const float* u, double* partials, ChanState* st, int max_iters, float tol, hipStream_t s);
 // mode 0: q = A z (z = p, y = D B z).  mode 1: q = A p_k and partials of the dot products; followed by
 // launch_finalize(kFinApply, nblk = apply_ntiles) for alpha_k, beta_k.
-// gmd: the interleaved statistics (launch_pan_stats), required by the split variant, otherwise unused.
 hipError_t launch_apply(const Geom& g, const OpConfig& cfg, int mode, const float* p, const float* r,
                         const float* y, const float* u, const float* G, const float* mu, const float* dinv,
-                        const float4* gmd, float* q, double* partials, ChanState* st, hipStream_t s);
+                        float* q, double* partials, ChanState* st, hipStream_t s);
 int dir_ntiles(const Geom& g, const OpConfig& cfg);
 int apply_ntiles(const Geom& g, const OpConfig& cfg);
 // After a network start: bands whose start is no better than zero restart from zero (see k_fallback).
@@ -103,7 +101,6 @@ struct SceneDesc {
   const float* u;  // kernel [n][n]
   float* x;        // HRMS [N][H][W] (the iterate)
   float *G, *MU, *DI, *b, *q, *y;
-  float4* GMD;  // (G, mu, dinv, 0) interleaved
   float* r[2];
   float* p[2];
   double* partials;  // [N][pstride][3]
@@ -115,7 +112,7 @@ struct SceneDesc {
   int seg_rows;                  // split variant: rows per sweep segment
   // The same device buffers as byte offsets from the batch workspace base: the batched kernels form their
   // pointers from the workspace base (a kernel argument, hence known to be global memory) and these offsets.
-  size_t o_x, o_r[2], o_p[2], o_q, o_y, o_G, o_MU, o_DI, o_GMD, o_partials;
+  size_t o_x, o_r[2], o_p[2], o_q, o_y, o_G, o_MU, o_DI, o_partials;
   int taps_index;                // the scene's kernel taps: taps table + taps_index * kTapStride
 };
 constexpr int kTapStride = 1024;  // floats per scene in the batch's kernel-tap table (n <= 31)

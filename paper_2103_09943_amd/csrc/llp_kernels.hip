@@ -44,8 +44,7 @@ __device__ __forceinline__ double lap64(const float* __restrict__ Y, int i, int 
 }
 
 __global__ __launch_bounds__(kBlock) void k_pan_stats(Geom g, const float* __restrict__ Y, float* __restrict__ G,
-                                                      float* __restrict__ MU, float* __restrict__ DI,
-                                                      float4* __restrict__ GMD) {
+                                                      float* __restrict__ MU, float* __restrict__ DI) {
   const size_t HW = (size_t)g.H * g.W;
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= HW) return;
@@ -69,14 +68,12 @@ __global__ __launch_bounds__(kBlock) void k_pan_stats(Geom g, const float* __res
   G[idx] = gv;
   MU[idx] = mv;
   DI[idx] = dv;
-  if (GMD) GMD[idx] = make_float4(gv, mv, dv, 0.0f);
 }
 
-hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, float4* gmd,
-                            hipStream_t s) {
+hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, float* dinv, hipStream_t s) {
   const size_t HW = (size_t)g.H * g.W;
   hipLaunchKernelGGL(k_pan_stats, dim3((unsigned)((HW + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g, Y, G, mu,
-                     dinv, gmd);
+                     dinv);
   return hipGetLastError();
 }
 

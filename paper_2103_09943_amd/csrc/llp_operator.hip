@@ -470,7 +470,7 @@ static hipError_t launch_apply_kernel(const Geom& g, const OpConfig& cfg, ApplyA
 
 hipError_t launch_apply(const Geom& g, const OpConfig& cfg, int mode, const float* p, const float* r,
                         const float* y, const float* u, const float* G, const float* mu, const float* dinv,
-                        const float4* gmd, float* q, double* partials, ChanState* st, hipStream_t s) {
+                        float* q, double* partials, ChanState* st, hipStream_t s) {
   ApplyArgs A{};
   A.mode = mode;
   A.p = p;
