@@ -89,7 +89,7 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
     lcol[ci] = valid ? (col % C) * S::PS + col / C : -1;
   }
   double acc = 0.0;
-  constexpr int RPI = 3;  // region rows per wave per iteration (their loads are in flight together)
+  constexpr int RPI = 2;  // region rows per wave per iteration (their loads are in flight together)
   for (int row_b = wave; row_b < S::RH; row_b += kWaves * RPI) {
     float rv[RPI][NCI], qv[RPI][NCI], pv[RPI][NCI], xv[RPI][NCI];
     unsigned so[RPI];
