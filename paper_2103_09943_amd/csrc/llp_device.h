@@ -22,30 +22,30 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sums K values over the block; results valid in thread 0.
-template <int K>
+// Sums K values over a block of NW waves (red: K * NW doubles of LDS); results valid in thread 0.
+template <int K, int NW = kWaves>
 __device__ __forceinline__ void block_sums(double (&v)[K], double* red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     v[k] = wave_sum(v[k]);
-    if (lane == 0) red[k * kWaves + wid] = v[k];
+    if (lane == 0) red[k * NW + wid] = v[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       double t = 0.0;
-      for (int i = 0; i < kWaves; ++i) t += red[k * kWaves + i];
+      for (int i = 0; i < NW; ++i) t += red[k * NW + i];
       v[k] = t;
     }
   }
 }
 
 // Sums K values over the workgroup and stores them at dst[0..K) (thread 0).
-template <int K>
+template <int K, int NW = kWaves>
 __device__ __forceinline__ void block_partials(double (&v)[K], double* red, double* dst) {
-  block_sums<K>(v, red);
+  block_sums<K, NW>(v, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) dst[k] = v[k];

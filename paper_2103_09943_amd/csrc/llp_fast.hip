@@ -20,15 +20,23 @@ using namespace dev;
 
 // ==================================================================================== k_dir_fast ===
 
+// Words per polyphase plane: the C planes a row of the region is dealt to must start an odd multiple of 64/C
+// banks apart, so that the 64 lanes of one LDS store hit distinct banks.
+constexpr int phase_stride(int v, int C) {
+  return ((v % 64) % (64 / C) == 0 && ((v % 64) / (64 / C)) % 2 == 1) ? v : pad_to(v, (64 / C) % 64);
+}
+
+// One LR row of the tile per wave: TYL = 4 runs 4 waves (256 threads), TYL = 8 runs 8 waves (512 threads).
 template <int C, int R, int TYL_ = 4>
 struct DirShape {
-  static constexpr int TYL = TYL_, TXL = 64;
+  static constexpr int TYL = TYL_, TXL = 64, NW = TYL_;
   static constexpr int HYR = (R + C - 1) / C;
   static constexpr int PR = TYL + 2 * HYR, PC = TXL + 2 * HYR;
-  static constexpr int PS = pad_to(PR * PC, (64 / C) % 64);  // consecutive phase planes 64/C banks apart
+  static constexpr int PS = phase_stride(PR * PC, C);
   static constexpr int RH = C * PR, RW = C * PC;
   static constexpr int LDS = C * C * PS;
   static constexpr int LDS_ALLOC = LDS + 64;  // plus one slot per lane for the stores of lanes past the region
+  static_assert(NW == 4 || NW == 8, "4 or 8 LR rows per tile");
 };
 
 // Byte offset past every plane: buffer loads from it return 0 and stores to it are dropped (the planes of the
@@ -38,9 +46,9 @@ constexpr unsigned kNoAccess = 0x80000000u;
 template <int C, int R, int TYL, int MODE>
 __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, const float* __restrict__ u, int bid) {
   using S = DirShape<C, R, TYL>;
-  constexpr int n = 2 * R + 1;
+  constexpr int n = 2 * R + 1, NW = S::NW;
   extern __shared__ float smem[];
-  __shared__ double red[kWaves];
+  __shared__ double red[NW];
   int tile, ch;
   tile_and_band(A.ntiles, g.N, bid, tile, ch);
   const int m0 = (tile / A.tiles_x) * S::TYL, k0 = (tile % A.tiles_x) * S::TXL;
@@ -90,12 +98,12 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
   }
   double acc = 0.0;
   constexpr int RPI = 2;  // region rows per wave per iteration (their loads are in flight together)
-  for (int row_b = wave; row_b < S::RH; row_b += kWaves * RPI) {
+  for (int row_b = wave; row_b < S::RH; row_b += NW * RPI) {
     float rv[RPI][NCI], qv[RPI][NCI], pv[RPI][NCI], xv[RPI][NCI];
     unsigned so[RPI];
 #pragma unroll
     for (int j = 0; j < RPI; ++j) {
-      const int row = row_b + j * kWaves;
+      const int row = row_b + j * NW;
       const int gr = row0 + row;
       so[j] = (unsigned)(wrap1(gr, H) * W) * 4u;
       const bool own_row = row >= in_r0 && row < in_r1 && gr < H;
@@ -116,7 +124,7 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
     }
 #pragma unroll
     for (int j = 0; j < RPI; ++j) {
-      const int row = row_b + j * kWaves;
+      const int row = row_b + j * NW;
       if (row >= S::RH) continue;
       const int gr = row0 + row;
       const bool own_row = row >= in_r0 && row < in_r1 && gr < H;
@@ -150,10 +158,10 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
   __syncthreads();
 
   if (!(MODE == 2 && A.final_step)) {
-    // y[m][k] = sum_{a,b} u[a][b] p[C m + R - a][C k + R - b]; rows m0 + wave and m0 + wave + 4.
+    // y[m][k] = sum_{a,b} u[a][b] p[C m + R - a][C k + R - b] on LR row m0 + wave, column k0 + lane.
     // Every tap is one LDS read at an immediate offset from the lane's base and one FMA with the tap in a
-    // scalar register.  Each lane computes TYL/4 LR points of one column.
-    constexpr int MPW = TYL / kWaves;
+    // scalar register.
+    constexpr int MPW = TYL / NW;
     const float* b0 = smem + (S::HYR + wave) * S::PC + S::HYR + lane;
     float sacc[MPW];
 #pragma unroll
@@ -167,7 +175,7 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
         const int off = cpmod(R - b, C) * S::PS + cfdiv(R - b, C);
         const float w = urow[b];
 #pragma unroll
-        for (int m = 0; m < MPW; ++m) sacc[m] = fmaf(w, rowp[off + m * kWaves * S::PC], sacc[m]);
+        for (int m = 0; m < MPW; ++m) sacc[m] = fmaf(w, rowp[off + m * NW * S::PC], sacc[m]);
       }
     }
     const int k = k0 + lane;
@@ -176,14 +184,14 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
     const unsigned ko = k < g.w ? (unsigned)k * 4u : kNoAccess;
 #pragma unroll
     for (int m = 0; m < MPW; ++m) {
-      const int mm = m0 + wave + m * kWaves;
+      const int mm = m0 + wave + m * NW;
       if (mm < g.h) st(sacc[m], Ry, ko, (unsigned)(mm * g.w) * 4u);
     }
   }
 
   if (MODE == 0) return;
   double v[1] = {acc};
-  block_partials<1>(v, red, A.partials + (size_t)ch * A.pstride * 3 + tile);
+  block_partials<1, NW>(v, red, A.partials + (size_t)ch * A.pstride * 3 + tile);
 }
 
 // ================================================================================== k_apply_fast ===
@@ -572,7 +580,7 @@ __device__ __forceinline__ void apply_fast_body(const Geom& g, const ApplyArgs& 
 // ================================================================================ kernel wrappers ===
 
 template <int C, int R, int TYL, int MODE>
-__global__ __launch_bounds__(kBlock) void k_dir_fast(Geom g, DirArgs A, const float* __restrict__ u) {
+__global__ __launch_bounds__(TYL * 64) void k_dir_fast(Geom g, DirArgs A, const float* __restrict__ u) {
   dir_fast_body<C, R, TYL, MODE>(g, A, u, blockIdx.x);
 }
 
@@ -596,7 +604,7 @@ __device__ __forceinline__ int find_scene(const SceneDesc* __restrict__ t, int c
 
 // Batched CG iteration kernels (mode 2 / mode 1 of the single-scene kernels) over a table of scenes.
 template <int C, int R, int TYL>
-__global__ __launch_bounds__(kBlock) void k_dir_fast_batch(const SceneDesc* __restrict__ t, int count, int parity,
+__global__ __launch_bounds__(TYL * 64) void k_dir_fast_batch(const SceneDesc* __restrict__ t, int count, int parity,
                                                            ChanState* __restrict__ st, char* __restrict__ ws,
                                                            const float* __restrict__ taps) {
   const int si = find_scene<true>(t, count, blockIdx.x);
@@ -665,7 +673,7 @@ hipError_t run_dir_fast_m(const Geom& g, DirArgs A, const float* u, hipStream_t 
   A.PS = S::PS;
   A.tiles_x = (g.w + S::TXL - 1) / S::TXL;
   A.ntiles = A.tiles_x * ((g.h + S::TYL - 1) / S::TYL);
-  hipLaunchKernelGGL((k_dir_fast<C, R, TYL, MODE>), dim3(A.ntiles * g.N), dim3(kBlock), bytes, s, g, A, u);
+  hipLaunchKernelGGL((k_dir_fast<C, R, TYL, MODE>), dim3(A.ntiles * g.N), dim3(S::NW * 64), bytes, s, g, A, u);
   return hipGetLastError();
 }
 
@@ -774,8 +782,8 @@ hipError_t run_dir_batch(const SceneDesc* t, int count, int blocks, int parity, 
   hipError_t e = set_lds_fast(k_dir_fast_batch<C, R, TYL>, bytes);
   if (e != hipSuccess) return e;
   if (blocks == 0) return hipSuccess;  // prepare only (before a graph capture)
-  hipLaunchKernelGGL((k_dir_fast_batch<C, R, TYL>), dim3(blocks), dim3(kBlock), bytes, s, t, count, parity, st, ws,
-                     taps);
+  hipLaunchKernelGGL((k_dir_fast_batch<C, R, TYL>), dim3(blocks), dim3(DirShape<C, R, TYL>::NW * 64), bytes, s, t,
+                     count, parity, st, ws, taps);
   return hipGetLastError();
 }
 
