@@ -1,4 +1,5 @@
-"""GPU: the split operator variant (data term per LR cell + column sweep of the LLP term) against the oracle.
+"""GPU: the column-sweep operator variant (the LLP term, and for c = 4 the data term on the matrix cores inside the
+sweep; for c = 2 a separate data-term launch) against the oracle.
 
 The variant is forced with LLP_APPLY_VARIANT=2 (and segment lengths with LLP_SEG_ROWS) so that it is exercised
 on small, ragged shapes too: strips of 52 (r = 2) or 56 (r = 1) output columns and segments of 32..96 rows,
@@ -30,14 +31,16 @@ def torch_dev():
     return torch
 
 
-def make_ctx(seg_rows):
-    os.environ["LLP_APPLY_VARIANT"] = "2"
-    os.environ["LLP_SEG_ROWS"] = str(seg_rows)
+def make_ctx(seg_rows, dir_rows=None):
+    env = {"LLP_APPLY_VARIANT": "2", "LLP_SEG_ROWS": str(seg_rows)}
+    if dir_rows is not None:
+        env["LLP_DIR_ROWS"] = str(dir_rows)
+    os.environ.update(env)
     try:
         return B.Context(0)
     finally:
-        del os.environ["LLP_APPLY_VARIANT"]
-        del os.environ["LLP_SEG_ROWS"]
+        for k in env:
+            del os.environ[k]
 
 
 @pytest.fixture(scope="module", params=[32, 96])
@@ -68,6 +71,8 @@ SHAPES = [  # N, h, w, c, n, r  (H = c h >= 3 (2r + 2) rows)
     (1, 9, 33, 4, 15, 1),     # W = 132: 3 strips, the last one ragged
     (5, 40, 16, 4, 17, 2),    # five bands: two waves of a workgroup idle
     (2, 64, 64, 4, 9, 1),
+    (2, 20, 24, 4, 13, 1),    # n 13: the c = 4 classes with a 4 x 4 y neighbourhood
+    (1, 16, 20, 4, 29, 2),    # n 29: an 8 x 8 neighbourhood, 16 K steps of the matrix-core product
 ]
 
 
@@ -116,3 +121,22 @@ def test_sweep_batch_matches_single(torch_dev):
         for (X, Y, u), Z, rs in zip(ds, outs, reps):
             Zs, rs_s, _ = ctx.pansharpen(X, Y, u, **kw)
             assert torch_dev.equal(Z, Zs) and rs == rs_s
+
+
+@pytest.mark.parametrize("shape", [(2, 40, 40, 4, 17, 2), (1, 48, 36, 4, 9, 1), (2, 40, 40, 2, 9, 1)])
+def test_eight_row_update_tiles(torch_dev, shape):
+    """The update kernel's 8-row tiles (8 waves of 512 threads, one LR row each): the CG iterate after a fixed
+    count matches the oracle, and the batched launch reproduces the single-scene one bit for bit."""
+    N, h, w, c, n, r = shape
+    rng = np.random.default_rng(np.random.SeedSequence([63, *shape]))
+    X, Y, u, _ = scenes.random_problem(rng, N, h * c, w * c, c, n)
+    lam, eps = 0.05, 1e-2
+    d = tuple(dev(torch_dev, a) for a in (X, Y, u))
+    with make_ctx(32, dir_rows=8) as ctx:
+        Z, _, _ = ctx.pansharpen(*d, r=r, lam=lam, eps=eps, max_iters=20, tol=0.0)
+        outs, _, _ = ctx.pansharpen_batch([d, d], r=r, lam=lam, eps=eps, max_iters=20, tol=0.0)
+    prob = Problem(u=u, c=c, Y=Y, r=r, lam=f32(lam), eps=f32(eps))
+    want, _ = oracle.cg(prob, oracle.rhs(X, prob), max_iters=20)
+    assert np.all(rel_l2(host(Z), want) < 1e-5)
+    for o in outs:
+        assert torch_dev.equal(o, Z)
