@@ -1,6 +1,6 @@
 """Train the warm-start network on the GPU and measure what it saves.
 
-    python -m paper_2103_09943_amd.train_cnn [--train 2000] [--eval 500] [--epochs 6] [--out PATH]
+    python -m paper_2103_09943_amd.train_cnn [--train 2000] [--eval 500] [--epochs 40] [--lr 2e-3] [--out PATH]
 
 1. Synthetic training scenes (4 bands, 256^2 PAN, the batch workload's blur recipe) and their plain-solver HRMS
    (cold start, tolerance 1e-6) as targets.
@@ -88,8 +88,8 @@ def main():
     ap.add_argument("--eval", type=int, default=500)
     ap.add_argument("--train-side", type=int, default=None)
     ap.add_argument("--eval-side", type=int, default=None)
-    ap.add_argument("--epochs", type=int, default=6)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--chunk", type=int, default=128, help="scenes per batched solve")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--out", default=DEFAULT_OUT)
