@@ -21,6 +21,12 @@
 #include "llp_device.h"
 
 namespace llp {
+
+// Periodic index for -n <= i < 2n by one conditional add or subtract (no division); pos_mod otherwise.
+__device__ __forceinline__ int wrap_p(int i, int n) {
+  if (i >= -n && i < 2 * n) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return dev::pos_mod(i, n);
+}
 using namespace dev;
 
 namespace {
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_input(CnnGeom g, const float* __rest
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   const int band = blockIdx.y;
   if (idx >= HW) return;
-  const int i = (int)(idx / g.W), j = (int)(idx % g.W);
+  const int i = (int)idx / g.W, j = (int)idx - i * g.W;  // H W < 2^31
   const int mi = i / g.c, mj = j / g.c;
   const float ti = (float)(i - mi * g.c) / (float)g.c, tj = (float)(j - mj * g.c) / (float)g.c;
   float wy[4], wx[4];
@@ -116,10 +122,10 @@ __global__ __launch_bounds__(kBlock) void k_input(CnnGeom g, const float* __rest
   float v = 0.0f;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int r = pos_mod(mi + a - 1, g.h);
+    const int r = wrap_p(mi + a - 1, g.h);
     float rs = 0.0f;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rs = fmaf(wx[b], Xb[(size_t)r * g.w + pos_mod(mj + b - 1, g.w)], rs);
+    for (int b = 0; b < 4; ++b) rs = fmaf(wx[b], Xb[(size_t)r * g.w + wrap_p(mj + b - 1, g.w)], rs);
     v = fmaf(wy[a], rs, v);
   }
   xup[(size_t)band * HW + idx] = v;
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_conv(CnnGeom g, const uint16_t* __re
   for (int k = threadIdx.x; k < (kTileRows + 2) * (kTileW + 2) * 4; k += kBlock) {
     const int pix = k >> 2, part = k & 3;
     const int lr = pix / (kTileW + 2), lc = pix % (kTileW + 2);
-    const int sr = pos_mod(row0 + lr - 1, H), sc = pos_mod(col0 + lc - 1, W);
+    const int sr = wrap_p(row0 + lr - 1, H), sc = wrap_p(col0 + lc - 1, W);
     *(u32x4*)&tile[lr][lc][part * 8] = *(const u32x4*)(inb + ((size_t)sr * W + sc) * kCh + part * 8);
   }
   __syncthreads();
@@ -291,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_wgrad(CnnGeom g, const uint16_t* __r
     for (int k = threadIdx.x; k < kAR * (kGC + 2) * 4; k += kBlock) {
       const int pix = k >> 2, part8 = k & 3;
       const int lr = pix / (kGC + 2), lc = pix % (kGC + 2);
-      const int rr = pos_mod(r0 + lr - 1, H), cc = pos_mod(c0 + lc - 1, W);
+      const int rr = wrap_p(r0 + lr - 1, H), cc = wrap_p(c0 + lc - 1, W);
       const u32x4 v = *(const u32x4*)(ib + ((size_t)rr * W + cc) * kCh + part8 * 8);
       const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
