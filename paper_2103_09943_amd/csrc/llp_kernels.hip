@@ -14,6 +14,12 @@ using namespace dev;
 
 constexpr int kChunk = kBlock * 16;  // elements per workgroup in the flat kernels
 
+// Periodic index: one conditional add or subtract for -n <= i < 2n (the usual case), a true modulo otherwise.
+__device__ __forceinline__ int wrapc(int i, int n) {
+  if (i >= -n && i < 2 * n) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return wrapi(i, n);
+}
+
 // ---------------------------------------------------------------------------------- input checks ---
 
 __global__ __launch_bounds__(kBlock) void k_check_finite(const float* __restrict__ a, size_t count,
@@ -48,14 +54,14 @@ __global__ __launch_bounds__(kBlock) void k_pan_stats(Geom g, const float* __res
   const size_t HW = (size_t)g.H * g.W;
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= HW) return;
-  const int ki = (int)(idx / g.W), kj = (int)(idx % g.W);
+  const int ki = (int)idx / g.W, kj = (int)idx - ki * g.W;  // H W < 2^31
   const int r = g.r;
   const double nw = (double)((2 * r + 1) * (2 * r + 1));
   double s1 = 0.0, s2 = 0.0;
   for (int dy = -r; dy <= r; ++dy) {
-    const int i = wrapi(ki + dy, g.H);
+    const int i = wrapc(ki + dy, g.H);
     for (int dx = -r; dx <= r; ++dx) {
-      const double v = lap64(Y, i, wrapi(kj + dx, g.W), g.H, g.W);
+      const double v = lap64(Y, i, wrapc(kj + dx, g.W), g.H, g.W);
       s1 += v;
       s2 += v * v;
     }
@@ -179,30 +185,49 @@ hipError_t launch_finalize(const Geom& g, int op, const double* partials, int nb
 // b = B^T D^T X: the low-resolution sample X[m][k] sits at (c m, c k); B^T correlates with u, so
 // b[i][j] = sum over taps (a, b') with (i + a - R) = c m and (j + b' - R) = c k of u[a][b'] X[m][k].
 
+// b = B^T D^T X and the partial sums of |b|^2.  One workgroup per 32 x 128 block of HR pixels; the LR region of X
+// its taps reach is staged in LDS once.  Per pixel the taps run in the same order as in a direct loop.
+constexpr int kRhsTH = 32, kRhsTW = 128;
+
+__host__ __device__ __forceinline__ int rhs_lr_count(int t, int R, int c) {  // LR rows (columns) t rows reach
+  return (t - 1 + 2 * R) / c + 2;
+}
+
 __global__ __launch_bounds__(kBlock) void k_rhs(Geom g, const float* __restrict__ X, const float* __restrict__ u,
                                                 float* __restrict__ b, double* __restrict__ partials,
                                                 int pstride) {
+  extern __shared__ float rhs_sh[];
   __shared__ double red[kWaves];
   const int ch = blockIdx.y;
+  const int c = g.c, n = g.n, R = g.R;
   const size_t HW = (size_t)g.H * g.W;
   const float* Xc = X + (size_t)ch * g.h * g.w;
   float* bc = b + (size_t)ch * HW;
+  const int tiles_x = (g.W + kRhsTW - 1) / kRhsTW;
+  const int i0 = (int)(blockIdx.x / tiles_x) * kRhsTH, j0 = (int)(blockIdx.x % tiles_x) * kRhsTW;
+  // LR rows floor((i0 - R) / c) ..; LR columns likewise
+  const int mlo = floor_div(i0 - R, c), klo = floor_div(j0 - R, c);
+  const int LH = rhs_lr_count(kRhsTH, R, c), LW = rhs_lr_count(kRhsTW, R, c);
+  for (int idx = threadIdx.x; idx < LH * LW; idx += kBlock) {
+    const int li = idx / LW, lj = idx - li * LW;
+    rhs_sh[idx] = Xc[(size_t)wrapc(mlo + li, g.h) * g.w + wrapc(klo + lj, g.w)];
+  }
+  __syncthreads();
   double acc = 0.0;
-  const size_t e0 = (size_t)blockIdx.x * kChunk;
-  const size_t e1 = e0 + kChunk < HW ? e0 + kChunk : HW;
-  for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-    const int i = (int)(e / g.W), j = (int)(e % g.W);
-    const int a0 = wrapi(g.R - i, g.c), b0 = wrapi(g.R - j, g.c);
+  for (int p = threadIdx.x; p < kRhsTH * kRhsTW; p += kBlock) {
+    const int pi = p / kRhsTW, pj = p - pi * kRhsTW;
+    const int i = i0 + pi, j = j0 + pj;
+    if (i >= g.H || j >= g.W) continue;
+    const int a0 = wrapi(R - i, c), b0 = wrapi(R - j, c);
+    // i + a - R and j + b - R are multiples of c on the taps visited: the LR indices step by one per tap
+    const int m0 = (i + a0 - R) / c - mlo, k0 = (j + b0 - R) / c - klo;
     double v = 0.0;
-    for (int a = a0; a < g.n; a += g.c) {
-      const int m = wrapi((i + a - g.R) / g.c, g.h);
-      for (int bb = b0; bb < g.n; bb += g.c) {
-        const int k = wrapi((j + bb - g.R) / g.c, g.w);
-        v += (double)u[a * g.n + bb] * (double)Xc[(size_t)m * g.w + k];
-      }
+    for (int a = a0, m = m0; a < n; a += c, ++m) {
+      const float* xrow = rhs_sh + m * LW;
+      for (int bb = b0, k = k0; bb < n; bb += c, ++k) v += (double)u[a * n + bb] * (double)xrow[k];
     }
     const float vf = (float)v;
-    bc[e] = vf;
+    bc[(size_t)i * g.W + j] = vf;
     acc += (double)vf * (double)vf;
   }
   double v[1] = {acc};
@@ -211,10 +236,11 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geom g, const float* __restrict_
 
 hipError_t launch_rhs(const Geom& g, const float* X, const float* u, float* b, double* partials, ChanState* st,
                       hipStream_t s) {
-  const size_t HW = (size_t)g.H * g.W;
-  const int nblk = (int)((HW + kChunk - 1) / kChunk);
+  // blocks of 32 x 128 pixels: no more than the operator's 16 x 64 tiles, so within the partials per band
+  const int nblk = ((g.H + kRhsTH - 1) / kRhsTH) * ((g.W + kRhsTW - 1) / kRhsTW);
   const int pstride = (int)max_partials_per_band(g);
-  hipLaunchKernelGGL(k_rhs, dim3(nblk, g.N), dim3(kBlock), 0, s, g, X, u, b, partials, pstride);
+  const size_t lds = (size_t)rhs_lr_count(kRhsTH, g.R, g.c) * rhs_lr_count(kRhsTW, g.R, g.c) * sizeof(float);
+  hipLaunchKernelGGL(k_rhs, dim3(nblk, g.N), dim3(kBlock), lds, s, g, X, u, b, partials, pstride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finalize(g, kFinBnorm, partials, nblk, st, nullptr, 0, 0, 0, 0.0f, s);
@@ -321,25 +347,38 @@ hipError_t launch_residual_norm(const Geom& g, const float* b, const float* q, d
 // (l_i - a G_i - c)^2 + eps a^2] with l = L z (eq. pansharp with the per-window optimum; equal to
 // (L z)^T M_LY (L z) of eq. initialize_z_fast).  Every term is a sum of squares accumulated in FP64.
 
+// Data part of the objective: sum over LR cells of (D B z - X)^2.  One workgroup per block of LR cells covering
+// about 32 x 128 HR pixels (32/c x 128/c cells); the z region the block's taps reach is staged in LDS once.
 __global__ __launch_bounds__(kBlock) void k_obj_data(Geom g, const float* __restrict__ z, const float* __restrict__ X,
                                                      const float* __restrict__ u, double* __restrict__ partials,
                                                      int pstride) {
+  extern __shared__ float objd_sh[];
   __shared__ double red[kWaves];
   const int ch = blockIdx.y;
-  const size_t hw = (size_t)g.h * g.w;
+  const int c = g.c, n = g.n, R = g.R;
+  const int TM = 32 / c, TK = 128 / c;
+  const int RH = c * TM + n - 1, RW = c * TK + n - 1;
+  const int tiles_x = (g.w + TK - 1) / TK;
+  const int m0 = (int)(blockIdx.x / tiles_x) * TM, k0 = (int)(blockIdx.x % tiles_x) * TK;
   const float* zc = z + (size_t)ch * g.H * g.W;
+  // region rows c m0 - R .. c (m0 + TM - 1) + R, columns likewise
+  const int r0 = c * m0 - R, q0 = c * k0 - R;
+  for (int idx = threadIdx.x; idx < RH * RW; idx += kBlock) {
+    const int li = idx / RW, lj = idx - li * RW;
+    objd_sh[idx] = zc[(size_t)wrapc(r0 + li, g.H) * g.W + wrapc(q0 + lj, g.W)];
+  }
+  __syncthreads();
   double acc = 0.0;
-  const size_t e0 = (size_t)blockIdx.x * kChunk;
-  const size_t e1 = e0 + kChunk < hw ? e0 + kChunk : hw;
-  for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-    const int m = (int)(e / g.w), k = (int)(e % g.w);
+  for (int p = threadIdx.x; p < TM * TK; p += kBlock) {
+    const int pm = p / TK, pk = p - pm * TK;
+    const int m = m0 + pm, k = k0 + pk;
+    if (m >= g.h || k >= g.w) continue;
     double v = 0.0;
-    for (int a = 0; a < g.n; ++a) {
-      const size_t row = (size_t)wrapi(g.c * m + g.R - a, g.H) * g.W;
-      for (int b = 0; b < g.n; ++b)
-        v += (double)u[a * g.n + b] * (double)zc[row + wrapi(g.c * k + g.R - b, g.W)];
+    for (int a = 0; a < n; ++a) {
+      const float* zrow = objd_sh + (c * pm + 2 * R - a) * RW + c * pk + 2 * R;  // row c m + R - a, column c k + R
+      for (int b = 0; b < n; ++b) v += (double)u[a * n + b] * (double)zrow[-b];
     }
-    const double d = v - (double)X[(size_t)ch * hw + e];
+    const double d = v - (double)X[(size_t)ch * g.h * g.w + (size_t)m * g.w + k];
     acc += d * d;
   }
   double v[1] = {acc};
@@ -353,40 +392,57 @@ __device__ __forceinline__ double lapz(const float* __restrict__ z, int i, int j
          (double)z[(size_t)i * W + jm] - (double)z[(size_t)i * W + jp];
 }
 
+// LLP part of the objective per window k (Levin's form): sum over the window of (l_i - a_k G_i - c_k)^2 plus
+// eps a_k^2, with l = L z and (a_k, c_k) the window's least-squares coefficients.  One workgroup per tile of
+// kObjTH x kObjTW windows: l (FP64) and G over the tile and its r-halo are staged in LDS once.
+constexpr int kObjTH = 32, kObjTW = 64;
+
 __global__ __launch_bounds__(kBlock) void k_obj_llp(Geom g, const float* __restrict__ z, const float* __restrict__ G,
                                                     const float* __restrict__ MU, const float* __restrict__ DI,
                                                     double* __restrict__ partials, int pstride) {
+  extern __shared__ double obj_sh[];
   __shared__ double red[kWaves];
   const int ch = blockIdx.y;
-  const size_t HW = (size_t)g.H * g.W;
+  const int H = g.H, W = g.W, r = g.r;
+  const size_t HW = (size_t)H * W;
   const float* zc = z + (size_t)ch * HW;
-  const int r = g.r;
+  const int EH = kObjTH + 2 * r, EW = kObjTW + 2 * r;
+  double* Ls = obj_sh;
+  float* Gs = (float*)(obj_sh + EH * EW);
+  const int tiles_x = (W + kObjTW - 1) / kObjTW;
+  const int i0 = (int)(blockIdx.x / tiles_x) * kObjTH, j0 = (int)(blockIdx.x % tiles_x) * kObjTW;
+  for (int idx = threadIdx.x; idx < EH * EW; idx += kBlock) {
+    const int li = idx / EW, lj = idx - li * EW;
+    const int i = wrapc(i0 - r + li, H), j = wrapc(j0 - r + lj, W);
+    Ls[idx] = lapz(zc, i, j, H, W);
+    Gs[idx] = G[(size_t)i * W + j];
+  }
+  __syncthreads();
   const double nw = (double)((2 * r + 1) * (2 * r + 1));
   double acc = 0.0;
-  const size_t e0 = (size_t)blockIdx.x * kChunk;
-  const size_t e1 = e0 + kChunk < HW ? e0 + kChunk : HW;
-  for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-    const int ki = (int)(e / g.W), kj = (int)(e % g.W);
+  for (int p = threadIdx.x; p < kObjTH * kObjTW; p += kBlock) {
+    const int pi = p / kObjTW, pj = p - pi * kObjTW;
+    const int ki = i0 + pi, kj = j0 + pj;
+    if (ki >= H || kj >= W) continue;
     double sl = 0.0, sgl = 0.0;
     for (int dy = -r; dy <= r; ++dy) {
-      const int i = wrapi(ki + dy, g.H);
+      const int rowo = (pi + r + dy) * EW + pj + r;
       for (int dx = -r; dx <= r; ++dx) {
-        const int j = wrapi(kj + dx, g.W);
-        const double l = lapz(zc, i, j, g.H, g.W);
+        const double l = Ls[rowo + dx];
         sl += l;
-        sgl += (double)G[(size_t)i * g.W + j] * l;
+        sgl += (double)Gs[rowo + dx] * l;
       }
     }
+    const size_t e = (size_t)ki * W + kj;
     const double mu = MU[e], di = DI[e];
     const double m1 = sl / nw, m2 = sgl / nw;
     const double a = (m2 - mu * m1) * di;
     const double cc = m1 - a * mu;
     double pen = (double)g.eps * a * a;
     for (int dy = -r; dy <= r; ++dy) {
-      const int i = wrapi(ki + dy, g.H);
+      const int rowo = (pi + r + dy) * EW + pj + r;
       for (int dx = -r; dx <= r; ++dx) {
-        const int j = wrapi(kj + dx, g.W);
-        const double res = lapz(zc, i, j, g.H, g.W) - a * (double)G[(size_t)i * g.W + j] - cc;
+        const double res = Ls[rowo + dx] - a * (double)Gs[rowo + dx] - cc;
         pen += res * res;
       }
     }
@@ -400,15 +456,19 @@ hipError_t launch_objective(const Geom& g, const float* z, const float* X, const
                             const float* mu, const float* dinv, double* partials, ChanState* st, double* results,
                             hipStream_t s) {
   const int pstride = (int)max_partials_per_band(g);
-  const size_t hw = (size_t)g.h * g.w, HW = (size_t)g.H * g.W;
-  const int nb1 = (int)((hw + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_obj_data, dim3(nb1, g.N), dim3(kBlock), 0, s, g, z, X, u, partials, pstride);
+  // blocks of about 32 x 128 HR pixels: no more than the operator's 16 x 64 tiles, so within the partials
+  const int TM = 32 / g.c, TK = 128 / g.c;
+  const int nb1 = ((g.h + TM - 1) / TM) * ((g.w + TK - 1) / TK);
+  const size_t lds1 = (size_t)(g.c * TM + g.n - 1) * (g.c * TK + g.n - 1) * sizeof(float);
+  hipLaunchKernelGGL(k_obj_data, dim3(nb1, g.N), dim3(kBlock), lds1, s, g, z, X, u, partials, pstride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = launch_finalize(g, kFinResult, partials, nb1, st, results, kSlotObjData, 0, 0, 0.0f, s);
   if (e != hipSuccess) return e;
-  const int nb2 = (int)((HW + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_obj_llp, dim3(nb2, g.N), dim3(kBlock), 0, s, g, z, G, mu, dinv, partials, pstride);
+  // tiles of 32 x 64 windows: no more than the operator's 16 x 64 tiles, so within the partials per band
+  const int nb2 = ((g.H + kObjTH - 1) / kObjTH) * ((g.W + kObjTW - 1) / kObjTW);
+  const size_t lds = (size_t)(kObjTH + 2 * g.r) * (kObjTW + 2 * g.r) * (sizeof(double) + sizeof(float));
+  hipLaunchKernelGGL(k_obj_llp, dim3(nb2, g.N), dim3(kBlock), lds, s, g, z, G, mu, dinv, partials, pstride);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finalize(g, kFinResult, partials, nb2, st, results, kSlotObjLlp, 0, 0, 0.0f, s);
