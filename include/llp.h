@@ -90,7 +90,7 @@ typedef struct llp_ctx llp_ctx;
 /* Create a context bound to HIP device `device`.  *out receives the handle.  If the environment variable
  * LLP_FORCE_GENERIC is set (and not "0") at creation, the context uses only the generic kernels (no
  * specialisation on kernel size, scale and window radius); results agree to rounding.  LLP_DIR_ROWS (4, 8),
- * LLP_APPLY_VARIANT (0: 32x64 tiles, 1: 16x64 tiles, 2: split data term + column sweep) and LLP_SEG_ROWS
+ * LLP_APPLY_VARIANT (0: 32x64 tiles, 1: 16x64 tiles, 2: column sweep) and LLP_SEG_ROWS
  * (rows per sweep segment, >= 32, rounded down to a multiple of 4) force a launch configuration of the
  * specialised kernels instead of the tuned or default one. */
 llp_status llp_create(llp_ctx** out, int device);
@@ -153,7 +153,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
 typedef struct {
   int fast;                   /* 1: kernels specialised on (c, n, r); 0: generic kernels */
   int dir_rows;               /* LR rows per tile of the update kernel (4 or 8) */
-  int apply_variant;          /* operator kernel: 0 32x64 tiles, 1 16x64 tiles, 2 split (data term + sweep) */
+  int apply_variant;          /* operator kernel: 0 32x64 tiles, 1 16x64 tiles, 2 column sweep */
   int seg_rows;               /* rows per sweep segment (apply_variant 2) */
   double us_per_iter;         /* measured time of one CG iteration (both kernels, all bands) with that choice */
   double default_us_per_iter; /* the same for the untuned default choice */

@@ -35,7 +35,7 @@ struct BatchClass {
   int C, R, r, dir_rows, variant;
   int first, count;
   int dir_blocks, apply_blocks;
-  int data_blocks;  // split variant: k_data workgroups
+  int data_blocks;  // column sweep, c = 2: k_data workgroups
 };
 
 llp_status ensure_batch_mirrors(llp_ctx* ctx, int bands, int scenes) {

@@ -78,7 +78,7 @@ struct llp_ctx {
   bool allow_fast = true;  // false when LLP_FORCE_GENERIC is set at creation: generic kernels only
   int want_dir_rows = 0;   // launch-shape overrides (0: default), from LLP_DIR_ROWS / LLP_APPLY_VARIANT
   int want_apply_variant = -1;
-  int want_seg_rows = 0;  // LLP_SEG_ROWS: rows per sweep segment of the split variant (>= kMinSegRows)
+  int want_seg_rows = 0;  // LLP_SEG_ROWS: rows per segment of the column sweep (>= kMinSegRows)
   void* ws = nullptr;
   size_t ws_bytes = 0;
   // views into ws

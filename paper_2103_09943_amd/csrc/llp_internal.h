@@ -38,8 +38,8 @@ struct OpConfig {
   int fast;           // 1: kernels specialised on (c, R, r) (fast_path_available), 0: generic kernels
   int dir_rows;       // generic k_dir: LR rows per tile, 4 or 8 (64 LR columns)
   int apply_variant;  // k_apply tile shape index: generic 0 .. kApplyVariants-1 (apply_tile()); fast 0: 32x64,
-                      // 1: 16x64, 2: split (k_data + the column sweep k_llp, see llp_sweep.hip)
-  int seg_rows;       // split variant: rows per sweep segment
+                      // 1: 16x64, 2: the column sweep k_llp (llp_sweep.hip)
+  int seg_rows;       // column sweep: rows per segment
 };
 constexpr int kSweepVariant = 2;
 constexpr int kMinSegRows = 32;  // shortest sweep segment the partial-sum buffers are sized for
@@ -108,8 +108,8 @@ struct SceneDesc {
   int band0;                  // first band of the scene in the batch's band-state array
   int dir_ntiles, apply_ntiles;
   int dir_block0, apply_block0;  // first workgroup of the scene in its class's k_dir / k_apply launch
-  int data_block0;               // split variant: first workgroup of the scene in its class's k_data launch
-  int seg_rows;                  // split variant: rows per sweep segment
+  int data_block0;               // column sweep, c = 2: first workgroup of the scene in its class's k_data launch
+  int seg_rows;                  // column sweep: rows per segment
   // The same device buffers as byte offsets from the batch workspace base: the batched kernels form their
   // pointers from the workspace base (a kernel argument, hence known to be global memory) and these offsets.
   size_t o_x, o_r[2], o_p[2], o_q, o_y, o_G, o_MU, o_DI, o_partials;
@@ -117,9 +117,9 @@ struct SceneDesc {
 };
 constexpr int kTapStride = 1024;  // floats per scene in the batch's kernel-tap table (n <= 31)
 
-// Split variant of q = A p (llp_sweep.hip): q_D = B^T D^T y (k_data), then q = q_D + lambda L^T M L p and, in
-// mode 1, the dot products (k_llp); apply_ntiles() partials per band.  For the classes of sweep_fused() the
-// sweep forms q_D itself and there is no k_data launch.  Segments are multiples of 4 rows.
+// Column-sweep variant of q = A p (llp_sweep.hip): q_D = B^T D^T y (k_data), then q = q_D + lambda L^T M L p
+// and, in mode 1, the dot products (k_llp); apply_ntiles() partials per band.  For the classes of sweep_fused()
+// the sweep forms q_D itself and there is no k_data launch.  Segments are multiples of 4 rows.
 bool sweep_fused(int C, int R);
 bool sweep_fits(const Geom& g, int seg_rows);
 int sweep_ntiles(const Geom& g, int seg_rows);
