@@ -180,10 +180,11 @@ llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* 
  * difference of the wall time of batched solves of 2 iters and of iters iterations (the fastest of three each,
  * after an untimed solve), and the fastest is kept as the class's batched entry, unless it is less than 3%
  * faster than the common batched shape (column sweep, 4-row update tiles, 64-row segments at r = 1), which
- * keeps scenes of different sizes in shared launches.  LLP_E_UNSUPPORTED if no specialised kernel fits the geometry (no specialised
- * kernels for (c, n, r), or an image narrower or lower than their tiles): such scenes are never batched.  0 <= copies <= 256; 1 <= iters <= 1000, rounded up to a multiple of 8 (batched solves iterate in
- * chunks of 8).  Allocates and frees copies * N*H*W floats of output
- * scratch.  Synchronises `stream`. */
+ * keeps scenes of different sizes in shared launches.  LLP_E_UNSUPPORTED if no specialised kernel fits the
+ * geometry (no specialised kernels for (c, n, r), or an image narrower or lower than their tiles): such scenes
+ * are never batched.  0 <= copies <= 256; 1 <= iters <= 1000, rounded up to a multiple of 8 (batched solves
+ * iterate in chunks of 8).  Allocates and frees copies * N*H*W floats of output scratch.  Synchronises
+ * `stream`. */
 llp_status llp_autotune_batch(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
                               const float* pan, const float* kernel, int copies, int iters, llp_tune_result* out,
                               hipStream_t stream);

@@ -527,8 +527,10 @@ hipError_t launch_apply_sweep_batch(const SceneDesc* table, int count, int data_
   if (llp_blocks > 0) {
     const dim3 grid(llp_blocks);
     if (!fused) {
-      if (r == 1) hipLaunchKernelGGL((k_llp_batch<1, 0, 0>), grid, dim3(kBlock), 0, s, table, count, parity, st, ws, taps);
-      else if (r == 2) hipLaunchKernelGGL((k_llp_batch<2, 0, 0>), grid, dim3(kBlock), 0, s, table, count, parity, st, ws, taps);
+      if (r == 1)
+        hipLaunchKernelGGL((k_llp_batch<1, 0, 0>), grid, dim3(kBlock), 0, s, table, count, parity, st, ws, taps);
+      else if (r == 2)
+        hipLaunchKernelGGL((k_llp_batch<2, 0, 0>), grid, dim3(kBlock), 0, s, table, count, parity, st, ws, taps);
       else return hipErrorInvalidValue;
     } else {
 #define LLP_LLPB_CASE(CC, RR, rr)                                                                              \
