@@ -318,7 +318,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the per-band solves would shard "
-              "across GPUs with no communication, but this build runs on one device.", file=sys.stderr)
+              "across GPUs with no communication, but this program runs on one device.", file=sys.stderr)
         sys.exit(2)
     if args.workload != "scene":
         return main_batch(args)

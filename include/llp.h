@@ -43,7 +43,7 @@ typedef enum {
   LLP_NOT_CONVERGED = 1,  /* tolerance not reached within max_iters; output is the last iterate */
   LLP_E_ARG = -1,         /* NULL pointer or parameter out of range */
   LLP_E_SHAPE = -2,       /* inconsistent sizes (n even, n > min(H, W), 2r+1 > min(H, W), ...) */
-  LLP_E_UNSUPPORTED = -3, /* valid but beyond this build's limits (see LLP_MAX_*) */
+  LLP_E_UNSUPPORTED = -3, /* valid but beyond the library's limits (see LLP_MAX_*) */
   LLP_E_HIP = -4,         /* a HIP runtime call failed */
   LLP_E_OOM = -5,         /* workspace allocation failed */
   LLP_E_BREAKDOWN = -6,   /* p^T A p <= 0 or not finite in some band: A is not positive definite */
@@ -101,7 +101,7 @@ void llp_destroy(llp_ctx* ctx);
 /* Static description of a status code. */
 const char* llp_status_str(int status);
 
-/* Host-only check of a problem description against the rules above and this build's limits (no device
+/* Host-only check of a problem description against the rules above and the library's limits (no device
  * work, no context needed).  `params` may be NULL to check the shape alone.  Returns LLP_OK or the error that
  * llp_pansharpen would return for these arguments. */
 llp_status llp_validate(const llp_shape* shape, const llp_params* params);
@@ -131,8 +131,8 @@ llp_status llp_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params
  * the update kernel per class of scenes that share (c, n, r) and a tile shape, plus two launches that finish
  * the per-band reductions, and a band that meets its stopping rule stops while the others go on.  Chunks of
  * iterations are captured once in a HIP graph and replayed (cached in the context while the classes and the
- * workspace stay the same).  Scenes without specialised kernels (llp_validate accepts them, but their
- * (c, n, r) has no specialised kernels in this build) are solved after the batch with llp_pansharpen.
+ * workspace stay the same).  Scenes whose (c, n, r) has no specialised kernels (llp_validate accepts them)
+ * are solved after the batch with llp_pansharpen.
  *   S        number of scenes, >= 0 (0: nothing to do, LLP_OK)
  *   shapes   host array [S]; params: ONE llp_params for all scenes (host)
  *   lrms, pan, kernel, hrms   host arrays [S] of device pointers, laid out as for llp_pansharpen

@@ -353,7 +353,7 @@ const char* llp_status_str(int status) {
     case LLP_NOT_CONVERGED: return "tolerance not reached within max_iters";
     case LLP_E_ARG: return "invalid argument";
     case LLP_E_SHAPE: return "inconsistent shape";
-    case LLP_E_UNSUPPORTED: return "unsupported size for this build";
+    case LLP_E_UNSUPPORTED: return "unsupported size for this library";
     case LLP_E_HIP: return "HIP runtime error";
     case LLP_E_OOM: return "out of device memory";
     case LLP_E_BREAKDOWN: return "CG breakdown: p^T A p <= 0 or not finite";

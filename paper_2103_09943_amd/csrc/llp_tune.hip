@@ -32,7 +32,7 @@ namespace {
 constexpr int kRuns = 3;            // timed runs per candidate
 constexpr double kMargin = 0.97;    // a candidate replaces the default only if at least 3% faster
 
-// Every launch configuration that fits this build's kernels and the LDS: the specialised kernels' shapes when
+// Every launch configuration that fits the library's kernels and the LDS: the specialised kernels' shapes when
 // (c, R, r) has them, otherwise the generic kernels' shapes.
 std::vector<OpConfig> candidates(const Geom& g, bool allow_fast) {
   std::vector<OpConfig> out;
