@@ -19,10 +19,14 @@ from .llp import (  # noqa: F401
     decimate_adjoint,
     kernel_otf,
     laplacian,
+    laplacian_symbol,
     matting_apply,
+    matting_diag_mean,
     matting_stats,
     objective,
     objective_levin,
+    pcg,
+    precond_apply,
     rhs,
     solve,
     window_sum,

@@ -167,3 +167,65 @@ def test_training_target_inverts_warm_start():
     t = cnn.training_target(X, Z, 4)
     _, s = cnn.band_stats(X)
     np.testing.assert_allclose(cnn.bicubic(X, 4) + s * t[0], Z, atol=1e-12)
+
+
+def test_adam_constant_gradient_closed_form_over_steps():
+    """With the same gradient g at every step, Adam's bias corrections make m_hat = g and v_hat = g^2 exactly
+    (Kingma and Ba, Sec. 3), so every step moves a parameter by lr * g / (|g| + eps).  A wrong bias correction or
+    moment update at t >= 2 breaks this."""
+    r = rng(20)
+    p0 = [(r.standard_normal((2, 1, 3, 3)), r.standard_normal(2))]
+    g = [(r.standard_normal((2, 1, 3, 3)), r.standard_normal(2))]
+    lr, eps = 3e-3, 1e-8
+    params, state = p0, (0, [], [])
+    for t in range(1, 6):
+        params, state = cnn.adam_step(params, g, state, lr, eps=eps)
+        assert state[0] == t
+        for k in range(2):
+            want = p0[0][k] - t * lr * g[0][k] / (np.abs(g[0][k]) + eps)
+            np.testing.assert_allclose(params[0][k], want, rtol=0, atol=1e-13)
+
+
+def test_adam_three_steps_hand_unrolled():
+    """Three Adam steps on scalars, written out from the update rule: gradients 0.5, 0 (a zero-gradient step),
+    -2.  Each moment and bias correction is evaluated by hand below."""
+    lr, b1, b2, eps = 0.1, 0.9, 0.999, 1e-8
+    params = [(np.array([1.0]), np.array([-3.0]))]
+    gs = [0.5, 0.0, -2.0]
+    state = (0, [], [])
+    for gv in gs:
+        params, state = cnn.adam_step(params, [(np.array([gv]), np.array([2 * gv]))], state, lr)
+    # weight: g = 0.5, 0, -2
+    m1, v1 = 0.1 * 0.5, 0.001 * 0.25
+    x1 = 1.0 - lr * (m1 / 0.1) / (np.sqrt(v1 / 0.001) + eps)           # = 1 - 0.1 * 0.5/0.5
+    m2, v2 = 0.9 * m1, 0.999 * v1
+    x2 = x1 - lr * (m2 / (1 - 0.81)) / (np.sqrt(v2 / (1 - 0.998001)) + eps)
+    m3, v3 = 0.9 * m2 + 0.1 * (-2.0), 0.999 * v2 + 0.001 * 4.0
+    x3 = x2 - lr * (m3 / (1 - 0.729)) / (np.sqrt(v3 / (1 - 0.997002999)) + eps)
+    assert abs(x1 - 0.9) < 1e-8
+    np.testing.assert_allclose(params[0][0], [x3], rtol=0, atol=1e-12)
+    # bias: g = 1, 0, -4 (twice the weight's): Adam is invariant to a constant gradient scale up to eps
+    c1 = -3.0 - lr * 1.0
+    np.testing.assert_allclose(params[0][1], [c1 + (x3 - 0.9)], rtol=0, atol=1e-6)
+    t, m, v = state
+    assert t == 3
+    np.testing.assert_allclose(m[0], [m3], rtol=1e-13)
+    np.testing.assert_allclose(v[0], [v3], rtol=1e-13)
+
+
+def test_band_stats_population_std_by_loop():
+    """band_stats: mean and population standard deviation (divide by the count), 1 for a flat band."""
+    r = rng(21)
+    a = r.standard_normal((5, 7))
+    vals = [float(v) for v in a.ravel()]
+    mean = sum(vals) / len(vals)
+    std = (sum((v - mean) ** 2 for v in vals) / len(vals)) ** 0.5
+    m, s = cnn.band_stats(a)
+    assert abs(m - mean) < 1e-14 and abs(s - std) < 1e-14
+    # values 1..n: population variance (n^2 - 1)/12
+    n = 12
+    m, s = cnn.band_stats(np.arange(1, n + 1, dtype=float).reshape(3, 4))
+    assert abs(m - 6.5) < 1e-14 and abs(s - np.sqrt((n * n - 1) / 12.0)) < 1e-14
+    # a flat band has s = 1 (no division by zero)
+    m, s = cnn.band_stats(np.full((4, 4), 0.25))
+    assert m == 0.25 and s == 1.0
