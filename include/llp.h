@@ -68,21 +68,32 @@ typedef struct {
   float lambda;  /* LLP weight, >= 0 */
   float eps;     /* matting regulariser epsilon, >= 0 (enters as eps/|w| + sigma^2) */
   int max_iters; /* CG iteration cap, >= 0 */
-  float tol;     /* > 0: stop a band when ||r_k|| <= tol * ||b|| (r_k the CG residual, b = B^T D^T X_i);
-                    <= 0: run exactly max_iters iterations */
+  float tol;     /* > 0: stop a band when ||b - A Z|| <= tol * ||b|| (b = B^T D^T X_i) for its iterate Z: when the
+                    CG residual r_k meets the bound, r_k is recomputed as b - A Z in FP64 from Z (carried as FP64
+                    plus a float32 part) and the band stops only if that meets it too, else it iterates on from
+                    the recomputed residual; the same replacement runs every 32 iterations.  The returned HRMS is
+                    float(Z).  <= 0: run exactly max_iters iterations (with the same replacements) */
   int init_mode; /* 0: start from Z = 0; 1: start from the caller's `init`; 2: start from the warm-start
                     network's estimate (llp_cnn_set_weights first), band by band only where it is closer
                     than Z = 0 (||b - A Z0|| < ||b||), else from Z = 0 */
+  int precond;   /* 0: plain conjugate gradients; 1: preconditioned by P = B^T D^T D B + lambda mbar L^T L,
+                    mbar the mean of diag(M_LY), applied exactly in the Fourier domain (not in the paper; the
+                    same minimiser, fewer iterations).  Needs r >= 1, lambda > 0, h and w with prime factors in
+                    {2, 3, 5, 7} and c W, c H <= 16384 (LLP_E_UNSUPPORTED otherwise) and a kernel with nonzero
+                    sum (LLP_E_BREAKDOWN otherwise) */
 } llp_params;
 
 typedef struct {
   int iters;                /* CG iterations run for this band */
   int status;               /* llp_status of this band (LLP_OK, LLP_NOT_CONVERGED, LLP_E_BREAKDOWN) */
-  double rel_residual;      /* ||r_k|| / ||b|| of the CG recursion at exit */
-  double true_rel_residual; /* ||b - A Z|| / ||b|| recomputed from the returned Z */
-  double objective;         /* eq. (initialize_z_fast) at the returned Z */
+  double rel_residual;      /* ||r_k|| / ||b|| of the CG residual at exit (the last replaced one, see below) */
+  double true_rel_residual; /* ||b - A Z|| / ||b|| of the solver's iterate Z, evaluated in FP64 (the quantity the
+                               tolerance is checked on) */
+  double objective;         /* eq. (initialize_z_fast) at the returned float32 HRMS */
   int init;                 /* how the band started: 0 Z = 0, 1 the caller's init, 2 the network's estimate,
                                3 the network's estimate was rejected (no better than Z = 0) and Z = 0 used */
+  double out_rel_residual;  /* ||b - A Z32|| / ||b|| of the returned float32 HRMS Z32 = float(Z), in FP64: at
+                               least the residual that rounding Z to float32 causes */
 } llp_report;
 
 typedef struct llp_ctx llp_ctx;
@@ -183,8 +194,9 @@ llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* 
  * keeps scenes of different sizes in shared launches.  LLP_E_UNSUPPORTED if no specialised kernel fits the
  * geometry (no specialised kernels for (c, n, r), or an image narrower or lower than their tiles): such scenes
  * are never batched.  0 <= copies <= 256; 1 <= iters <= 1000, rounded up to a multiple of 8 (batched solves
- * iterate in chunks of 8).  Allocates and frees copies * N*H*W floats of output scratch.  Synchronises
- * `stream`. */
+ * iterate in chunks of 8).  A candidate whose two timings do not differ by a positive amount (timing noise) is
+ * skipped; if no candidate gives a valid time, nothing is stored and the call returns the warning
+ * LLP_NOT_CONVERGED.  Allocates and frees copies * N*H*W floats of output scratch.  Synchronises `stream`. */
 llp_status llp_autotune_batch(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
                               const float* pan, const float* kernel, int copies, int iters, llp_tune_result* out,
                               hipStream_t stream);
@@ -244,6 +256,19 @@ llp_status llp_rhs(llp_ctx* ctx, const llp_shape* shape, const float* lrms, cons
  * z, Az [N][H][W] device (must not alias). */
 llp_status llp_apply_A(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
                        const float* kernel, const float* z, float* Az, hipStream_t stream);
+
+/* The two terms of that matrix separately, with the solve's own kernels and launch configuration:
+ *   llp_apply_data: out = B^T D^T D B z, the data term of eq. (Z_ini_matting) (Sec. II-A: B circular
+ *                   convolution by the kernel, D decimation by c).  params selects the launch configuration only
+ *                   (its r; lambda and eps are not used); no PAN image is needed.
+ *   llp_apply_llp:  out = lambda L^T M_LY L z, the LLP term of eq. (Z_ini_matting) with M_LY of
+ *                   eq. (matting_matrix); the kernel is read (the operator kernel is shared with the data term)
+ *                   but contributes nothing.
+ * z, out [N][H][W] device, 16-byte aligned, must not alias.  Asynchronous on `stream`. */
+llp_status llp_apply_data(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* kernel,
+                          const float* z, float* out, hipStream_t stream);
+llp_status llp_apply_llp(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
+                         const float* kernel, const float* z, float* out, hipStream_t stream);
 
 /* Objective of eq. (initialize_z_fast) for every band of z: obj host [N] (FP64).  The LLP part is summed
  * window by window in the form of eq. (pansharp) with the optimal (a, c) of each window. */

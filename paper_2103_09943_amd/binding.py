@@ -25,12 +25,14 @@ class Shape(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int), ("lam", ctypes.c_float), ("eps", ctypes.c_float),
-                ("max_iters", ctypes.c_int), ("tol", ctypes.c_float), ("init_mode", ctypes.c_int)]
+                ("max_iters", ctypes.c_int), ("tol", ctypes.c_float), ("init_mode", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("true_rel_residual", ctypes.c_double), ("objective", ctypes.c_double), ("init", ctypes.c_int)]
+                ("true_rel_residual", ctypes.c_double), ("objective", ctypes.c_double), ("init", ctypes.c_int),
+                ("out_rel_residual", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,6 +67,8 @@ _SIGS = {
     "llp_pan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
     "llp_rhs": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), _vp, _vp, _vp, _vp]),
     "llp_apply_A": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
+    "llp_apply_data": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp]),
+    "llp_apply_llp": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
     "llp_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "llp_get_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
     "llp_objective": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
@@ -175,7 +179,8 @@ class Context:
         self.close()
 
     def pansharpen(self, lrms, pan, kernel, *, r: int, lam: float, eps: float, max_iters: int, tol: float = 0.0,
-                   init=None, out=None, report: bool = True, stream=None, allow_not_converged: bool = True):
+                   init=None, out=None, report: bool = True, stream=None, allow_not_converged: bool = True,
+                   precond: int = 0):
         """Solve eq. (Z_ini_matting) for every band.  Returns (hrms, list of report dicts or None, status)."""
         import torch
         shp = shape_of(lrms, pan, kernel)
@@ -185,7 +190,7 @@ class Context:
         mode = 2 if isinstance(init, str) and init == "cnn" else (1 if init is not None else 0)
         if mode == 2:
             init = None
-        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), mode)
+        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), mode, int(precond))
         reps = (Report * shp.N)() if report else None
         st = lib().llp_pansharpen(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(lrms), _ptr(pan), _ptr(kernel),
                                   _ptr(init), _ptr(out), reps, _stream(stream))
@@ -195,7 +200,7 @@ class Context:
 
     def pansharpen_batch(self, scenes, *, r: int, lam: float, eps: float, max_iters: int, tol: float = 0.0,
                          inits=None, outs=None, report: bool = True, flags: int = 0, stream=None,
-                         allow_not_converged: bool = True):
+                         allow_not_converged: bool = True, precond: int = 0):
         """Solve every band of several scenes together (llp_pansharpen_batch).  `scenes` is a sequence of
         (lrms, pan, kernel) device tensors.  Returns (list of hrms, list of per-scene report lists or None,
         status)."""
@@ -211,7 +216,7 @@ class Context:
         mode = 2 if isinstance(inits, str) and inits == "cnn" else (1 if inits is not None else 0)
         if mode == 2:
             inits = None
-        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), mode)
+        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), mode, int(precond))
         nb = sum(shapes[i].N for i in range(S))
         reps = (Report * max(nb, 1))() if report else None
         st = lib().llp_pansharpen_batch(self._h, S, shapes, ctypes.byref(prm), arr([s[0] for s in scenes]),
@@ -340,6 +345,28 @@ class Context:
         out = torch.empty_like(z)
         _check(lib().llp_apply_A(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(pan), _ptr(kernel), _ptr(z),
                                  _ptr(out), _stream(stream)), "llp_apply_A")
+        return out
+
+    def apply_data(self, z, kernel, *, c: int, r: int, stream=None):
+        """B^T D^T D B z (llp_apply_data)."""
+        import torch
+        N, H, W = z.shape
+        shp = Shape(N, H // c, W // c, c, kernel.shape[0])
+        prm = Params(int(r), 0.0, 0.0, 0, 0.0, 0)
+        out = torch.empty_like(z)
+        _check(lib().llp_apply_data(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(kernel), _ptr(z), _ptr(out),
+                                    _stream(stream)), "llp_apply_data")
+        return out
+
+    def apply_llp(self, z, pan, kernel, *, c: int, r: int, lam: float, eps: float, stream=None):
+        """lambda L^T M_LY L z (llp_apply_llp)."""
+        import torch
+        N, H, W = z.shape
+        shp = Shape(N, H // c, W // c, c, kernel.shape[0])
+        prm = Params(int(r), float(lam), float(eps), 0, 0.0, 0)
+        out = torch.empty_like(z)
+        _check(lib().llp_apply_llp(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(pan), _ptr(kernel), _ptr(z),
+                                   _ptr(out), _stream(stream)), "llp_apply_llp")
         return out
 
     def objective(self, z, lrms, pan, kernel, *, r: int, lam: float, eps: float, stream=None):

@@ -14,7 +14,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libllp.so")
-SOURCES = ["llp_kernels.hip", "llp_operator.hip", "llp_fast.hip", "llp_sweep.hip", "llp_api.hip", "llp_batch.hip", "llp_tune.hip", "llp_cnn.hip",
+SOURCES = ["llp_kernels.hip", "llp_operator.hip", "llp_fast.hip", "llp_sweep.hip", "llp_refine.hip", "llp_precond.hip",
+           "llp_api.hip",
+           "llp_batch.hip", "llp_tune.hip", "llp_cnn.hip",
            "llp_cnn_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -35,15 +37,19 @@ def _run(cmd):
 
 def build(verbose: bool = False) -> str:
     """Compile every HIP source and link libllp.so.  Always recompiles."""
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
+
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        out = _run([HIPCC, *COMMON, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        if verbose and out.strip():
-            print(out)
-        objs.append(obj)
+    objs = [os.path.join(bdir, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", 0)) or os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as ex:  # one hipcc process per source
+        outs = list(ex.map(lambda so: _run([HIPCC, *COMMON, *DEVICE_FLAGS, "-c", os.path.join(CSRC, so[0]), "-o",
+                                            so[1]]), zip(SOURCES, objs)))
+    if verbose:
+        for out in outs:
+            if out.strip():
+                print(out)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)

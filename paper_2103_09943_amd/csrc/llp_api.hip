@@ -50,10 +50,13 @@ llp_status validate(const llp_shape* s, const llp_params* p, Geom* g) {
     if (!isfinite(p->eps) || p->eps < 0.0f) return LLP_E_ARG;
     if (p->max_iters < 0 || !isfinite(p->tol)) return LLP_E_ARG;
     if (p->init_mode < 0 || p->init_mode > 2) return LLP_E_ARG;
+    if (p->precond < 0 || p->precond > 1) return LLP_E_ARG;
     g->r = p->r;
     g->lam = p->lambda;
     g->eps = p->eps;
   }
+  if (ref_y_lds(*g) > kRefMaxLds || ref_res_lds(*g) > kRefMaxLds) return LLP_E_UNSUPPORTED;
+  if (p && p->precond && !pc_supported(*g)) return LLP_E_UNSUPPORTED;
   return LLP_OK;
 }
 
@@ -96,7 +99,7 @@ bool pick_config(const Geom& g, OpConfig* cfg, bool allow_fast, int want_dir_row
   return cfg->dir_rows > 0 && cfg->apply_variant >= 0;
 }
 
-llp_status ensure_workspace(llp_ctx* ctx, const Geom& g) {
+llp_status ensure_workspace(llp_ctx* ctx, const Geom& g, bool precond) {
   const size_t HW = (size_t)g.H * g.W;
   const size_t planes = 3 * HW + 6 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w;
   const size_t pstride = max_partials_per_band(g);
@@ -111,6 +114,26 @@ llp_status ensure_workspace(llp_ctx* ctx, const Geom& g) {
   off = align_up(off + (size_t)g.N * kResultSlots * sizeof(double), 256);
   const size_t o_flags = off;
   off = align_up(off + 16 * sizeof(int), 256);
+  const size_t o_xacc = off;
+  off = align_up(off + (size_t)g.N * HW * sizeof(double), 256);
+  const size_t o_y64 = off;
+  off = align_up(off + (size_t)g.N * g.h * g.w * sizeof(double), 256);
+  const size_t o_ref = off;
+  off = align_up(off + sizeof(RefDesc), 256);
+  // preconditioner: s, spectra, kernel DFT, twiddles, mbar and its partials, the descriptor
+  const bool pc = precond && pc_supported(g);
+  const size_t o_s = off;
+  if (pc) off = align_up(off + (size_t)g.N * HW * sizeof(float), 256);
+  const size_t o_spec = off;
+  if (pc) off = align_up(off + pc_spec_floats(g) * sizeof(float), 256);
+  const size_t o_uhat = off;
+  if (pc) off = align_up(off + pc_uhat_floats(g) * sizeof(float), 256);
+  const size_t o_tw = off;
+  if (pc) off = align_up(off + pc_tw_floats(g) * sizeof(float), 256);
+  const size_t o_mbar = off;
+  off = align_up(off + (1 + kPcMbarBlocks) * sizeof(double), 256);
+  const size_t o_pc = off;
+  off = align_up(off + sizeof(PcDesc), 256);
   const size_t need = off;
   if (need > ctx->ws_bytes) {
     if (ctx->ws) {
@@ -142,6 +165,27 @@ llp_status ensure_workspace(llp_ctx* ctx, const Geom& g) {
   ctx->st = (ChanState*)(base + o_st);
   ctx->results = (double*)(base + o_res);
   ctx->flags = (int*)(base + o_flags);
+  ctx->xacc = (double*)(base + o_xacc);
+  ctx->y64 = (double*)(base + o_y64);
+  ctx->d_ref = (RefDesc*)(base + o_ref);
+  if (!ctx->h_ref && hipHostMalloc((void**)&ctx->h_ref, sizeof(RefDesc), hipHostMallocDefault) != hipSuccess)
+    return LLP_E_OOM;
+  ctx->s = pc ? (float*)(base + o_s) : nullptr;
+  ctx->spec = pc ? (float*)(base + o_spec) : nullptr;
+  ctx->uhat = pc ? (float*)(base + o_uhat) : nullptr;
+  ctx->tw = pc ? (float*)(base + o_tw) : nullptr;
+  ctx->mbar = (double*)(base + o_mbar);
+  ctx->d_pc = (PcDesc*)(base + o_pc);
+  if (!ctx->h_pc && hipHostMalloc((void**)&ctx->h_pc, sizeof(PcDesc), hipHostMallocDefault) != hipSuccess)
+    return LLP_E_OOM;
+  if (pc && ctx->h_tw_cap < pc_tw_floats(g)) {
+    if (ctx->h_tw) (void)hipHostFree(ctx->h_tw);
+    ctx->h_tw = nullptr;
+    ctx->h_tw_cap = 0;
+    if (hipHostMalloc((void**)&ctx->h_tw, pc_tw_floats(g) * sizeof(float), hipHostMallocDefault) != hipSuccess)
+      return LLP_E_OOM;
+    ctx->h_tw_cap = pc_tw_floats(g);
+  }
   if (ctx->h_cap < g.N) {
     if (ctx->h_st) (void)hipHostFree(ctx->h_st);
     if (ctx->h_results) (void)hipHostFree(ctx->h_results);
@@ -204,6 +248,34 @@ llp_status apply_A_into(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const 
 }
 
 
+void ref_plan(RefDesc* tab, int count, RefPlan* plan) {
+  RefPlan P;
+  P.count = count;
+  for (int i = 0; i < count; ++i) {
+    RefDesc& d = tab[i];
+    d.e_block0 = P.eblocks;
+    d.y_block0 = P.yblocks;
+    d.r_block0 = P.rblocks;
+    P.eblocks += ref_elem_blocks(d.g);
+    P.yblocks += ref_y_blocks(d.g);
+    P.rblocks += ref_res_blocks(d.g);
+    P.bands += d.g.N;
+    const size_t yl = ref_y_lds(d.g), rl = ref_res_lds(d.g);
+    if (yl > P.ylds) P.ylds = yl;
+    if (rl > P.rlds) P.rlds = rl;
+  }
+  *plan = P;
+}
+
+llp_status ref_pass(const RefDesc* d_tab, const RefPlan& P, ChanState* st, double* results, int fin_op, int force,
+                    int rpar, int write_r, int max_iters, float tol, int plain_cg, hipStream_t s) {
+  if (fin_op != kRefOut) HIP_TRY(launch_ref_elem(kRefFlush, d_tab, P.count, P.eblocks, st, force, s));
+  HIP_TRY(launch_ref_y(d_tab, P.count, P.yblocks, P.ylds, st, force, s));
+  HIP_TRY(launch_ref_res(d_tab, P.count, P.rblocks, P.rlds, st, force, rpar, write_r, s));
+  HIP_TRY(launch_ref_fin(fin_op, d_tab, P.count, P.bands, st, results, force, plain_cg, max_iters, tol, s));
+  return LLP_OK;
+}
+
 bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg, bool batched) {
   if (ctx->want_dir_rows == 0 && ctx->want_apply_variant < 0 && ctx->want_seg_rows == 0) {
     const int bucket = area_bucket(g);
@@ -228,7 +300,7 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
                        const float* lrms, const float* pan, const float* kernel, const float* init, float* hrms,
                        llp_report* rep, hipStream_t stream) {
   llp_status v;
-  v = ensure_workspace(ctx, g);
+  v = ensure_workspace(ctx, g, params->precond != 0);
   if (v != LLP_OK) return v;
   hipStream_t s = stream;
   const size_t NHW = (size_t)g.N * g.H * g.W;
@@ -247,27 +319,86 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
     v = cnn_warm_start(ctx, g, lrms, pan, hrms, nullptr, s);
     if (v != LLP_OK) return v;
   }
-  if (from_init) {
-    v = apply_A_into(ctx, g, cfg, hrms, kernel, ctx->q, s);
+  HIP_TRY(launch_init(g, from_init, ctx->b, ctx->r[0], ctx->st, s));
+  // The iterate is xacc (FP64) + hrms (float32, advanced by the iteration kernels between replacements).
+  RefDesc& rd = *ctx->h_ref;
+  memset(&rd, 0, sizeof(rd));
+  rd.g = g;
+  rd.Y = pan;
+  rd.u = kernel;
+  rd.b = ctx->b;
+  rd.z = hrms;
+  rd.xacc = ctx->xacc;
+  rd.r[0] = ctx->r[0];
+  rd.r[1] = ctx->r[1];
+  rd.p[0] = ctx->p[0];
+  rd.p[1] = ctx->p[1];
+  rd.y64 = ctx->y64;
+  rd.partials = ctx->partials;
+  rd.pstride = (int)max_partials_per_band(g);
+  rd.band0 = 0;
+  RefPlan P;
+  ref_plan(&rd, 1, &P);
+  HIP_TRY(hipMemcpyAsync(ctx->d_ref, &rd, sizeof(RefDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_ref_elem(from_init ? kRefStartFrom : kRefStartZero, ctx->d_ref, 1, P.eblocks, ctx->st, 1, s));
+  if (from_init) {  // r_0 = b - A Z0 in FP64; ||r_0||^2 decides a network start
+    v = ref_pass(ctx->d_ref, P, ctx->st, ctx->results, kRefStart, 1, 0, 1, max_iters, tol, 1, s);
     if (v != LLP_OK) return v;
   }
-  HIP_TRY(launch_init(g, from_init, ctx->b, ctx->q, ctx->r[0], hrms, ctx->st, s));
-  if (params->init_mode == 2) {
-    HIP_TRY(launch_residual_norm(g, ctx->b, ctx->q, ctx->partials, ctx->st, ctx->results, s));
-    HIP_TRY(launch_fallback(g, ctx->results, ctx->st, ctx->b, ctx->r[0], hrms, s));
-  }
+  if (params->init_mode == 2) HIP_TRY(launch_fallback(g, ctx->results, ctx->st, ctx->b, ctx->r[0], ctx->xacc, s));
 
   // CG.  k_dir(k) produces x_k, r_k, p_k and y = D B p_k; k_apply(k) produces q_k = A p_k, alpha_k, beta_k.
   // Residual and direction alternate between two buffers so that no tile reads a neighbour's new values.
+  // After every chunk of kCheckEvery iterations a residual-replacement pass runs for the bands that are due.
+  // Preconditioned: k_apply, alpha; r_k, x_k and the forward rows of the transform; the columns with the group
+  // solve; the inverse rows giving s_k = P^{-1} r_k, beta; p_k = s_k + beta p_{k-1} and y = D B p_k; the
+  // stopping rule.
+  const bool pc = params->precond != 0;
   const int nb_dir = dir_ntiles(g, cfg), nb_apply = apply_ntiles(g, cfg);
-  HIP_TRY(launch_dir(g, cfg, 1, 0, 0, ctx->r[0], nullptr, nullptr, nullptr, ctx->p[0], hrms, ctx->y, kernel,
-                     ctx->partials, ctx->st, max_iters, tol, s));
-  HIP_TRY(launch_finalize(g, kFinDir, ctx->partials, nb_dir, ctx->st, nullptr, 0, 0, max_iters, tol, s));
+  PcPlan PP;
+  if (pc) {
+    PcDesc& pd = *ctx->h_pc;
+    memset(&pd, 0, sizeof(pd));
+    pc_fill(pd, g, ctx->tw);
+    pd.spec = (float2*)ctx->spec;
+    pd.uhat = (float2*)ctx->uhat;
+    pd.u = kernel;
+    pd.DI = ctx->DI;
+    pd.mbar = ctx->mbar;
+    pd.r[0] = ctx->r[0];
+    pd.r[1] = ctx->r[1];
+    pd.p[0] = ctx->p[0];
+    pd.p[1] = ctx->p[1];
+    pd.q = ctx->q;
+    pd.z = hrms;
+    pd.s = ctx->s;
+    pd.partials = ctx->partials;
+    pd.pstride = (int)max_partials_per_band(g);
+    pd.band0 = 0;
+    pc_plan(&pd, 1, &PP);
+    pc_twiddles(g, ctx->h_tw);
+    HIP_TRY(hipMemcpyAsync(ctx->tw, ctx->h_tw, pc_tw_floats(g) * sizeof(float), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->d_pc, &pd, sizeof(PcDesc), hipMemcpyHostToDevice, s));
+    // per scene: the kernel's DFT at every group member, and mbar
+    HIP_TRY(launch_pc_rows(kPcRowsKernel, ctx->d_pc, PP, ctx->st, 0, 0, s));
+    HIP_TRY(launch_pc_cols(kPcColsKernel, ctx->d_pc, PP, ctx->st, s));
+    HIP_TRY(launch_pc_mbar(ctx->d_pc, 1, ctx->mbar + 1, s));
+    // s_0 = P^{-1} r_0, rho_0 = r_0^T s_0, p_0 = s_0, y = D B p_0
+    HIP_TRY(launch_pc_rows(kPcRowsStart, ctx->d_pc, PP, ctx->st, 0, 0, s));
+    HIP_TRY(launch_pc_cols(kPcColsSolve, ctx->d_pc, PP, ctx->st, s));
+    HIP_TRY(launch_pc_rows_inv(ctx->d_pc, PP, ctx->st, 0, s));
+    HIP_TRY(launch_finalize(g, kFinPcgStart, ctx->partials, g.h, ctx->st, nullptr, 0, 0, max_iters, tol, s));
+    HIP_TRY(launch_dir(g, cfg, 1, 0, 0, ctx->s, nullptr, nullptr, nullptr, ctx->p[0], hrms, ctx->y, kernel,
+                       ctx->partials, ctx->st, max_iters, tol, s));
+  } else {
+    HIP_TRY(launch_dir(g, cfg, 1, 0, 0, ctx->r[0], nullptr, nullptr, nullptr, ctx->p[0], hrms, ctx->y, kernel,
+                       ctx->partials, ctx->st, max_iters, tol, s));
+    HIP_TRY(launch_finalize(g, kFinDir, ctx->partials, nb_dir, ctx->st, nullptr, 0, 0, max_iters, tol, s));
+  }
   const bool tol_mode = tol > 0.0f;
   int chunk_no = 0;
   for (int k = 1; k <= max_iters;) {
-    const int todo = tol_mode ? (max_iters - k + 1 < kCheckEvery ? max_iters - k + 1 : kCheckEvery)
-                              : max_iters - k + 1;
+    const int todo = max_iters - k + 1 < kCheckEvery ? max_iters - k + 1 : kCheckEvery;
     for (int t = 0; t < todo; ++t, ++k) {
       const int prev = (k - 1) & 1, cur = k & 1;
       hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -277,23 +408,38 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
         HIP_TRY(hipEventRecord(e[0], s));
       }
       HIP_TRY(launch_apply(g, cfg, 1, ctx->p[prev], ctx->r[prev], ctx->y, kernel, ctx->G, ctx->MU, ctx->DI,
-                           ctx->q,
-                           ctx->partials, ctx->st, s));
+                           ctx->q, ctx->partials, ctx->st, s));
       if (ctx->profiling) HIP_TRY(hipEventRecord(e[1], s));
+      if (pc) {
+        HIP_TRY(launch_finalize(g, kFinPcgAlpha, ctx->partials, nb_apply, ctx->st, nullptr, 0, 0, 0, 0.0f, s));
+        if (ctx->profiling) HIP_TRY(hipEventRecord(e[2], s));
+        HIP_TRY(launch_pc_rows(kPcRowsUpdate, ctx->d_pc, PP, ctx->st, prev, cur, s));
+        HIP_TRY(launch_pc_cols(kPcColsSolve, ctx->d_pc, PP, ctx->st, s));
+        HIP_TRY(launch_pc_rows_inv(ctx->d_pc, PP, ctx->st, cur, s));
+        HIP_TRY(launch_finalize(g, kFinPcgBeta, ctx->partials, g.h, ctx->st, nullptr, 0, 0, 0, 0.0f, s));
+        HIP_TRY(launch_dir(g, cfg, 3, 0, k, ctx->s, nullptr, ctx->p[prev], nullptr, ctx->p[cur], hrms, ctx->y,
+                           kernel, ctx->partials, ctx->st, max_iters, tol, s));
+        if (ctx->profiling) HIP_TRY(hipEventRecord(e[3], s));
+        HIP_TRY(launch_finalize(g, kFinPcgStop, ctx->partials, 0, ctx->st, nullptr, 0, -1, max_iters, tol, s));
+        continue;
+      }
       HIP_TRY(launch_finalize(g, kFinApply, ctx->partials, nb_apply, ctx->st, nullptr, 0, 0, 0, 0.0f, s));
       if (ctx->profiling) HIP_TRY(hipEventRecord(e[2], s));
       HIP_TRY(launch_dir(g, cfg, 2, k == max_iters, k, ctx->r[prev], ctx->q, ctx->p[prev], ctx->r[cur],
                          ctx->p[cur], hrms, ctx->y, kernel, ctx->partials, ctx->st, max_iters, tol, s));
       if (ctx->profiling) HIP_TRY(hipEventRecord(e[3], s));
-      HIP_TRY(launch_finalize(g, kFinDir, ctx->partials, nb_dir, ctx->st, nullptr, 0, k, max_iters, tol, s));
+      HIP_TRY(launch_finalize(g, kFinDir, ctx->partials, nb_dir, ctx->st, nullptr, 0, -1, max_iters, tol, s));
     }
-    if (!tol_mode) break;
+    // the next iteration (k) reads the buffers of parity (k - 1) & 1
+    v = ref_pass(ctx->d_ref, P, ctx->st, ctx->results, kRefStep, 0, (k - 1) & 1, 1, max_iters, tol, pc ? 0 : 1, s);
+    if (v != LLP_OK) return v;
+    if (!tol_mode) continue;
     // Poll the band states of the chunk before last while this one runs (at most two chunks in flight).
     const int slot = chunk_no & 1;
     if (chunk_no >= 2) {
       HIP_TRY(hipEventSynchronize(ctx->ev[slot]));
       bool any = false;
-      for (int i = 0; i < g.N; ++i) any |= ctx->h_st[i].active != 0;
+      for (int i = 0; i < g.N; ++i) any |= ctx->h_st[i].active != 0 || ctx->h_st[i].pending != 0;
       if (!any) break;
     }
     HIP_TRY(hipMemcpyAsync(ctx->h_st, ctx->st, sizeof(ChanState) * g.N, hipMemcpyDeviceToHost, s));
@@ -301,11 +447,16 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
     ++chunk_no;
   }
 
-  // The true residual and the objective of the returned iterate.
+  // The returned HRMS: float32(xacc + z).  With a report: the FP64 residual of the iterate before that rounding,
+  // the FP64 residual of the float32 output, and the objective of the output.
   if (rep) {
-    v = apply_A_into(ctx, g, cfg, hrms, kernel, ctx->q, s);
+    v = ref_pass(ctx->d_ref, P, ctx->st, ctx->results, kRefFinal, 1, 0, 0, max_iters, tol, 1, s);
     if (v != LLP_OK) return v;
-    HIP_TRY(launch_residual_norm(g, ctx->b, ctx->q, ctx->partials, ctx->st, ctx->results, s));
+  }
+  HIP_TRY(launch_ref_elem(rep ? kRefOutputBack : kRefOutput, ctx->d_ref, 1, P.eblocks, ctx->st, 1, s));
+  if (rep) {
+    v = ref_pass(ctx->d_ref, P, ctx->st, ctx->results, kRefOut, 1, 0, 0, max_iters, tol, 1, s);
+    if (v != LLP_OK) return v;
     HIP_TRY(launch_objective(g, hrms, lrms, kernel, ctx->G, ctx->MU, ctx->DI, ctx->partials, ctx->st,
                              ctx->results, s));
     HIP_TRY(hipMemcpyAsync(ctx->h_results, ctx->results, sizeof(double) * kResultSlots * g.N,
@@ -323,7 +474,7 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
   llp_status worst = LLP_OK;
   for (int i = 0; i < g.N; ++i) {
     const ChanState& cs = ctx->h_st[i];
-    const int st = cs.active ? (tol_mode ? LLP_NOT_CONVERGED : LLP_OK) : cs.status;
+    const int st = (cs.active || cs.pending) ? (tol_mode ? LLP_NOT_CONVERGED : LLP_OK) : cs.status;
     if (st < 0 && (worst >= 0 || st < worst)) worst = (llp_status)st;
     if (st > 0 && worst == LLP_OK) worst = (llp_status)st;
     if (rep) {
@@ -335,6 +486,8 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
       R.rel_residual = bn2 > 0 ? sqrt(cs.rho / bn2) : sqrt(cs.rho);
       const double tr = ctx->h_results[i * kResultSlots + kSlotTrueRes];
       R.true_rel_residual = bn2 > 0 ? sqrt(tr / bn2) : sqrt(tr);
+      const double orr = ctx->h_results[i * kResultSlots + kSlotOutRes];
+      R.out_rel_residual = bn2 > 0 ? sqrt(orr / bn2) : sqrt(orr);
       R.objective = 0.5 * ctx->h_results[i * kResultSlots + kSlotObjData] +
                     0.5 * (double)g.lam * ctx->h_results[i * kResultSlots + kSlotObjLlp];
     }
@@ -377,6 +530,8 @@ llp_status llp_create(llp_ctx** out, int device) {
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return LLP_E_ARG;
   HIP_TRY(hipSetDevice(device));
+  HIP_TRY(ref_prepare());
+  HIP_TRY(pc_prepare());
   llp_ctx* ctx = new (std::nothrow) llp_ctx();
   if (!ctx) return LLP_E_OOM;
   ctx->device = device;
@@ -403,6 +558,9 @@ void llp_destroy(llp_ctx* ctx) {
   if (ctx->h_st) (void)hipHostFree(ctx->h_st);
   if (ctx->h_results) (void)hipHostFree(ctx->h_results);
   if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+  if (ctx->h_ref) (void)hipHostFree(ctx->h_ref);
+  if (ctx->h_pc) (void)hipHostFree(ctx->h_pc);
+  if (ctx->h_tw) (void)hipHostFree(ctx->h_tw);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->tev) (void)hipEventDestroy(e);
@@ -413,6 +571,7 @@ void llp_destroy(llp_ctx* ctx) {
   if (ctx->h_bres) (void)hipHostFree(ctx->h_bres);
   if (ctx->h_bflags) (void)hipHostFree(ctx->h_bflags);
   if (ctx->h_table) (void)hipHostFree(ctx->h_table);
+  if (ctx->h_rtable) (void)hipHostFree(ctx->h_rtable);
   if (ctx->bev_in) (void)hipEventDestroy(ctx->bev_in);
   if (ctx->bstream) (void)hipStreamDestroy(ctx->bstream);
   cnn_free(ctx->cnn);
@@ -457,6 +616,46 @@ llp_status llp_apply_A(llp_ctx* ctx, const llp_shape* shape, const llp_params* p
   if (v != LLP_OK) return v;
   HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
   return apply_A_into(ctx, g, cfg, z, kernel, Az, stream);
+}
+
+llp_status llp_apply_data(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* kernel,
+                          const float* z, float* out, hipStream_t stream) {
+  if (!ctx || !params || !kernel || !z || !out || z == out) return LLP_E_ARG;
+  if (!aligned16(z) || !aligned16(out)) return LLP_E_ARG;
+  Geom g;
+  llp_status v = validate(shape, params, &g);
+  if (v != LLP_OK) return v;
+  OpConfig cfg;
+  if (!ctx_config(ctx, g, &cfg)) return LLP_E_UNSUPPORTED;
+  HIP_TRY(hipSetDevice(ctx->device));
+  v = ensure_workspace(ctx, g);
+  if (v != LLP_OK) return v;
+  // The solve's operator kernels with lambda = 0 and zero PAN statistics: the LLP part is then exactly 0.
+  const size_t HW = (size_t)g.H * g.W;
+  HIP_TRY(hipMemsetAsync(ctx->G, 0, 3 * HW * sizeof(float), stream));
+  Geom gd = g;
+  gd.lam = 0.0f;
+  return apply_A_into(ctx, gd, cfg, z, kernel, out, stream);
+}
+
+llp_status llp_apply_llp(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
+                         const float* kernel, const float* z, float* out, hipStream_t stream) {
+  if (!ctx || !params || !pan || !kernel || !z || !out || z == out) return LLP_E_ARG;
+  if (!aligned16(z) || !aligned16(out)) return LLP_E_ARG;
+  Geom g;
+  llp_status v = validate(shape, params, &g);
+  if (v != LLP_OK) return v;
+  OpConfig cfg;
+  if (!ctx_config(ctx, g, &cfg)) return LLP_E_UNSUPPORTED;
+  HIP_TRY(hipSetDevice(ctx->device));
+  v = ensure_workspace(ctx, g);
+  if (v != LLP_OK) return v;
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
+  // The solve's operator kernel with y = D B z replaced by 0: its data part B^T D^T y is then exactly 0.
+  HIP_TRY(hipMemsetAsync(ctx->y, 0, (size_t)g.N * g.h * g.w * sizeof(float), stream));
+  HIP_TRY(launch_apply(g, cfg, 0, z, nullptr, ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, out, ctx->partials,
+                       ctx->st, stream));
+  return LLP_OK;
 }
 
 llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,

@@ -57,12 +57,16 @@ llp_status ensure_batch_mirrors(llp_ctx* ctx, int bands, int scenes) {
   if (ctx->hb_scenes < scenes) {
     if (ctx->h_bflags) (void)hipHostFree(ctx->h_bflags);
     if (ctx->h_table) (void)hipHostFree(ctx->h_table);
+    if (ctx->h_rtable) (void)hipHostFree(ctx->h_rtable);
     ctx->h_bflags = nullptr;
     ctx->h_table = nullptr;
+    ctx->h_rtable = nullptr;
     ctx->hb_scenes = 0;
     if (hipHostMalloc((void**)&ctx->h_bflags, sizeof(int) * scenes, hipHostMallocDefault) != hipSuccess)
       return LLP_E_OOM;
     if (hipHostMalloc((void**)&ctx->h_table, sizeof(SceneDesc) * scenes, hipHostMallocDefault) != hipSuccess)
+      return LLP_E_OOM;
+    if (hipHostMalloc((void**)&ctx->h_rtable, sizeof(RefDesc) * scenes, hipHostMallocDefault) != hipSuccess)
       return LLP_E_OOM;
     ctx->hb_scenes = scenes;
   }
@@ -73,7 +77,8 @@ llp_status ensure_batch_mirrors(llp_ctx* ctx, int bands, int scenes) {
 // every class launch is bracketed by timing events of that context.
 llp_status enqueue_batch_iters(const std::vector<BatchClass>& classes, const SceneDesc* d_table, int nscenes,
                                int nbands, ChanState* st, char* ws, const float* taps, int count, int parity,
-                               int max_iters, float tol, hipStream_t s, llp_ctx* prof) {
+                               int max_iters, float tol, hipStream_t s, llp_ctx* prof, const RefDesc* d_ref,
+                               const RefPlan& rplan, double* results) {
   std::vector<hipEvent_t> ev(prof ? 4 * classes.size() : 0);
   for (int j = 0; j < count; ++j) {
     const int par = (parity + j) & 1;
@@ -95,12 +100,13 @@ llp_status enqueue_batch_iters(const std::vector<BatchClass>& classes, const Sce
       const BatchClass& k = classes[c];
       if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 2], s));
       HIP_TRY(launch_dir_fast_batch(d_table + k.first, k.count, k.dir_blocks, k.C, k.R, k.dir_rows, par, st, ws,
-                                    taps, s));
+                                    taps, 2, s));
       if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 3], s));
     }
     HIP_TRY(launch_finalize_batch(kFinDir, d_table, nscenes, nbands, st, ws, max_iters, tol, s));
   }
-  return LLP_OK;
+  // residual replacement for the bands that are due; the next iteration reads the buffers of parity + count
+  return ref_pass(d_ref, rplan, st, results, kRefStep, 0, (parity + count) & 1, 1, max_iters, tol, 1, s);
 }
 }  // namespace
 
@@ -155,7 +161,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     if (!ctx_config(ctx, b.g, &b.cfg, batched)) return LLP_E_UNSUPPORTED;
     b.cls = class_key(b.g, b.cfg);
     total_bands += b.g.N;
-    if (b.cfg.fast && !(flags & LLP_BATCH_SERIAL)) fast.push_back(b);
+    if (b.cfg.fast && !(flags & LLP_BATCH_SERIAL) && !params->precond) fast.push_back(b);
     else slow.push_back(b);
   }
   HIP_TRY(hipSetDevice(ctx->device));
@@ -188,8 +194,10 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       const Geom& g = fast[i].g;
       const size_t HW = (size_t)g.H * g.W;
       o_pl[i] = off;
-      // the statistics G, mu, dinv, b, r (2), p (2), q, the iterate x, and y
+      // the statistics G, mu, dinv, b, r (2), p (2), q, the iterate's float32 part x, and y; then the iterate's
+      // FP64 part and D B x in FP64
       off = align_up(off + (3 * HW + 7 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w) * sizeof(float), 256);
+      off = align_up(off + ((size_t)g.N * HW + (size_t)g.N * g.h * g.w) * sizeof(double), 256);
       o_part[i] = off;
       off = align_up(off + (size_t)g.N * max_partials_per_band(g) * 3 * sizeof(double), 256);
       nbands += g.N;
@@ -204,6 +212,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     off = align_up(off + (size_t)nf * sizeof(SceneDesc), 256);
     const size_t o_taps = off;
     off = align_up(off + (size_t)nf * kTapStride * sizeof(float), 256);
+    const size_t o_ref = off;
+    off = align_up(off + (size_t)nf * sizeof(RefDesc), 256);
     if (off > ctx->bws_bytes) {
       if (ctx->bws) {
         HIP_TRY(hipStreamSynchronize(s));
@@ -230,7 +240,9 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     int* bflags = (int*)(base + o_flags);
     SceneDesc* d_table = (SceneDesc*)(base + o_table);
     float* d_taps = (float*)(base + o_taps);
+    RefDesc* d_ref = (RefDesc*)(base + o_ref);
     SceneDesc* tab = ctx->h_table;
+    RefDesc* rtab = ctx->h_rtable;
     std::vector<BatchClass> classes;
     int band = 0;
     for (int i = 0; i < nf; ++i) {
@@ -256,6 +268,23 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       d.x = d.q + NHW;  // the iterate lives in the workspace during the solve; copied to hrms at the end
       d.y = d.x + NHW;
       d.partials = (double*)(base + o_part[i]);
+      RefDesc& rd = rtab[i];
+      memset(&rd, 0, sizeof(rd));
+      rd.g = g;
+      rd.Y = d.Y;
+      rd.u = d.u;
+      rd.b = d.b;
+      rd.z = d.x;
+      rd.xacc = (double*)(base + align_up(o_pl[i] + (3 * HW + 7 * NHW + (size_t)g.N * g.h * g.w) * sizeof(float),
+                                          256));
+      rd.y64 = rd.xacc + NHW;
+      for (int j = 0; j < 2; ++j) {
+        rd.r[j] = d.r[j];
+        rd.p[j] = d.p[j];
+      }
+      rd.partials = d.partials;
+      rd.pstride = (int)max_partials_per_band(g);
+      rd.band0 = band;
       auto rel = [base](const void* ptr) { return (size_t)((const char*)ptr - base); };
       d.o_x = rel(d.x);
       d.o_r[0] = rel(d.r[0]);
@@ -303,16 +332,18 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       }
       k.count += 1;
     }
+    RefPlan rplan;
+    ref_plan(rtab, nf, &rplan);
     HIP_TRY(hipMemcpyAsync(d_table, tab, sizeof(SceneDesc) * nf, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_ref, rtab, sizeof(RefDesc) * nf, hipMemcpyHostToDevice, s));
     for (int i = 0; i < nf; ++i)
       HIP_TRY(hipMemcpyAsync(d_taps + (size_t)i * kTapStride, tab[i].u, sizeof(float) * tab[i].g.n * tab[i].g.n,
                              hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemsetAsync(bflags, 0, sizeof(int) * nf, s));
-    // Per scene: input checks, PAN statistics, right-hand side, start of CG (x_0, r_0, p_0, rho_0).
+    // Per scene: input checks, PAN statistics, right-hand side, the start Z0 (into the float32 part x).
     for (int i = 0; i < nf; ++i) {
       const SceneDesc& d = tab[i];
       const Geom& g = d.g;
-      const OpConfig& cfg = fast[i].cfg;
       ChanState* sst = st + d.band0;
       HIP_TRY(launch_check_finite(d.X, (size_t)g.N * g.h * g.w, bflags + i, s));
       HIP_TRY(launch_check_finite(d.Y, (size_t)g.H * g.W, bflags + i, s));
@@ -328,17 +359,23 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         v = cnn_warm_start(ctx, g, d.X, d.Y, d.x, nullptr, s);
         if (v != LLP_OK) return v;
       }
-      if (from_init || net_init) {
-        HIP_TRY(launch_dir(g, cfg, 0, 0, 0, d.x, nullptr, nullptr, nullptr, nullptr, nullptr, d.y, d.u, d.partials,
-                           sst, 0, 0.0f, s));
-        HIP_TRY(launch_apply(g, cfg, 0, d.x, nullptr, d.y, d.u, d.G, d.MU, d.DI, d.q, d.partials, sst, s));
-      }
-      HIP_TRY(launch_init(g, from_init || net_init, d.b, d.q, d.r[0], d.x, sst, s));
-      if (net_init) {
-        double* sres = results + (size_t)d.band0 * kResultSlots;
-        HIP_TRY(launch_residual_norm(g, d.b, d.q, d.partials, sst, sres, s));
-        HIP_TRY(launch_fallback(g, sres, sst, d.b, d.r[0], d.x, s));
-      }
+      HIP_TRY(launch_init(g, from_init || net_init, d.b, d.r[0], sst, s));
+    }
+    // All scenes: the iterate's FP64 part from the start; for a given start r_0 = b - A Z0 in FP64.
+    HIP_TRY(launch_ref_elem((from_init || net_init) ? kRefStartFrom : kRefStartZero, d_ref, nf, rplan.eblocks, st, 1,
+                            s));
+    if (from_init || net_init) {
+      v = ref_pass(d_ref, rplan, st, results, kRefStart, 1, 0, 1, max_iters, tol, 1, s);
+      if (v != LLP_OK) return v;
+    }
+    // Per scene: network-start check, then p_0, y = D B p_0 and rho_0.
+    for (int i = 0; i < nf; ++i) {
+      const SceneDesc& d = tab[i];
+      const Geom& g = d.g;
+      const OpConfig& cfg = fast[i].cfg;
+      ChanState* sst = st + d.band0;
+      if (net_init)
+        HIP_TRY(launch_fallback(g, results + (size_t)d.band0 * kResultSlots, sst, d.b, d.r[0], rtab[i].xacc, s));
       HIP_TRY(launch_dir(g, cfg, 1, 0, 0, d.r[0], nullptr, nullptr, nullptr, d.p[0], d.x, d.y, d.u, d.partials,
                          sst, max_iters, tol, s));
       HIP_TRY(launch_finalize(g, kFinDir, d.partials, d.dir_ntiles, sst, nullptr, 0, 0, max_iters, tol, s));
@@ -352,7 +389,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       uint32_t tol_bits = 0;
       memcpy(&tol_bits, &tol, sizeof(tol_bits));
       std::vector<long long> key = {(long long)(uintptr_t)d_table, (long long)(uintptr_t)st, nf, nbands, max_iters,
-                                    (long long)tol_bits};
+                                    (long long)tol_bits, (long long)(uintptr_t)d_ref, rplan.eblocks, rplan.yblocks,
+                                    rplan.rblocks, (long long)rplan.ylds, (long long)rplan.rlds};
       for (const BatchClass& k : classes)
         for (long long x : {(long long)k.C, (long long)k.R, (long long)k.r, (long long)k.dir_rows,
                             (long long)k.variant, (long long)k.first, (long long)k.count, (long long)k.dir_blocks,
@@ -368,7 +406,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         for (const BatchClass& k : classes) {  // LDS limits are set outside the capture
           if (k.variant != kSweepVariant)
             HIP_TRY(launch_apply_fast_batch(d_table, k.count, 0, k.C, k.R, k.r, k.variant, 0, st, base, d_taps, s));
-          HIP_TRY(launch_dir_fast_batch(d_table, k.count, 0, k.C, k.R, k.dir_rows, 0, st, base, d_taps, s));
+          HIP_TRY(launch_dir_fast_batch(d_table, k.count, 0, k.C, k.R, k.dir_rows, 0, st, base, d_taps, 2, s));
         }
         hipStream_t cs = nullptr;
         HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -377,7 +415,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) cv = LLP_E_HIP;
         if (cv == LLP_OK)
           cv = enqueue_batch_iters(classes, d_table, nf, nbands, st, base, d_taps, kCheckEvery, 0, max_iters, tol, cs,
-                                   nullptr);
+                                   nullptr, d_ref, rplan, results);
         if (hipStreamEndCapture(cs, &graph) != hipSuccess && cv == LLP_OK) cv = LLP_E_HIP;
         (void)hipStreamDestroy(cs);
         if (cv == LLP_OK && hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -394,7 +432,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       if (use_graph) HIP_TRY(hipGraphLaunch(ctx->gexec, s));
       else {
         v = enqueue_batch_iters(classes, d_table, nf, nbands, st, base, d_taps, kCheckEvery, 0, max_iters, tol, s,
-                                prof);
+                                prof, d_ref, rplan, results);
         if (v != LLP_OK) return v;
       }
       if (!tol_mode) continue;
@@ -403,7 +441,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       if (chunk_no >= 2) {
         HIP_TRY(hipEventSynchronize(ctx->ev[slot]));
         bool any = false;
-        for (int i = 0; i < nbands; ++i) any |= ctx->h_bst[slot][i].active != 0;
+        for (int i = 0; i < nbands; ++i) any |= ctx->h_bst[slot][i].active != 0 || ctx->h_bst[slot][i].pending != 0;
         if (!any) break;
       }
       HIP_TRY(hipMemcpyAsync(ctx->h_bst[slot], st, sizeof(ChanState) * nbands, hipMemcpyDeviceToHost, s));
@@ -411,17 +449,20 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       ++chunk_no;
     }
 
-    // True residual and objective of every returned iterate.
+    // The returned HRMS float32(xacc + x); with a report, the FP64 residuals of the iterate and of that output
+    // and the output's objective.
     if (rep) {
+      v = ref_pass(d_ref, rplan, st, results, kRefFinal, 1, 0, 0, max_iters, tol, 1, s);
+      if (v != LLP_OK) return v;
+    }
+    HIP_TRY(launch_ref_elem(rep ? kRefOutputBack : kRefOutput, d_ref, nf, rplan.eblocks, st, 1, s));
+    if (rep) {
+      v = ref_pass(d_ref, rplan, st, results, kRefOut, 1, 0, 0, max_iters, tol, 1, s);
+      if (v != LLP_OK) return v;
       for (int i = 0; i < nf; ++i) {
         const SceneDesc& d = tab[i];
-        const OpConfig& cfg = fast[i].cfg;
         ChanState* sst = st + d.band0;
         double* sres = results + (size_t)d.band0 * kResultSlots;
-        HIP_TRY(launch_dir(d.g, cfg, 0, 0, 0, d.x, nullptr, nullptr, nullptr, nullptr, nullptr, d.y, d.u,
-                           d.partials, sst, 0, 0.0f, s));
-        HIP_TRY(launch_apply(d.g, cfg, 0, d.x, nullptr, d.y, d.u, d.G, d.MU, d.DI, d.q, d.partials, sst, s));
-        HIP_TRY(launch_residual_norm(d.g, d.b, d.q, d.partials, sst, sres, s));
         HIP_TRY(launch_objective(d.g, d.x, d.X, d.u, d.G, d.MU, d.DI, d.partials, sst, sres, s));
       }
       HIP_TRY(hipMemcpyAsync(ctx->h_bres, results, sizeof(double) * kResultSlots * nbands, hipMemcpyDeviceToHost,
@@ -445,7 +486,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       for (int c = 0; c < d.g.N; ++c) {
         const ChanState& cs = ctx->h_bst[0][d.band0 + c];
         const int bst = ctx->h_bflags[i] ? LLP_E_NONFINITE
-                                          : (cs.active ? (tol_mode ? LLP_NOT_CONVERGED : LLP_OK) : cs.status);
+                                          : ((cs.active || cs.pending) ? (tol_mode ? LLP_NOT_CONVERGED : LLP_OK)
+                                                                       : cs.status);
         merge(bst);
         if (rep) {
           llp_report& R = rep[fast[i].rep0 + c];
@@ -456,6 +498,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
           const double bn2 = cs.bnorm2;
           R.rel_residual = bn2 > 0 ? sqrt(cs.rho / bn2) : sqrt(cs.rho);
           R.true_rel_residual = bn2 > 0 ? sqrt(res[kSlotTrueRes] / bn2) : sqrt(res[kSlotTrueRes]);
+          R.out_rel_residual = bn2 > 0 ? sqrt(res[kSlotOutRes] / bn2) : sqrt(res[kSlotOutRes]);
           R.objective = 0.5 * res[kSlotObjData] + 0.5 * (double)d.g.lam * res[kSlotObjLlp];
         }
       }

@@ -42,7 +42,7 @@ bool pick_config(const Geom& g, OpConfig* cfg, bool allow_fast = true, int want_
 // The configuration a context uses for g: environment overrides, else a tuned entry (for batched solves the
 // batched entry of the class if there is one, then the single-scene entry), else the default.
 bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg, bool batched = false);
-llp_status ensure_workspace(llp_ctx* ctx, const Geom& g);
+llp_status ensure_workspace(llp_ctx* ctx, const Geom& g, bool precond = false);
 hipEvent_t timing_event(llp_ctx* ctx);
 llp_status collect_times(llp_ctx* ctx);
 llp_status check_inputs(llp_ctx* ctx, const Geom& g, const float* lrms, const float* pan, const float* kernel,
@@ -65,6 +65,18 @@ void cnn_free(CnnState* c);
 llp_status cnn_warm_start(llp_ctx* ctx, const Geom& g, const float* X, const float* Y, float* z0, float* netout,
                           hipStream_t s);
 
+// Launch sizes of a residual-replacement pass over a RefDesc table (blocks and LDS over all its scenes).
+struct RefPlan {
+  int count = 0, bands = 0;
+  int eblocks = 0, yblocks = 0, rblocks = 0;
+  size_t ylds = 0, rlds = 0;
+};
+// Assigns the table's block offsets (e_block0, y_block0, r_block0) in order and sums the plan.
+void ref_plan(RefDesc* tab, int count, RefPlan* plan);
+// One replacement pass over the table: flush (except for kRefOut), D B x, residual, finalisation fin_op.
+llp_status ref_pass(const RefDesc* d_tab, const RefPlan& P, ChanState* st, double* results, int fin_op, int force,
+                    int rpar, int write_r, int max_iters, float tol, int plain_cg, hipStream_t s);
+
 // The whole single-scene solve with launch configuration cfg (the body of llp_pansharpen).
 llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const llp_params* params,
                        const float* lrms, const float* pan, const float* kernel, const float* init, float* hrms,
@@ -86,6 +98,20 @@ struct llp_ctx {
   float* r[2] = {nullptr, nullptr};  // residual, alternating between iterations
   float* p[2] = {nullptr, nullptr};  // direction, alternating between iterations
   double* partials = nullptr;
+  double* xacc = nullptr;  // FP64 part of the iterate [N][H][W]
+  double* y64 = nullptr;   // D B x of the FP64 residual pass [N][h][w]
+  llp::RefDesc* d_ref = nullptr;  // the scene's residual-pass table (one entry)
+  llp::RefDesc* h_ref = nullptr;  // pinned host copy
+  // preconditioner (solves with precond = 1)
+  float* s = nullptr;      // P^{-1} r [N][H][W]
+  float* spec = nullptr;   // spectra of the band pairs
+  float* uhat = nullptr;   // kernel DFT at the group members
+  float* tw = nullptr;     // twiddle tables
+  double* mbar = nullptr;  // mbar, then kPcMbarBlocks partials
+  llp::PcDesc* d_pc = nullptr;
+  llp::PcDesc* h_pc = nullptr;  // pinned
+  float* h_tw = nullptr;        // pinned twiddle staging
+  size_t h_tw_cap = 0;
   llp::ChanState* st = nullptr;
   double* results = nullptr;
   int* flags = nullptr;
@@ -109,6 +135,7 @@ struct llp_ctx {
   double* h_bres = nullptr;
   int* h_bflags = nullptr;
   llp::SceneDesc* h_table = nullptr;
+  llp::RefDesc* h_rtable = nullptr;
   int hb_bands = 0, hb_scenes = 0;  // capacities of the batch mirrors
   hipGraphExec_t gexec = nullptr;
   std::vector<long long> gkey;  // what the cached graph was captured for

@@ -77,7 +77,7 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, vo, so, 0);
   };
   const __amdgpu_buffer_rsrc_t Rr = rsrc(A.rin);
-  const __amdgpu_buffer_rsrc_t Rq = rsrc(MODE == 2 ? A.qin : A.rin), Rp = rsrc(MODE == 2 ? A.pin : A.rin);
+  const __amdgpu_buffer_rsrc_t Rq = rsrc(MODE == 2 ? A.qin : A.rin), Rp = rsrc(MODE >= 2 ? A.pin : A.rin);
   const __amdgpu_buffer_rsrc_t Rro = rsrc(MODE == 2 ? A.rout : A.rin), Rx = rsrc(MODE == 2 ? A.x : A.rin);
   const __amdgpu_buffer_rsrc_t Rpo = rsrc(MODE != 0 ? A.pout : A.rin);
 
@@ -111,10 +111,8 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
 #pragma unroll
         for (int ci = 0; ci < NCI; ++ci) {
           rv[j][ci] = ld(Rr, vld[ci], so[j]);
-          if (MODE == 2) {
-            qv[j][ci] = ld(Rq, vld[ci], so[j]);
-            pv[j][ci] = ld(Rp, vld[ci], so[j]);
-          }
+          if (MODE == 2) qv[j][ci] = ld(Rq, vld[ci], so[j]);
+          if (MODE >= 2) pv[j][ci] = ld(Rp, vld[ci], so[j]);
         }
         if (MODE == 2 && own_row) {
 #pragma unroll
@@ -132,13 +130,17 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
       float vv[NCI];
 #pragma unroll
       for (int ci = 0; ci < NCI; ++ci)
-        vv[ci] = MODE == 2 ? fmaf(beta, pv[j][ci], fmaf(-alpha, qv[j][ci], rv[j][ci])) : rv[j][ci];
+        vv[ci] = MODE == 2   ? fmaf(beta, pv[j][ci], fmaf(-alpha, qv[j][ci], rv[j][ci]))
+                 : MODE == 3 ? fmaf(beta, pv[j][ci], rv[j][ci])
+                             : rv[j][ci];
       if (MODE != 0 && own_row) {
 #pragma unroll
         for (int ci = 0; ci < NCI; ++ci) {
           if (MODE == 1) {
             st(vv[ci], Rpo, vown[ci], so[j]);
             acc += (double)(vown[ci] != kNoAccess ? vv[ci] * vv[ci] : 0.0f);
+          } else if (MODE == 3) {
+            st(vv[ci], Rpo, vown[ci], so[j]);
           } else {
             const float rn = fmaf(-alpha, qv[j][ci], rv[j][ci]);
             st(rn, Rro, vown[ci], so[j]);
@@ -189,7 +191,7 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
     }
   }
 
-  if (MODE == 0) return;
+  if (MODE == 0 || MODE == 3) return;
   double v[1] = {acc};
   block_partials<1, NW>(v, red, A.partials + (size_t)ch * A.pstride * 3 + tile);
 }
@@ -602,8 +604,8 @@ __device__ __forceinline__ int find_scene(const SceneDesc* __restrict__ t, int c
   return lo;
 }
 
-// Batched CG iteration kernels (mode 2 / mode 1 of the single-scene kernels) over a table of scenes.
-template <int C, int R, int TYL>
+// Batched CG iteration kernels (mode 2 or 3 / mode 1 of the single-scene kernels) over a table of scenes.
+template <int C, int R, int TYL, int MODE>
 __global__ __launch_bounds__(TYL * 64) void k_dir_fast_batch(const SceneDesc* __restrict__ t, int count, int parity,
                                                            ChanState* __restrict__ st, char* __restrict__ ws,
                                                            const float* __restrict__ taps) {
@@ -612,8 +614,8 @@ __global__ __launch_bounds__(TYL * 64) void k_dir_fast_batch(const SceneDesc* __
   const int local = blockIdx.x - d.dir_block0;  // scenes start on multiples of 8 workgroups (one per XCD)
   if (local >= d.dir_ntiles * d.g.N) return;
   DirArgs A{};
-  A.mode = 2;
-  A.rin = (const float*)(ws + d.o_r[parity]);
+  A.mode = MODE;
+  A.rin = (const float*)(ws + (MODE == 3 ? d.o_s : d.o_r[parity]));
   A.qin = (const float*)(ws + d.o_q);
   A.pin = (const float*)(ws + d.o_p[parity]);
   A.rout = (float*)(ws + d.o_r[1 - parity]);
@@ -626,7 +628,7 @@ __global__ __launch_bounds__(TYL * 64) void k_dir_fast_batch(const SceneDesc* __
   A.tiles_x = (d.g.w + DirShape<C, R, TYL>::TXL - 1) / DirShape<C, R, TYL>::TXL;
   A.ntiles = d.dir_ntiles;
   A.PS = DirShape<C, R, TYL>::PS;
-  dir_fast_body<C, R, TYL, 2>(d.g, A, taps + (size_t)d.taps_index * kTapStride, local);
+  dir_fast_body<C, R, TYL, MODE>(d.g, A, taps + (size_t)d.taps_index * kTapStride, local);
 }
 
 template <int C, int R, int r, int TH, int TW>
@@ -682,6 +684,7 @@ hipError_t run_dir_fast_t(const Geom& g, DirArgs A, const float* u, hipStream_t 
   switch (A.mode) {
     case 0: return run_dir_fast_m<C, R, TYL, 0>(g, A, u, s);
     case 1: return run_dir_fast_m<C, R, TYL, 1>(g, A, u, s);
+    case 3: return run_dir_fast_m<C, R, TYL, 3>(g, A, u, s);
     default: return run_dir_fast_m<C, R, TYL, 2>(g, A, u, s);
   }
 }
@@ -775,16 +778,23 @@ hipError_t launch_apply_fast(const Geom& g, int variant, ApplyArgs A, const floa
 
 namespace {
 
-template <int C, int R, int TYL>
-hipError_t run_dir_batch(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, char* ws,
-                         const float* taps, hipStream_t s) {
+template <int C, int R, int TYL, int MODE>
+hipError_t run_dir_batch_m(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, char* ws,
+                           const float* taps, hipStream_t s) {
   const size_t bytes = (size_t)DirShape<C, R, TYL>::LDS_ALLOC * sizeof(float);
-  hipError_t e = set_lds_fast(k_dir_fast_batch<C, R, TYL>, bytes);
+  hipError_t e = set_lds_fast(k_dir_fast_batch<C, R, TYL, MODE>, bytes);
   if (e != hipSuccess) return e;
   if (blocks == 0) return hipSuccess;  // prepare only (before a graph capture)
-  hipLaunchKernelGGL((k_dir_fast_batch<C, R, TYL>), dim3(blocks), dim3(DirShape<C, R, TYL>::NW * 64), bytes, s, t,
-                     count, parity, st, ws, taps);
+  hipLaunchKernelGGL((k_dir_fast_batch<C, R, TYL, MODE>), dim3(blocks), dim3(DirShape<C, R, TYL>::NW * 64), bytes, s,
+                     t, count, parity, st, ws, taps);
   return hipGetLastError();
+}
+
+template <int C, int R, int TYL>
+hipError_t run_dir_batch(const SceneDesc* t, int count, int blocks, int parity, ChanState* st, char* ws,
+                         const float* taps, int mode, hipStream_t s) {
+  return mode == 3 ? run_dir_batch_m<C, R, TYL, 3>(t, count, blocks, parity, st, ws, taps, s)
+                   : run_dir_batch_m<C, R, TYL, 2>(t, count, blocks, parity, st, ws, taps, s);
 }
 
 template <int C, int R, int r, int TH, int TW>
@@ -802,11 +812,11 @@ hipError_t run_apply_batch(const SceneDesc* t, int count, int blocks, int parity
 }  // namespace
 
 hipError_t launch_dir_fast_batch(const SceneDesc* table, int count, int total_blocks, int C, int R, int tyl,
-                                 int parity, ChanState* st, char* ws, const float* taps, hipStream_t s) {
-#define LLP_DIRB_CASE(CC, RR, rr)                                                                     \
-  if (C == CC && R == RR)                                                                             \
-    return tyl == 8 ? run_dir_batch<CC, RR, 8>(table, count, total_blocks, parity, st, ws, taps, s) \
-                    : run_dir_batch<CC, RR, 4>(table, count, total_blocks, parity, st, ws, taps, s);
+                                 int parity, ChanState* st, char* ws, const float* taps, int mode, hipStream_t s) {
+#define LLP_DIRB_CASE(CC, RR, rr)                                                                           \
+  if (C == CC && R == RR)                                                                                   \
+    return tyl == 8 ? run_dir_batch<CC, RR, 8>(table, count, total_blocks, parity, st, ws, taps, mode, s) \
+                    : run_dir_batch<CC, RR, 4>(table, count, total_blocks, parity, st, ws, taps, mode, s);
   LLP_FAST_R_LIST2(LLP_DIRB_CASE, 0)
   LLP_FAST_R_LIST4(LLP_DIRB_CASE, 0)
 #undef LLP_DIRB_CASE

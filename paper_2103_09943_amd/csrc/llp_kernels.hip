@@ -85,22 +85,57 @@ hipError_t launch_pan_stats(const Geom& g, const float* Y, float* G, float* mu, 
 
 // ------------------------------------------------------------------------------- reduction finalisation ---
 
-// Applies a band's summed partials s[] (op kFinDir: rho of x_k; kFinApply: gamma, sigma, tau) to its CG state.
+// The stopping rule after iterate x_k, from rr = |r_k|^2 of the recursion.
+__device__ __forceinline__ void stop_rule(ChanState& c, double rr, int k_iter, int max_iters, float tol) {
+  c.iters = k_iter;
+  if (!isfinite(rr)) {
+    c.status = -6;
+    c.active = 0;
+  } else if (rr == 0.0 || (tol > 0.0f && sqrt(rr) <= (double)tol * sqrt(c.bnorm2))) {
+    c.active = 0;
+    if (tol > 0.0f) c.pending = 1;  // stops only once the residual recomputed from the iterate agrees
+    else c.status = 0;
+  } else if (k_iter >= max_iters) {
+    c.status = tol > 0.0f ? 1 : 0;
+    c.active = 0;
+  }
+}
+
+// Applies a band's summed partials s[] to its CG state.  kFinDir: rho of x_k; kFinApply: gamma, sigma, tau.
+// Preconditioned iteration: kFinPcgStart and kFinPcgBeta: |r|^2, r^T s; kFinPcgAlpha: gamma; kFinPcgStop: none.
 __device__ void finish_band(int op, const double (&s)[3], ChanState& c, int k_iter, int max_iters, float tol) {
   if (op == kFinDir) {  // rho_k of the iterate x_k, and the stopping rule
-    const double rho = s[0];
-    c.rho = rho;
-    c.iters = k_iter;
-    if (!isfinite(rho)) {
+    c.rho = s[0];
+    stop_rule(c, s[0], k_iter, max_iters, tol);
+  } else if (op == kFinPcgStart) {  // r_0^T r_0, rho_0 = r_0^T P^{-1} r_0
+    c.rr = s[0];
+    c.rho = s[1];
+    if (!isfinite(s[1]) || s[1] < 0.0) {
       c.status = -6;
       c.active = 0;
-    } else if (rho == 0.0 || (tol > 0.0f && sqrt(rho) <= (double)tol * sqrt(c.bnorm2))) {
-      c.status = 0;
-      c.active = 0;
-    } else if (k_iter >= max_iters) {
-      c.status = tol > 0.0f ? 1 : 0;
-      c.active = 0;
+    } else {
+      stop_rule(c, s[0], 0, max_iters, tol);
     }
+  } else if (op == kFinPcgAlpha) {  // alpha_k = rho / p^T A p
+    const double gam = s[0];
+    c.gamma = gam;
+    if (!(gam > 0.0) || !isfinite(gam)) {
+      c.status = -6;
+      c.active = 0;
+    } else {
+      c.alpha = c.rho / gam;
+    }
+  } else if (op == kFinPcgBeta) {  // |r_k|^2 and rho_k = r_k^T P^{-1} r_k -> beta_k
+    if (!isfinite(s[0]) || !isfinite(s[1]) || s[1] < 0.0) {
+      c.status = -6;
+      c.active = 0;
+    } else {
+      c.beta = c.rho > 0.0 ? s[1] / c.rho : 0.0;
+      c.rho = s[1];
+      c.rr = s[0];
+    }
+  } else if (op == kFinPcgStop) {  // end of iteration k: the stopping rule on |r_k|
+    stop_rule(c, c.rr, k_iter, max_iters, tol);
   } else if (op == kFinApply) {  // gamma = p^T A p, sigma = r^T A p, tau = |A p|^2 -> alpha, beta
     const double gam = s[0], sig = s[1], tau = s[2];
     c.gamma = gam;
@@ -115,6 +150,11 @@ __device__ void finish_band(int op, const double (&s)[3], ChanState& c, int k_it
       c.beta = rt / c.rho;
     }
   }
+}
+
+// Doubles per workgroup partial of each finalisation.
+__device__ __forceinline__ int fin_values(int op) {
+  return (op == kFinApply || op == kFinPcgStart || op == kFinPcgAlpha || op == kFinPcgBeta) ? 3 : 1;
 }
 
 // Sum, in a fixed order, of nblk partials of K doubles each (result in thread 0).
@@ -133,14 +173,14 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int op, const double* __res
                                                      int max_iters, float tol) {
   __shared__ double red[3 * kWaves];
   const int ch = blockIdx.x;
-  if ((op == kFinDir || op == kFinApply) && !st[ch].active) return;
+  if (op != kFinBnorm && op != kFinResult && !st[ch].active) return;
   double s[3];
-  sum_partials(partials + (size_t)ch * pstride * 3, nblk, op == kFinApply ? 3 : 1, s, red);
+  sum_partials(partials + (size_t)ch * pstride * 3, nblk, fin_values(op), s, red);
   if (threadIdx.x != 0) return;
   ChanState& c = st[ch];
   if (op == kFinBnorm) c.bnorm2 = s[0];
   else if (op == kFinResult) results[ch * kResultSlots + slot] = s[0];
-  else finish_band(op, s, c, k_iter, max_iters, tol);
+  else finish_band(op, s, c, k_iter < 0 ? c.iters + 1 : k_iter, max_iters, tol);  // k_iter < 0: the band's next
 }
 
 // Batched finalisation (kFinDir / kFinApply) over every band of a scene table; one workgroup per band.  The
@@ -159,13 +199,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(int op, const SceneDe
   }
   const SceneDesc& d = t[lo];
   const int ch = band - d.band0;
-  const int nblk = op == kFinApply ? d.apply_ntiles : d.dir_ntiles;
+  const int nblk = (op == kFinApply || op == kFinPcgAlpha) ? d.apply_ntiles
+                   : op == kFinDir                          ? d.dir_ntiles
+                   : op == kFinPcgStop                      ? 0
+                                                            : d.g.h;  // the preconditioner's rows
   double s[3];
-  sum_partials((const double*)(ws + d.o_partials) + (size_t)ch * d.pstride * 3, nblk, op == kFinApply ? 3 : 1, s,
-               red);
+  sum_partials((const double*)(ws + d.o_partials) + (size_t)ch * d.pstride * 3, nblk, fin_values(op), s, red);
   if (threadIdx.x != 0) return;
   ChanState& c = st[band];
-  finish_band(op, s, c, c.iters + 1, max_iters, tol);
+  finish_band(op, s, c, op == kFinPcgStart ? 0 : c.iters + 1, max_iters, tol);
 }
 
 hipError_t launch_finalize_batch(int op, const SceneDesc* table, int count, int bands, ChanState* st,
@@ -247,22 +289,18 @@ hipError_t launch_rhs(const Geom& g, const float* X, const float* u, float* b, d
 }
 
 // ------------------------------------------------------------------------------ CG start (a4, a7) ---
-// r_0 = b (start from Z = 0, which is written to x) or r_0 = b - q (q = A Z0, x already holds Z0); the band
-// states are reset by the first workgroup of each band.  rho_0 is summed by the first k_dir launch.
+// Resets the band states (first workgroup of each band) and, for a start from Z = 0, sets r_0 = b.  A start
+// from a given Z0 gets r_0 = b - A Z0 from the FP64 residual pass instead.  rho_0 is summed by the first k_dir
+// launch.
 __global__ __launch_bounds__(kBlock) void k_init(Geom g, int from_init, const float* __restrict__ b,
-                                                 const float* __restrict__ q, float* __restrict__ r,
-                                                 float* __restrict__ x, ChanState* __restrict__ st) {
+                                                 float* __restrict__ r, ChanState* __restrict__ st) {
   const int ch = blockIdx.y;
   const size_t HW = (size_t)g.H * g.W;
   const size_t base = (size_t)ch * HW;
   const size_t e0 = (size_t)blockIdx.x * kChunk;
   const size_t e1 = e0 + kChunk < HW ? e0 + kChunk : HW;
-  for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-    float v = b[base + e];
-    if (from_init) v -= q[base + e];
-    else x[base + e] = 0.0f;
-    r[base + e] = v;
-  }
+  if (!from_init)
+    for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) r[base + e] = b[base + e];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ChanState& s = st[ch];
     s.rho = 0.0;
@@ -273,22 +311,23 @@ __global__ __launch_bounds__(kBlock) void k_init(Geom g, int from_init, const fl
     s.active = 1;
     s.status = 0;
     s.init = from_init ? kInitUser : kInitZero;
+    s.pending = 0;
+    s.last_rep = 0;
   }
 }
 
-hipError_t launch_init(const Geom& g, int from_init, const float* b, const float* q, float* r, float* x,
-                       ChanState* st, hipStream_t s) {
+hipError_t launch_init(const Geom& g, int from_init, const float* b, float* r, ChanState* st, hipStream_t s) {
   const size_t HW = (size_t)g.H * g.W;
   const int nblk = (int)((HW + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_init, dim3(nblk, g.N), dim3(kBlock), 0, s, g, from_init, b, q, r, x, st);
+  hipLaunchKernelGGL(k_init, dim3(nblk, g.N), dim3(kBlock), 0, s, g, from_init, b, r, st);
   return hipGetLastError();
 }
 
-// Check of a network start z0 (x = z0, r = b - A z0, results[kSlotTrueRes] = ||r||^2): a band whose start is no
-// better than Z = 0 (||r||^2 >= ||b||^2) restarts from Z = 0.  Records the band's start in its state.
+// Check of a network start z0 (xacc = z0, r = b - A z0, results[kSlotTrueRes] = ||r||^2): a band whose start is
+// no better than Z = 0 (||r||^2 >= ||b||^2) restarts from Z = 0.  Records the band's start in its state.
 __global__ __launch_bounds__(kBlock) void k_fallback(Geom g, const double* __restrict__ results,
                                                      ChanState* __restrict__ st, const float* __restrict__ b,
-                                                     float* __restrict__ r, float* __restrict__ x) {
+                                                     float* __restrict__ r, double* __restrict__ x) {
   const int ch = blockIdx.y;
   const bool reject = !(results[ch * kResultSlots + kSlotTrueRes] < st[ch].bnorm2);
   const size_t HW = (size_t)g.H * g.W;
@@ -297,15 +336,15 @@ __global__ __launch_bounds__(kBlock) void k_fallback(Geom g, const double* __res
   const size_t e1 = e0 + kChunk < HW ? e0 + kChunk : HW;
   if (reject) {
     for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-      x[base + e] = 0.0f;
+      x[base + e] = 0.0;
       r[base + e] = b[base + e];
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) st[ch].init = reject ? kInitNetRejected : kInitNet;
 }
 
-hipError_t launch_fallback(const Geom& g, const double* results, ChanState* st, const float* b, float* r, float* x,
-                           hipStream_t s) {
+hipError_t launch_fallback(const Geom& g, const double* results, ChanState* st, const float* b, float* r,
+                           double* x, hipStream_t s) {
   const size_t HW = (size_t)g.H * g.W;
   const int nblk = (int)((HW + kChunk - 1) / kChunk);
   hipLaunchKernelGGL(k_fallback, dim3(nblk, g.N), dim3(kBlock), 0, s, g, results, st, b, r, x);

@@ -74,6 +74,9 @@ __global__ __launch_bounds__(kBlock) void k_dir(Geom g, DirArgs A, const float* 
           A.pout[off] = v;
           acc += (double)v * v;
         }
+      } else if (A.mode == 3) {
+        v = fmaf(beta, A.pin[off], A.rin[off]);
+        if (own) A.pout[off] = v;
       } else {
         const float pv = A.pin[off];
         const float rn = fmaf(-alpha, A.qin[off], A.rin[off]);
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(Geom g, DirArgs A, const float* 
     }
   }
 
-  if (A.mode == 0) return;
+  if (A.mode == 0 || A.mode == 3) return;
   double v[1] = {acc};
   block_partials<1>(v, red, A.partials + (size_t)ch * A.pstride * 3 + tile);
 }
@@ -516,6 +519,11 @@ size_t max_partials_per_band(const Geom& g) {
   // column sweep: strips of at least 52 columns, segments of at least kMinSegRows rows
   const size_t sw = (size_t)((g.W + 51) / 52) * ((g.H + kMinSegRows - 1) / kMinSegRows);
   if (sw > m) m = sw;
+  // preconditioner: one per LR row
+  if ((size_t)g.h > m) m = g.h;
+  // FP64 residual replacement: one per tile of 8 x 64 pixels
+  const size_t rt = (size_t)ref_res_blocks(g) / g.N;
+  if (rt > m) m = rt;
   return m;
 }
 

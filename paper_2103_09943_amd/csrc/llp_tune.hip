@@ -180,6 +180,7 @@ llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* 
   const llp_kernel_times saved = ctx->times;
   ctx->profiling = true;
   double best_us = 0.0, def_us = 0.0;
+  bool have_best = false;
   OpConfig best = cands[0];
   for (const OpConfig& c : cands) {
     double us = 0.0;
@@ -250,6 +251,7 @@ llp_status llp_autotune_batch(llp_ctx* ctx, const llp_shape* shape, const llp_pa
   // Per candidate and iteration count (iters, 2 iters): one untimed solve (graph capture, workspace), then the
   // fastest of kRuns solves; the difference of the two is the time of iters iterations without the set-up work.
   double best_us = 0.0, def_us = 0.0;
+  bool have_best = false;
   OpConfig best = cands[0];
   for (const OpConfig& c : cands) {
     double t[2] = {0.0, 0.0};
@@ -264,15 +266,23 @@ llp_status llp_autotune_batch(llp_ctx* ctx, const llp_shape* shape, const llp_pa
     }
     if (v != LLP_OK) break;
     const double t1 = t[0], t2 = t[1];
-    const double us = (t2 > t1 ? t2 - t1 : 0.0) * 1e6 / (double)iters / (double)copies;
+    if (!(t2 > t1)) continue;  // noise swamped the difference: no valid measurement for this candidate
+    const double us = (t2 - t1) * 1e6 / (double)iters / (double)copies;
     if (same(c, def)) def_us = us;
-    if (best_us == 0.0 || us < best_us) {
+    if (!have_best || us < best_us) {
+      have_best = true;
       best_us = us;
       best = c;
     }
   }
   (void)hipFree(outbuf);
   if (v != LLP_OK) return v;
+  if (!have_best) {  // nothing measured: keep the table as it is
+    if (out) {
+      *out = llp_tune_result{def.fast, def.dir_rows, def.apply_variant, def.seg_rows, 0.0, 0.0, (int)cands.size()};
+    }
+    return LLP_NOT_CONVERGED;
+  }
   if (def_us > 0.0 && !(best_us < kMargin * def_us)) {
     best = def;
     best_us = def_us;

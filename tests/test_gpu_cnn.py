@@ -140,7 +140,7 @@ def test_network_start_of_the_solve(ctx, torch_dev):
     assert status == B.OK
     assert all(r["init"] == B.INIT_NET for r in warm), warm
     assert all(r["init"] == B.INIT_ZERO for r in cold)
-    assert all(r["rel_residual"] <= 1e-6 for r in warm)
+    assert all(r["true_rel_residual"] <= 1e-6 for r in warm)
     # the (nearly untrained) network's estimate is about the bicubic upsampling: a start closer than zero
     assert np.mean([w["iters"] for w in warm]) < np.mean([c["iters"] for c in cold])
     np.testing.assert_allclose([w["objective"] for w in warm], [c["objective"] for c in cold], rtol=1e-6)
@@ -175,3 +175,61 @@ def test_batch_network_start_matches_single(ctx, torch_dev):
         Zs, rs_s, _ = ctx.pansharpen(X, Y, u, init="cnn", **kw)
         assert torch_dev.equal(Z, Zs) and rs == rs_s
         assert all(r["init"] in (B.INIT_NET, B.INIT_NET_REJECTED) for r in rs)
+
+
+def test_adam_three_steps_match_oracle(ctx, torch_dev):
+    """Three consecutive training steps against the oracle's Adam fed with the library's own gradient at each
+    step (the moments and bias corrections past the first step)."""
+    flat = params_for(9, last_std=0.1)
+    ctx.cnn_set_weights(flat)
+    X, Y, sc = small_scene(9, N=2, side=64)
+    args = (dev(torch_dev, X), dev(torch_dev, Y), dev(torch_dev, sc.Z[:2]), 4)
+    lr = 1e-3
+    params = cnn.unflatten(flat)
+    state = (0, [], [])
+    for step in range(3):
+        _, g = ctx.cnn_loss_grad(*args)  # the gradient the next training step uses (deterministic)
+        ctx.cnn_train_step(*args, lr=lr)
+        params, state = cnn.adam_step(params, cnn.unflatten(g), state, lr)
+        got = ctx.cnn_get_weights().astype(np.float64)
+        want = cnn.flatten(params)
+        # FP32 master weights and moments against FP64: each step moves a weight by at most about lr
+        np.testing.assert_allclose(got, want, rtol=0, atol=3e-6 * (step + 1), err_msg=f"step {step + 1}")
+        params = cnn.unflatten(got)  # continue from the library's FP32 weights
+
+
+def test_gradients_match_oracle_at_training_size(ctx, torch_dev):
+    """A 4-band 256 x 256 training scene: 1024 tiles of 4 x 64 pixels for the weight-gradient kernel's 512
+    persistent workgroups, so every workgroup accumulates two tiles."""
+    flat = params_for(10, last_std=0.1)
+    ctx.cnn_set_weights(flat)
+    sc, _ = scenes.config_scene(3, 10)
+    X, Y, Z = sc.X, sc.Y, sc.Z
+    assert X.shape == (4, 64, 64) and Y.shape == (256, 256)
+    loss, g = ctx.cnn_loss_grad(dev(torch_dev, X), dev(torch_dev, Y), dev(torch_dev, Z), 4)
+    params = cnn.unflatten(flat)
+    tot_loss, tot = 0.0, None
+    for b in range(4):
+        inp, _, _ = cnn.net_input(X[b], Y, 4)
+        t = cnn.training_target(X[b], Z[b], 4)
+        lb, gb = cnn.loss_and_grads(params, inp, t, quantize=True)
+        tot_loss += lb / 4
+        gb = [(dW / 4, db / 4) for dW, db in gb]
+        tot = gb if tot is None else [(a[0] + b_[0], a[1] + b_[1]) for a, b_ in zip(tot, gb)]
+    assert abs(loss - tot_loss) <= 1e-4 * tot_loss
+    for k, ((gW, gb_), (wW, wb)) in enumerate(zip(cnn.unflatten(g), tot)):
+        assert rel(gW, wW) < 1e-2, (k, rel(gW, wW))
+        assert rel(gb_, wb) < 1e-2, (k, rel(gb_, wb))
+
+
+def test_forward_matches_oracle_at_512(ctx, torch_dev):
+    """The network's estimate on a held-out 512 x 512 band (the size of the warm-start evaluation scenes)."""
+    flat = params_for(11)
+    ctx.cnn_set_weights(flat)
+    sc, _ = scenes.config_scene(3, 2000)
+    X, Y = np.ascontiguousarray(sc.X[:1]), sc.Y
+    z0, out = ctx.cnn_warm_start(dev(torch_dev, X), dev(torch_dev, Y), 4, z0=True, net_out=True)
+    inp, x_up, s = cnn.net_input(X[0], Y, 4)
+    want, _ = cnn.forward(cnn.unflatten(flat), inp, quantize=True)
+    assert rel(host(out[0]), want[0]) < 2e-3
+    assert rel(host(z0[0]), x_up + s * want[0]) < 1e-4

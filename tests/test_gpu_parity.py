@@ -5,6 +5,9 @@ FP64); the CG iterate after a fixed iteration count to relative L2 <= 1e-5 per b
 1e-6, the objective of the returned HRMS within 1e-6 (relative) of the objective at the exact minimiser.
 The oracle always receives the same float32-rounded inputs (and float32-rounded lambda, eps) as the library.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -50,6 +53,15 @@ def rel_l2(got, want):
 
 def rng_for(*key):
     return np.random.default_rng(np.random.SeedSequence([11, *key]))
+
+
+def out_residual(prob, b, Z):
+    """||f32(b) - A Z|| / ||f32(b)|| per band in FP64: the residual of a float32 HRMS against the float32-rounded
+    right-hand side (the one the library holds)."""
+    b32 = b.astype(np.float32).astype(np.float64)
+    res = b32 - oracle.apply_A(Z, prob)
+    N = b.shape[0]
+    return np.linalg.norm(res.reshape(N, -1), axis=1) / np.linalg.norm(b32.reshape(N, -1), axis=1)
 
 
 # ------------------------------------------------------------------------------------------ operators ---
@@ -108,6 +120,27 @@ def test_apply_A(ctx, torch_dev, shape):
     prob = Problem(u=u, c=c, Y=Y, r=r, lam=f32(lam), eps=f32(eps))
     err = rel_l2(host(got), oracle.apply_A(P, prob))
     assert np.all(err < 1e-5), err
+
+
+@pytest.mark.parametrize("shape", OP_SHAPES)
+def test_apply_data_and_llp_terms(ctx, torch_dev, shape):
+    """The two terms of the matrix of eq. (Z_ini_matting) separately (llp_apply_data, llp_apply_llp)."""
+    N, h, w, c, n, r = shape
+    rng = rng_for(7, *shape)
+    X, Y, u, P = scenes.random_problem(rng, N, h * c, w * c, c, n)
+    lam, eps = 0.05, 1e-3
+    prob = Problem(u=u, c=c, Y=Y, r=r, lam=f32(lam), eps=f32(eps))
+    Pd = dev(torch_dev, P)
+    got_d = ctx.apply_data(Pd, dev(torch_dev, u), c=c, r=r)
+    got_l = ctx.apply_llp(Pd, dev(torch_dev, Y), dev(torch_dev, u), c=c, r=r, lam=lam, eps=eps)
+    # a window of one pixel (r = 0) gives M = 0: the LLP term is then 0 and is measured against ||A P||
+    scale = np.linalg.norm(oracle.apply_A(P, prob).reshape(N, -1), axis=1)
+    err_d = rel_l2(host(got_d), oracle.apply_data(P, prob))
+    want_l = oracle.apply_llp(P, prob)
+    err_l = (np.linalg.norm((host(got_l) - want_l).reshape(N, -1), axis=1)
+             / np.maximum(np.linalg.norm(want_l.reshape(N, -1), axis=1), 1e-3 * scale))
+    assert np.all(err_d < 1e-5), err_d
+    assert np.all(err_l < 1e-5), err_l
 
 
 @pytest.mark.parametrize("shape", OP_SHAPES[:4])
@@ -186,27 +219,31 @@ def test_cg_fixed_iterations_parity(ctx, torch_dev, scene0):
     assert list(its) == [50] * 4
     err = rel_l2(host(Z), want)
     assert np.all(err < 1e-5), err
-    # the reported residual and objective describe the returned iterate
-    res = b - oracle.apply_A(host(Z), prob)
-    true_rel = np.linalg.norm(res.reshape(4, -1), axis=1) / np.linalg.norm(b.reshape(4, -1), axis=1)
+    # the reported residuals and objective describe the returned iterate: out_rel_residual is the FP64 residual
+    # of the float32 output (against the float32-rounded right-hand side the library holds), true_rel_residual
+    # that of the iterate before the rounding (the same to a few float32 roundings at this residual level)
+    true_rel = out_residual(prob, b, host(Z))
+    np.testing.assert_allclose([r["out_rel_residual"] for r in rep], true_rel, rtol=1e-6)
     np.testing.assert_allclose([r["true_rel_residual"] for r in rep], true_rel, rtol=1e-3)
     np.testing.assert_allclose([r["objective"] for r in rep], oracle.objective(host(Z), sc.X, prob), rtol=1e-6)
 
 
 def test_cg_tolerance_objective_parity(ctx, torch_dev, scene0, scene0_exact):
-    """Run to ||r|| <= 1e-6 ||b||: the objective matches the exact minimiser's to 1e-6."""
+    """Run to ||b - A Z|| <= 1e-6 ||b||: the FP64 residual of the solver's iterate meets the tolerance, the
+    float32 output's residual is what the oracle computes for it, and the objective matches the exact
+    minimiser's to 1e-6."""
     sc, st, prob, b = scene0
     Z, rep, status = run(ctx, torch_dev, sc, st, max_iters=5000, tol=1e-6)
     assert status == B.OK
+    assert all(r["true_rel_residual"] <= 1e-6 for r in rep), rep
+    np.testing.assert_allclose([r["out_rel_residual"] for r in rep], out_residual(prob, b, host(Z)), rtol=1e-6)
     f_exact = oracle.objective(scene0_exact, sc.X, prob)
     f_gpu = oracle.objective(host(Z), sc.X, prob)
     assert np.all(np.abs(f_gpu - f_exact) / f_exact < 1e-6), (f_gpu, f_exact)
     np.testing.assert_allclose([r["objective"] for r in rep], f_gpu, rtol=1e-6)
-    assert all(r["rel_residual"] <= 1e-6 for r in rep)
     _, its = oracle.cg(prob, b, max_iters=5000, tol=1e-6)
     for r_, o in zip(rep, its):
-        assert abs(r_["iters"] - o) <= max(3, 0.05 * o), (r_["iters"], o)
-    assert all(r["true_rel_residual"] < 1e-4 for r in rep)
+        assert abs(r_["iters"] - o) <= max(8, 0.1 * o), (r_["iters"], o)
 
 
 def test_warm_start_from_solution(ctx, torch_dev, scene0, scene0_exact):
@@ -214,7 +251,8 @@ def test_warm_start_from_solution(ctx, torch_dev, scene0, scene0_exact):
     init = dev(torch_dev, scene0_exact)
     Z, rep, status = run(ctx, torch_dev, sc, st, max_iters=5000, tol=1e-6, init=init)
     assert status == B.OK
-    assert all(r["iters"] <= 5 for r in rep), rep
+    # the float32-rounded solution is a few float32 roundings away from meeting 1e-6: a few iterations remain
+    assert all(r["iters"] <= 40 and r["true_rel_residual"] <= 1e-6 for r in rep), rep
     assert np.all(rel_l2(host(Z), scene0_exact) < 1e-5)
 
 
@@ -293,13 +331,16 @@ def test_full_size_solve_to_tolerance(ctx, torch_dev, scene1):
     sc, st = scene1
     Z, rep, status = run(ctx, torch_dev, sc, st)
     assert status == B.OK, rep
-    assert all(r["rel_residual"] <= 1e-6 for r in rep)
+    assert all(r["true_rel_residual"] <= 1e-6 for r in rep), rep
     prob = Problem(u=sc.u, c=sc.c, Y=sc.Y, r=st.r, lam=f32(st.lam), eps=f32(st.eps))
     bands = [1, 6]
     Zh = host(Z[bands])
     b = oracle.rhs(sc.X[bands], prob)
-    res = b - oracle.apply_A(Zh, prob)
-    true_rel = np.linalg.norm(res.reshape(2, -1), axis=1) / np.linalg.norm(b.reshape(2, -1), axis=1)
-    assert np.all(true_rel < 1e-4), true_rel
-    np.testing.assert_allclose([rep[i]["objective"] for i in bands], oracle.objective(Zh, sc.X[bands], prob),
-                               rtol=1e-6)
+    np.testing.assert_allclose([rep[i]["out_rel_residual"] for i in bands], out_residual(prob, b, Zh), rtol=1e-5)
+    f_out = oracle.objective(Zh, sc.X[bands], prob)
+    np.testing.assert_allclose([rep[i]["objective"] for i in bands], f_out, rtol=1e-6)
+    # the objective at the exact minimiser (FP64 CG to 1e-11, tests/golden/make_scene_objectives.py)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "scene_objectives.json")))
+    for i, band in enumerate(bands):
+        f_exact = gold["bands"][str(band)]["objective"]
+        assert abs(f_out[i] - f_exact) / f_exact < 1e-6, (band, f_out[i], f_exact)

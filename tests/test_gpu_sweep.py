@@ -88,6 +88,22 @@ def test_sweep_apply_matches_oracle(sweep_ctx, torch_dev, shape):
     assert np.all(err < 1e-5), err
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+def test_sweep_terms_match_oracle(sweep_ctx, torch_dev, shape):
+    """The data term and the LLP term separately through the sweep's launch configuration."""
+    N, h, w, c, n, r = shape
+    rng = np.random.default_rng(np.random.SeedSequence([63, *shape]))
+    X, Y, u, P = scenes.random_problem(rng, N, h * c, w * c, c, n)
+    lam, eps = 0.05, 1e-3
+    prob = Problem(u=u, c=c, Y=Y, r=r, lam=f32(lam), eps=f32(eps))
+    Pd = dev(torch_dev, P)
+    err_d = rel_l2(host(sweep_ctx.apply_data(Pd, dev(torch_dev, u), c=c, r=r)), oracle.apply_data(P, prob))
+    err_l = rel_l2(host(sweep_ctx.apply_llp(Pd, dev(torch_dev, Y), dev(torch_dev, u), c=c, r=r, lam=lam, eps=eps)),
+                   oracle.apply_llp(P, prob))
+    assert np.all(err_d < 1e-5), err_d
+    assert np.all(err_l < 1e-5), err_l
+
+
 @pytest.mark.parametrize("shape", SHAPES[:4])
 def test_sweep_cg_matches_oracle(sweep_ctx, torch_dev, shape):
     N, h, w, c, n, r = shape
