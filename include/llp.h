@@ -270,6 +270,20 @@ llp_status llp_apply_data(llp_ctx* ctx, const llp_shape* shape, const llp_params
 llp_status llp_apply_llp(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
                          const float* kernel, const float* z, float* out, hipStream_t stream);
 
+/* The Fourier-domain passes on their own (the transforms of the preconditioned solve, precond = 1):
+ *   llp_precond_apply:      out = P^{-1} r, P = B^T D^T D B + lambda mbar L^T L with mbar the mean of diag(M_LY)
+ *                           (eq. matting_matrix); not in the paper: the preconditioner of the solve of
+ *                           eq. (Z_ini_matting).
+ *   llp_apply_data_fourier: out = B^T D^T D B z, the data term of eq. (Z_ini_matting), applied in the Fourier
+ *                           domain (Sec. II-A: B circular, so DFT(B z) = DFT(u) DFT(z); D aliases the c^2
+ *                           frequencies (k1 + s h, k2 + t w) onto one); params selects nothing but is validated.
+ * Both need h and w with prime factors in {2, 3, 5, 7} and c W, c H <= 16384 (LLP_E_UNSUPPORTED otherwise);
+ * llp_precond_apply also r >= 1 and lambda > 0.  r, z, out [N][H][W] device, must not alias.  Asynchronous. */
+llp_status llp_precond_apply(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
+                             const float* kernel, const float* r, float* out, hipStream_t stream);
+llp_status llp_apply_data_fourier(llp_ctx* ctx, const llp_shape* shape, const llp_params* params,
+                                  const float* kernel, const float* z, float* out, hipStream_t stream);
+
 /* Objective of eq. (initialize_z_fast) for every band of z: obj host [N] (FP64).  The LLP part is summed
  * window by window in the form of eq. (pansharp) with the optimal (a, c) of each window. */
 llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,

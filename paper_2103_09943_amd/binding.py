@@ -69,6 +69,10 @@ _SIGS = {
     "llp_apply_A": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
     "llp_apply_data": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp]),
     "llp_apply_llp": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
+    "llp_precond_apply": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
+                                         _vp]),
+    "llp_apply_data_fourier": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp,
+                                              _vp]),
     "llp_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "llp_get_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
     "llp_objective": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
@@ -367,6 +371,28 @@ class Context:
         out = torch.empty_like(z)
         _check(lib().llp_apply_llp(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(pan), _ptr(kernel), _ptr(z),
                                    _ptr(out), _stream(stream)), "llp_apply_llp")
+        return out
+
+    def precond_apply(self, rr, pan, kernel, *, c: int, r: int, lam: float, eps: float, stream=None):
+        """P^{-1} r (llp_precond_apply)."""
+        import torch
+        N, H, W = rr.shape
+        shp = Shape(N, H // c, W // c, c, kernel.shape[0])
+        prm = Params(int(r), float(lam), float(eps), 0, 0.0, 0, 1)
+        out = torch.empty_like(rr)
+        _check(lib().llp_precond_apply(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(pan), _ptr(kernel),
+                                       _ptr(rr), _ptr(out), _stream(stream)), "llp_precond_apply")
+        return out
+
+    def apply_data_fourier(self, z, kernel, *, c: int, stream=None):
+        """B^T D^T D B z in the Fourier domain (llp_apply_data_fourier)."""
+        import torch
+        N, H, W = z.shape
+        shp = Shape(N, H // c, W // c, c, kernel.shape[0])
+        prm = Params(1, 0.0, 0.0, 0, 0.0, 0)
+        out = torch.empty_like(z)
+        _check(lib().llp_apply_data_fourier(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(kernel), _ptr(z),
+                                            _ptr(out), _stream(stream)), "llp_apply_data_fourier")
         return out
 
     def objective(self, z, lrms, pan, kernel, *, r: int, lam: float, eps: float, stream=None):

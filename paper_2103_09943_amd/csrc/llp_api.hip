@@ -296,6 +296,38 @@ bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg, bool batched) {
   return true;
 }
 
+// The preconditioner's descriptor for the context's buffers (z the float32 iterate, s the output plane), its
+// twiddles, the kernel DFT and mbar: the per-scene set-up of the Fourier-domain passes.
+llp_status pc_setup(llp_ctx* ctx, const Geom& g, const float* kernel, float* z, float* sout, PcPlan* PP,
+                    hipStream_t s) {
+  PcDesc& pd = *ctx->h_pc;
+  memset(&pd, 0, sizeof(pd));
+  pc_fill(pd, g, ctx->tw);
+  pd.spec = (float2*)ctx->spec;
+  pd.uhat = (float2*)ctx->uhat;
+  pd.u = kernel;
+  pd.DI = ctx->DI;
+  pd.mbar = ctx->mbar;
+  pd.r[0] = ctx->r[0];
+  pd.r[1] = ctx->r[1];
+  pd.p[0] = ctx->p[0];
+  pd.p[1] = ctx->p[1];
+  pd.q = ctx->q;
+  pd.z = z;
+  pd.s = sout;
+  pd.partials = ctx->partials;
+  pd.pstride = (int)max_partials_per_band(g);
+  pd.band0 = 0;
+  pc_plan(&pd, 1, PP);
+  pc_twiddles(g, ctx->h_tw);
+  HIP_TRY(hipMemcpyAsync(ctx->tw, ctx->h_tw, pc_tw_floats(g) * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ctx->d_pc, &pd, sizeof(PcDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_pc_rows(kPcRowsKernel, ctx->d_pc, *PP, ctx->st, 0, 0, s));
+  HIP_TRY(launch_pc_cols(kPcColsKernel, ctx->d_pc, *PP, ctx->st, s));
+  HIP_TRY(launch_pc_mbar(ctx->d_pc, 1, ctx->mbar + 1, s));
+  return LLP_OK;
+}
+
 llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const llp_params* params,
                        const float* lrms, const float* pan, const float* kernel, const float* init, float* hrms,
                        llp_report* rep, hipStream_t stream) {
@@ -357,32 +389,8 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
   const int nb_dir = dir_ntiles(g, cfg), nb_apply = apply_ntiles(g, cfg);
   PcPlan PP;
   if (pc) {
-    PcDesc& pd = *ctx->h_pc;
-    memset(&pd, 0, sizeof(pd));
-    pc_fill(pd, g, ctx->tw);
-    pd.spec = (float2*)ctx->spec;
-    pd.uhat = (float2*)ctx->uhat;
-    pd.u = kernel;
-    pd.DI = ctx->DI;
-    pd.mbar = ctx->mbar;
-    pd.r[0] = ctx->r[0];
-    pd.r[1] = ctx->r[1];
-    pd.p[0] = ctx->p[0];
-    pd.p[1] = ctx->p[1];
-    pd.q = ctx->q;
-    pd.z = hrms;
-    pd.s = ctx->s;
-    pd.partials = ctx->partials;
-    pd.pstride = (int)max_partials_per_band(g);
-    pd.band0 = 0;
-    pc_plan(&pd, 1, &PP);
-    pc_twiddles(g, ctx->h_tw);
-    HIP_TRY(hipMemcpyAsync(ctx->tw, ctx->h_tw, pc_tw_floats(g) * sizeof(float), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ctx->d_pc, &pd, sizeof(PcDesc), hipMemcpyHostToDevice, s));
-    // per scene: the kernel's DFT at every group member, and mbar
-    HIP_TRY(launch_pc_rows(kPcRowsKernel, ctx->d_pc, PP, ctx->st, 0, 0, s));
-    HIP_TRY(launch_pc_cols(kPcColsKernel, ctx->d_pc, PP, ctx->st, s));
-    HIP_TRY(launch_pc_mbar(ctx->d_pc, 1, ctx->mbar + 1, s));
+    v = pc_setup(ctx, g, kernel, hrms, ctx->s, &PP, s);
+    if (v != LLP_OK) return v;
     // s_0 = P^{-1} r_0, rho_0 = r_0^T s_0, p_0 = s_0, y = D B p_0
     HIP_TRY(launch_pc_rows(kPcRowsStart, ctx->d_pc, PP, ctx->st, 0, 0, s));
     HIP_TRY(launch_pc_cols(kPcColsSolve, ctx->d_pc, PP, ctx->st, s));
@@ -656,6 +664,44 @@ llp_status llp_apply_llp(llp_ctx* ctx, const llp_shape* shape, const llp_params*
   HIP_TRY(launch_apply(g, cfg, 0, z, nullptr, ctx->y, kernel, ctx->G, ctx->MU, ctx->DI, out, ctx->partials,
                        ctx->st, stream));
   return LLP_OK;
+}
+
+// Shared body of llp_precond_apply and llp_apply_data_fourier: z through the forward passes, the group
+// operation `op`, the inverse passes, into out.
+static llp_status fourier_apply(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
+                                const float* kernel, const float* z, float* out, int op, hipStream_t stream) {
+  if (!ctx || !params || !kernel || !z || !out || z == out || (op == kPcColsSolve && !pan)) return LLP_E_ARG;
+  Geom g;
+  llp_status v = validate(shape, params, &g);
+  if (v != LLP_OK) return v;
+  if (op == kPcColsData) g.lam = 1.0f;  // lambda and r matter only to the preconditioner
+  if (op == kPcColsData && g.r < 1) g.r = 1;
+  if (!pc_supported(g)) return LLP_E_UNSUPPORTED;
+  HIP_TRY(hipSetDevice(ctx->device));
+  v = ensure_workspace(ctx, g, true);
+  if (v != LLP_OK) return v;
+  const size_t NHW = (size_t)g.N * g.H * g.W;
+  if (op == kPcColsSolve) HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
+  else HIP_TRY(hipMemsetAsync(ctx->DI, 0, (size_t)g.H * g.W * sizeof(float), stream));
+  HIP_TRY(launch_init(g, 1, ctx->b, ctx->r[0], ctx->st, stream));  // every band active; r untouched
+  HIP_TRY(hipMemcpyAsync(ctx->r[0], z, NHW * sizeof(float), hipMemcpyDeviceToDevice, stream));
+  PcPlan PP;
+  v = pc_setup(ctx, g, kernel, ctx->q, out, &PP, stream);
+  if (v != LLP_OK) return v;
+  HIP_TRY(launch_pc_rows(kPcRowsStart, ctx->d_pc, PP, ctx->st, 0, 0, stream));
+  HIP_TRY(launch_pc_cols(op, ctx->d_pc, PP, ctx->st, stream));
+  HIP_TRY(launch_pc_rows_inv(ctx->d_pc, PP, ctx->st, 0, stream));
+  return LLP_OK;
+}
+
+llp_status llp_precond_apply(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
+                             const float* kernel, const float* r, float* out, hipStream_t stream) {
+  return fourier_apply(ctx, shape, params, pan, kernel, r, out, kPcColsSolve, stream);
+}
+
+llp_status llp_apply_data_fourier(llp_ctx* ctx, const llp_shape* shape, const llp_params* params,
+                                  const float* kernel, const float* z, float* out, hipStream_t stream) {
+  return fourier_apply(ctx, shape, params, nullptr, kernel, z, out, kPcColsData, stream);
 }
 
 llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,

@@ -241,7 +241,7 @@ struct PcPlan {
   size_t row_lds = 0, col_lds = 0;
 };
 enum PcRowsOp { kPcRowsStart = 0, kPcRowsUpdate = 1, kPcRowsKernel = 2 };
-enum PcColsOp { kPcColsSolve = 0, kPcColsKernel = 1 };
+enum PcColsOp { kPcColsSolve = 0, kPcColsKernel = 1, kPcColsData = 2 };
 // Radices of a transform length (8, 4, 2, 7, 5, 3 in that order) into rad; -1 if L has another prime factor.
 int pc_radices(int L, int* rad);
 // Whether geometry g can be preconditioned: c <= 4, r >= 1, lambda > 0, h and w with prime factors 2, 3, 5, 7

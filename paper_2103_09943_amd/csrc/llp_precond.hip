@@ -341,7 +341,8 @@ __global__ __launch_bounds__(T) void k_pc_rows(int op, const PcDesc* __restrict_
 
 // ---------------------------------------------------------------------------------------- column pass ---
 // op kPcColsSolve: forward length-h transforms, the group solve of every cell, inverse transforms (unscaled;
-// the inverse c x c DFT carries 1/c^2).  op kPcColsKernel: forward transforms and the c x c DFT of pair 0 (the
+// the inverse c x c DFT carries 1/c^2).  op kPcColsData: the same with the data term B^T D^T D B applied to
+// every group instead of P^{-1}.  op kPcColsKernel: forward transforms and the c x c DFT of pair 0 (the
 // embedded kernel), stored as U in the cell layout.
 
 __global__ __launch_bounds__(T) void k_pc_cols(int op, const PcDesc* __restrict__ t, int count,
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(T) void k_pc_cols(int op, const PcDesc* __restrict_
   if (local >= npair * g.w) return;
   const int pair = local / g.w, k2 = local - pair * g.w;
   const int c = g.c, c2 = c * c, h = g.h, w = g.w, H = g.H, W = g.W;
-  if (op == kPcColsSolve) {
+  if (op != kPcColsKernel) {
     const ChanState* sst = st + d.band0;
     if (!band_runs(sst, 2 * pair, g.N) && !band_runs(sst, 2 * pair + 1, g.N)) return;
   }
@@ -388,14 +389,21 @@ __global__ __launch_bounds__(T) void k_pc_cols(int op, const PcDesc* __restrict_
       continue;
     }
     float2 U[16], X[16];
-    float dd[16];
-    for (int s = 0; s < c; ++s)
-      for (int tt = 0; tt < c; ++tt) {
-        const float sym = 4.0f - 2.0f * d.twH[k1 + s * h].x - 2.0f * d.twW[k2 + tt * w].x;
-        dd[s * c + tt] = dscale * sym * sym;
-        U[s * c + tt] = uc[s * c + tt];
-      }
-    group_solve(c, F, U, dd, X);
+    for (int j = 0; j < c2; ++j) U[j] = uc[j];
+    if (op == kPcColsData) {  // B^T D^T D B in the Fourier domain: conj(U_j) / c^2 * sum_k U_k F_k
+      float2 S = make_float2(0.0f, 0.0f);
+      for (int k = 0; k < c2; ++k) S = cadd(S, cmul(U[k], F[k]));
+      S = make_float2(S.x * inv_c2, S.y * inv_c2);
+      for (int j = 0; j < c2; ++j) X[j] = cmul(conjf2(U[j]), S);
+    } else {
+      float dd[16];
+      for (int s = 0; s < c; ++s)
+        for (int tt = 0; tt < c; ++tt) {
+          const float sym = 4.0f - 2.0f * d.twH[k1 + s * h].x - 2.0f * d.twW[k2 + tt * w].x;
+          dd[s * c + tt] = dscale * sym * sym;
+        }
+      group_solve(c, F, U, dd, X);
+    }
     // inverse c x c DFT (1/c^2), conjugate twiddle; stored conjugated for the inverse length-h transforms
     for (int al = 0; al < c; ++al)
       for (int be = 0; be < c; ++be) {

@@ -1,0 +1,194 @@
+"""GPU: the Fourier-domain passes (batched mixed-radix FFT, per-group operations) and the preconditioned solve
+against the oracle, through the C ABI.
+
+Bars as for the plain solve: operators to relative L2 <= 1e-5 per band (float32 transforms against FP64), the
+preconditioned CG iterate after a fixed count to 1e-5, and at tol 1e-6 the FP64 residual of the iterate within
+the tolerance and the objective within 1e-6 of the exact minimiser's.  Shapes cover every radix (8, 4, 2 and
+3, 5, 7: LR sides 12, 14, 20, 24, 30), odd band counts (a band pair with an empty half), and c = 1..4.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.llp import Problem
+from paper_2103_09943_amd import binding as B
+from paper_2103_09943_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_l2(got, want):
+    got = got.reshape(got.shape[0], -1)
+    want = want.reshape(want.shape[0], -1)
+    return np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+
+
+SHAPES = [  # N, h, w, c, n, r
+    (3, 24, 20, 2, 5, 1),     # radices 8 x 3 and 4 x 5; odd band count
+    (1, 14, 12, 4, 9, 1),     # radix 7 (h = 14) and 4 x 3
+    (2, 16, 16, 4, 17, 2),
+    (4, 64, 64, 4, 9, 1),     # the 256^2 parity scene's shape
+    (2, 30, 30, 1, 3, 1),     # c = 1, radices 2 x 3 x 5
+    (1, 8, 8, 3, 5, 1),       # c = 3
+    (5, 32, 40, 4, 15, 2),    # five bands: the third pair has one band
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_data_term_in_fourier_domain(ctx, torch_dev, shape):
+    """B^T D^T D B z through the transforms against the oracle's convolution and decimation."""
+    N, h, w, c, n, r = shape
+    rng = np.random.default_rng(np.random.SeedSequence([71, *shape]))
+    X, Y, u, P = scenes.random_problem(rng, N, h * c, w * c, c, n)
+    got = ctx.apply_data_fourier(dev(torch_dev, P), dev(torch_dev, u), c=c)
+    prob = Problem(u=u, c=c, Y=Y, r=r, lam=0.05, eps=1e-3)
+    err = rel_l2(host(got), oracle.apply_data(P, prob))
+    assert np.all(err < 1e-5), err
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_preconditioner_matches_oracle(ctx, torch_dev, shape):
+    """P^{-1} r with mbar from the PAN statistics, against the oracle's block solve."""
+    N, h, w, c, n, r = shape
+    rng = np.random.default_rng(np.random.SeedSequence([72, *shape]))
+    X, Y, u, P = scenes.random_problem(rng, N, h * c, w * c, c, n)
+    lam, eps = 0.05, 1e-3
+    got = ctx.precond_apply(dev(torch_dev, P), dev(torch_dev, Y), dev(torch_dev, u), c=c, r=r, lam=lam, eps=eps)
+    prob = Problem(u=u, c=c, Y=Y, r=r, lam=f32(lam), eps=f32(eps))
+    want = oracle.precond_apply(P, prob, oracle.matting_diag_mean(prob))
+    err = rel_l2(host(got), want)
+    assert np.all(err < 1e-5), err
+
+
+def test_preconditioner_on_scene_statistics(ctx, torch_dev):
+    """The 256^2 parity scene (smooth residual-like input): near-DC groups, where the solve pivots."""
+    sc, st = scenes.config_scene(0, 0)
+    prob = Problem(u=sc.u, c=sc.c, Y=sc.Y, r=st.r, lam=f32(st.lam), eps=f32(st.eps))
+    b = oracle.rhs(sc.X, prob)
+    got = ctx.precond_apply(dev(torch_dev, b), dev(torch_dev, sc.Y), dev(torch_dev, sc.u), c=sc.c, r=st.r,
+                            lam=st.lam, eps=st.eps)
+    want = oracle.precond_apply(b.astype(np.float32).astype(np.float64), prob, oracle.matting_diag_mean(prob))
+    assert np.all(rel_l2(host(got), want) < 1e-5)
+
+
+@pytest.mark.parametrize("shape", SHAPES[:6])
+def test_pcg_fixed_iterations_matches_oracle(ctx, torch_dev, shape):
+    N, h, w, c, n, r = shape
+    rng = np.random.default_rng(np.random.SeedSequence([73, *shape]))
+    X, Y, u, _ = scenes.random_problem(rng, N, h * c, w * c, c, n)
+    lam, eps = 0.05, 1e-2
+    Z, rep, status = ctx.pansharpen(dev(torch_dev, X), dev(torch_dev, Y), dev(torch_dev, u), r=r, lam=lam, eps=eps,
+                                    max_iters=12, tol=0.0, precond=1)
+    assert status == B.OK
+    assert all(x["iters"] == 12 for x in rep)
+    prob = Problem(u=u, c=c, Y=Y, r=r, lam=f32(lam), eps=f32(eps))
+    want, _ = oracle.pcg(prob, oracle.rhs(X, prob), max_iters=12)
+    err = rel_l2(host(Z), want)
+    assert np.all(err < 1e-5), err
+
+
+@pytest.fixture(scope="module")
+def scene0():
+    sc, st = scenes.config_scene(0, 0)
+    prob = Problem(u=sc.u, c=sc.c, Y=sc.Y, r=st.r, lam=f32(st.lam), eps=f32(st.eps))
+    return sc, st, prob, oracle.rhs(sc.X, prob)
+
+
+def test_pcg_parity_scene_fixed_iterations(ctx, torch_dev, scene0):
+    """The 256^2 x 4 parity scene, 40 preconditioned iterations (one residual replacement at 32 on the way)."""
+    sc, st, prob, b = scene0
+    Z, rep, status = ctx.pansharpen(dev(torch_dev, sc.X), dev(torch_dev, sc.Y), dev(torch_dev, sc.u), r=st.r,
+                                    lam=st.lam, eps=st.eps, max_iters=40, tol=0.0, precond=1)
+    assert status == B.OK
+    want, _ = oracle.pcg(prob, b, max_iters=40)
+    err = rel_l2(host(Z), want)
+    assert np.all(err < 1e-5), err
+
+
+def test_pcg_tolerance(ctx, torch_dev, scene0):
+    """To tol 1e-6: the iterate's FP64 residual meets it, the objective is the exact minimiser's to 1e-6, the
+    iteration counts are the oracle PCG's, and far below plain CG's."""
+    sc, st, prob, b = scene0
+    args = (dev(torch_dev, sc.X), dev(torch_dev, sc.Y), dev(torch_dev, sc.u))
+    kw = dict(r=st.r, lam=st.lam, eps=st.eps, max_iters=5000, tol=1e-6)
+    Z, rep, status = ctx.pansharpen(*args, precond=1, **kw)
+    assert status == B.OK
+    assert all(x["true_rel_residual"] <= 1e-6 for x in rep), rep
+    exact, _ = oracle.cg(prob, b, max_iters=5000, tol=1e-11)
+    f_exact = oracle.objective(exact, sc.X, prob)
+    f_gpu = oracle.objective(host(Z), sc.X, prob)
+    assert np.all(np.abs(f_gpu - f_exact) / f_exact < 1e-6), (f_gpu, f_exact)
+    _, its = oracle.pcg(prob, b, max_iters=5000, tol=1e-6)
+    for x, o in zip(rep, its):
+        assert abs(x["iters"] - o) <= max(8, 0.1 * o), (x["iters"], o)
+    _, plain, _ = ctx.pansharpen(*args, **kw)
+    assert np.mean([x["iters"] for x in rep]) < 0.6 * np.mean([x["iters"] for x in plain])
+
+
+def test_pcg_warm_start_and_unsupported(ctx, torch_dev, scene0):
+    sc, st, prob, b = scene0
+    args = (dev(torch_dev, sc.X), dev(torch_dev, sc.Y), dev(torch_dev, sc.u))
+    exact, _ = oracle.pcg(prob, b, max_iters=5000, tol=1e-11)
+    Z, rep, status = ctx.pansharpen(*args, r=st.r, lam=st.lam, eps=st.eps, max_iters=500, tol=1e-6,
+                                    init=dev(torch_dev, exact), precond=1)
+    assert status == B.OK and all(x["iters"] <= 40 and x["true_rel_residual"] <= 1e-6 for x in rep), rep
+    # r = 0 (no window structure) and an LR side with the prime 11 cannot be preconditioned
+    with pytest.raises(B.LlpError) as ei:
+        ctx.pansharpen(*args, r=0, lam=st.lam, eps=st.eps, max_iters=5, precond=1)
+    assert ei.value.status == B.E_UNSUPPORTED
+    X11 = np.zeros((1, 11, 11), np.float32)
+    Y11 = np.random.default_rng(3).uniform(0, 1, (44, 44)).astype(np.float32)
+    with pytest.raises(B.LlpError) as ei:
+        ctx.pansharpen(dev(torch_dev, X11), dev(torch_dev, Y11), dev(torch_dev, sc.u), r=1, lam=0.01, eps=1e-3,
+                       max_iters=5, precond=1)
+    assert ei.value.status == B.E_UNSUPPORTED
+
+
+def test_pcg_full_size_scene(ctx, torch_dev):
+    """The 8-band 2048^2 scene to tol 1e-6 with the preconditioner: every band's iterate meets the tolerance,
+    and on sampled bands the output's objective is the exact minimiser's (tests/golden) to 1e-6."""
+    sc, st = scenes.config_scene(1, 0)
+    Z, rep, status = ctx.pansharpen(dev(torch_dev, sc.X), dev(torch_dev, sc.Y), dev(torch_dev, sc.u), r=st.r,
+                                    lam=st.lam, eps=st.eps, max_iters=st.max_iters, tol=st.tol, precond=1)
+    assert status == B.OK, rep
+    assert all(x["true_rel_residual"] <= 1e-6 for x in rep), rep
+    print("preconditioned iterations per band:", [x["iters"] for x in rep], flush=True)
+    gold = os.path.join(os.path.dirname(__file__), "golden", "scene_objectives.json")
+    if not os.path.exists(gold):
+        pytest.skip("tests/golden/scene_objectives.json not written yet")
+    g = json.load(open(gold))
+    prob = Problem(u=sc.u, c=sc.c, Y=sc.Y, r=st.r, lam=f32(st.lam), eps=f32(st.eps))
+    bands = [int(k) for k in g["bands"]]
+    f_out = oracle.objective(host(Z[bands]), sc.X[bands], prob)
+    for i, band in enumerate(bands):
+        f_exact = g["bands"][str(band)]["objective"]
+        assert abs(f_out[i] - f_exact) / f_exact < 1e-6, (band, f_out[i], f_exact)
