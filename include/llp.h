@@ -71,7 +71,7 @@ typedef struct {
   float tol;     /* > 0: stop a band when ||b - A Z|| <= tol * ||b|| (b = B^T D^T X_i) for its iterate Z: when the
                     CG residual r_k meets the bound, r_k is recomputed as b - A Z in FP64 from Z (carried as FP64
                     plus a float32 part) and the band stops only if that meets it too, else it iterates on from
-                    the recomputed residual; the same replacement runs every 32 iterations.  The returned HRMS is
+                    the recomputed residual; the same replacement runs every 64 iterations.  The returned HRMS is
                     float(Z).  <= 0: run exactly max_iters iterations (with the same replacements) */
   int init_mode; /* 0: start from Z = 0; 1: start from the caller's `init`; 2: start from the warm-start
                     network's estimate (llp_cnn_set_weights first), band by band only where it is closer

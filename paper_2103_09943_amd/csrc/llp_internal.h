@@ -31,7 +31,7 @@ struct ChanState {
 // Residual replacement (llp_refine.hip): every kRepEvery iterations, and whenever a band's recursive residual
 // meets the tolerance, the band's iterate is flushed into its FP64 accumulator and its residual is recomputed as
 // b - A x in FP64.
-constexpr int kRepEvery = 32;
+constexpr int kRepEvery = 64;
 
 enum InitKind { kInitZero = 0, kInitUser = 1, kInitNet = 2, kInitNetRejected = 3 };
 
@@ -209,6 +209,7 @@ hipError_t launch_ref_fin(int op, const RefDesc* t, int count, int bands, ChanSt
 // ---- Fourier-domain preconditioner (llp_precond.hip) -------------------------------------------------------------
 constexpr int kPcThreads = 1024;   // threads per workgroup of the transform passes
 constexpr int kPcMaxElems = 16384; // complex values a workgroup holds in LDS: c W and c H at most this
+constexpr int kPcSmallElems = 4096; // the same where a transform needs radix 2, 3, 5 or 7
 constexpr int kPcMaxRad = 16;      // radix passes per transform length
 constexpr int kPcMbarBlocks = 64;  // workgroups per scene of the mbar reduction
 // One scene of the preconditioner's launches.
@@ -239,6 +240,7 @@ struct PcDesc {
 struct PcPlan {
   int count = 0, bands = 0, row_blocks = 0, col_blocks = 0;
   size_t row_lds = 0, col_lds = 0;
+  bool mixed = false;  // some transform length needs radix 2, 3, 5 or 7 (the kernels for short transforms)
 };
 enum PcRowsOp { kPcRowsStart = 0, kPcRowsUpdate = 1, kPcRowsKernel = 2 };
 enum PcColsOp { kPcColsSolve = 0, kPcColsKernel = 1, kPcColsData = 2 };

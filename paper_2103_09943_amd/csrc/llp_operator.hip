@@ -521,8 +521,8 @@ size_t max_partials_per_band(const Geom& g) {
   if (sw > m) m = sw;
   // preconditioner: one per LR row
   if ((size_t)g.h > m) m = g.h;
-  // FP64 residual replacement: one per tile of 8 x 64 pixels
-  const size_t rt = (size_t)ref_res_blocks(g) / g.N;
+  // FP64 residual replacement: one per tile of 8 (or 16) x 64 pixels
+  const size_t rt = (size_t)ref_res_blocks(g);
   if (rt > m) m = rt;
   return m;
 }

@@ -36,7 +36,8 @@ using namespace dev;
 namespace {
 
 constexpr int T = kPcThreads;
-constexpr int kMaxPerThread = kPcMaxElems / T;  // complex values per thread in one pass
+constexpr int kMaxPerThread = kPcMaxElems / T;    // complex values per thread in one pass (radix 8 and 4)
+constexpr int kSmallPerThread = kPcSmallElems / T;  // the same for radix 2, 3, 5 and 7
 constexpr int kPcWaves = T / 64;
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -50,6 +51,11 @@ __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.
 // Forward DFT of R points in registers: X_m = sum_t v_t e^{-2 pi i m t / R}.
 template <int R>
 struct Dft;
+
+template <>
+struct Dft<1> {
+  static __device__ __forceinline__ void run(float2 (&)[1]) {}
+};
 
 template <>
 struct Dft<2> {
@@ -134,12 +140,18 @@ struct Dft<7> {
   static __device__ __forceinline__ void run(float2 (&v)[7]) { dft_odd<7>(v, kCos7, kSin7); }
 };
 
+// LDS slot of element i of sequence seq: one unused slot after every 16 elements and sequences S = L + L/16 + 1
+// slots apart, so that the strided accesses of the early passes (stride R Ns) and the accesses across
+// sequences (stride S, odd modulo the banks for the lengths used) spread over the banks.
+__host__ __device__ __forceinline__ int seq_stride(int L) { return L + (L >> 4) + 1; }
+__device__ __forceinline__ int pd(int seq, int S, int i) { return seq * S + i + (i >> 4); }
+
 // One Stockham pass of radix R over nseq sequences of length L stored back to back in buf; Ns is the length of
 // the sub-transforms already done.  tw[m] = e^{-2 pi i m / L}.
-template <int R>
+template <int R, int PER>
 __device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, const float2* __restrict__ tw) {
-  constexpr int NB = (kMaxPerThread + R - 1) / R;
-  const int M = L / R, total = nseq * M, stride = L / (Ns * R);
+  constexpr int NB = (PER + R - 1) / R;  // butterflies per thread: PER values per thread at most
+  const int M = L / R, total = nseq * M, stride = L / (Ns * R), S = seq_stride(L);
   float2 v[NB][R];
   int ob[NB];
 #pragma unroll
@@ -149,13 +161,12 @@ __device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, c
     if (j < total) {
       const int seq = j / M, jj = j - seq * M;
       const int k = jj % Ns;
-      const float2* src = buf + seq * L + jj;
 #pragma unroll
-      for (int t = 0; t < R; ++t) v[b][t] = src[t * M];
+      for (int t = 0; t < R; ++t) v[b][t] = buf[pd(seq, S, jj + t * M)];
 #pragma unroll
       for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], tw[t * k * stride]);
       Dft<R>::run(v[b]);
-      ob[b] = seq * L + (jj / Ns) * Ns * R + k;
+      ob[b] = (seq << 16) | ((jj / Ns) * Ns * R + k);  // sequence and element offset (L <= 16384)
     }
   }
   __syncthreads();
@@ -163,24 +174,36 @@ __device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, c
   for (int b = 0; b < NB; ++b) {
     if (ob[b] >= 0) {
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[ob[b] + t * Ns] = v[b][t];
+      for (int t = 0; t < R; ++t) buf[pd(ob[b] >> 16, S, (ob[b] & 0xffff) + t * Ns)] = v[b][t];
     }
   }
   __syncthreads();
 }
 
-// Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L).
-__device__ void fft_lds(float2* buf, int L, int nseq, const int* rad, int nrad, const float2* __restrict__ tw) {
+// Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L).  MIXED = false: radices 8
+// and 4 only, up to kMaxPerThread values per thread; MIXED = true: every radix, up to kSmallPerThread values per
+// thread (short transforms only, see pc_supported).  Splitting the two keeps every pass within the register
+// budget of a 1024-thread workgroup.
+template <bool MIXED>
+__device__ __forceinline__ void fft_lds(float2* buf, int L, int nseq, const int* rad, int nrad,
+                                        const float2* __restrict__ tw) {
+  constexpr int PER = MIXED ? kSmallPerThread : kMaxPerThread;
   int Ns = 1;
   for (int p = 0; p < nrad; ++p) {
     const int R = rad[p];
-    switch (R) {
-      case 8: fft_pass<8>(buf, L, nseq, Ns, tw); break;
-      case 4: fft_pass<4>(buf, L, nseq, Ns, tw); break;
-      case 2: fft_pass<2>(buf, L, nseq, Ns, tw); break;
-      case 3: fft_pass<3>(buf, L, nseq, Ns, tw); break;
-      case 5: fft_pass<5>(buf, L, nseq, Ns, tw); break;
-      default: fft_pass<7>(buf, L, nseq, Ns, tw); break;
+    if (MIXED) {
+      switch (R) {
+        case 8: fft_pass<8, PER>(buf, L, nseq, Ns, tw); break;
+        case 4: fft_pass<4, PER>(buf, L, nseq, Ns, tw); break;
+        case 2: fft_pass<2, PER>(buf, L, nseq, Ns, tw); break;
+        case 3: fft_pass<3, PER>(buf, L, nseq, Ns, tw); break;
+        case 5: fft_pass<5, PER>(buf, L, nseq, Ns, tw); break;
+        default: fft_pass<7, PER>(buf, L, nseq, Ns, tw); break;
+      }
+    } else if (R == 8) {
+      fft_pass<8, PER>(buf, L, nseq, Ns, tw);
+    } else {
+      fft_pass<4, PER>(buf, L, nseq, Ns, tw);
     }
     Ns *= R;
   }
@@ -197,63 +220,137 @@ __device__ __forceinline__ int find_pc(const PcDesc* t, int count, int bid, F fi
   return lo;
 }
 
-// w_c^k = e^{-2 pi i k / c} for c <= 4.
-__device__ __forceinline__ float2 root_c(int c, int k) {
-  k %= c;
-  if (c == 2) return make_float2(k ? -1.0f : 1.0f, 0.0f);
-  if (c == 4) {
-    const float2 r4[4] = {{1.0f, 0.0f}, {0.0f, -1.0f}, {-1.0f, 0.0f}, {0.0f, 1.0f}};
-    return r4[k];
+// Solve (diag(d) + conj(U) U^T / c^2) x = F on one group of N = c^2 members, in place (F becomes x).  The member
+// with the smallest d is eliminated through the rank-one equation when the rank-one term dominates its row (the
+// frequency nearest 0, where d is tiny or, at K = 0, zero): there the Sherman-Morrison form would cancel
+// catastrophically.  Every array index is a compile-time constant (the pivot is selected, never indexed).
+template <int N>
+__device__ __forceinline__ void group_solve(float2 (&F)[N], const float2 (&U)[N], const float (&d)[N]) {
+  const float c2 = (float)N;
+  int js = 0;
+  float dmin = d[0];
+  float2 Uj = U[0];
+#pragma unroll
+  for (int j = 1; j < N; ++j) {
+    if (d[j] < dmin) {
+      dmin = d[j];
+      js = j;
+      Uj = U[j];
+    }
   }
-  if (c == 3) return make_float2(kCos3[k], -kSin3[k]);
-  return make_float2(1.0f, 0.0f);
+  const float u2 = Uj.x * Uj.x + Uj.y * Uj.y;
+  const bool pivot = dmin * c2 < u2;
+  // S = U^T x / c^2 from the normal equation, scaled by dmin in the pivot case
+  float2 num = make_float2(0.0f, 0.0f);
+  float den = pivot ? c2 * dmin : c2;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const float wk = pivot ? (k == js ? 1.0f : dmin / d[k]) : 1.0f / d[k];
+    num = cadd(num, make_float2(wk * (U[k].x * F[k].x - U[k].y * F[k].y), wk * (U[k].x * F[k].y + U[k].y * F[k].x)));
+    den += wk * (U[k].x * U[k].x + U[k].y * U[k].y);
+  }
+  const float2 S = make_float2(num.x / den, num.y / den);
+  // x_j = (F_j - conj(U_j) S) / d_j; in the pivot case x_js instead from c^2 S = sum_j U_j x_j
+  float2 rest = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const bool piv = pivot && j == js;
+    const float dj = piv ? 1.0f : d[j];
+    const float2 t = csub(F[j], cmul(conjf2(U[j]), S));
+    F[j] = make_float2(t.x / dj, t.y / dj);
+    if (!piv) rest = cadd(rest, cmul(U[j], F[j]));
+  }
+  if (pivot) {
+    const float2 t = csub(make_float2(c2 * S.x, c2 * S.y), rest);  // U_js x_js
+    const float2 xs = make_float2((t.x * Uj.x + t.y * Uj.y) / u2, (t.y * Uj.x - t.x * Uj.y) / u2);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j == js) F[j] = xs;
+  }
 }
 
-// Solve (diag(d) + conj(U) U^T / c^2) x = F on one group (n = c^2 members).  The member with the smallest d is
-// eliminated through the rank-one equation when the rank-one term dominates its row (the frequency nearest
-// 0, where d is tiny or, at K = 0, zero): there the Sherman-Morrison form would cancel catastrophically.
-__device__ __forceinline__ void group_solve(int c, const float2* F, const float2* U, const float* d, float2* x) {
-  const int n = c * c;
-  const float c2 = (float)n;
-  int js = 0;
-  for (int j = 1; j < n; ++j)
-    if (d[j] < d[js]) js = j;
-  const float u2 = U[js].x * U[js].x + U[js].y * U[js].y;
-  if (d[js] * c2 < u2) {
-    // S = U^T x / c^2 from the scaled normal equation; x_j = (F_j - conj(U_j) S) / d_j for j != js; x_js from
-    // c^2 S = sum_j U_j x_j.
-    const float sc = d[js];
-    float2 num = make_float2(0.0f, 0.0f);
-    float den = c2 * sc;
-    for (int k = 0; k < n; ++k) {
-      const float wk = k == js ? 1.0f : sc / d[k];
-      num = cadd(num, make_float2(wk * (U[k].x * F[k].x - U[k].y * F[k].y), wk * (U[k].x * F[k].y + U[k].y * F[k].x)));
-      den += wk * (U[k].x * U[k].x + U[k].y * U[k].y);
-    }
-    const float2 S = make_float2(num.x / den, num.y / den);
-    float2 rest = make_float2(0.0f, 0.0f);
-    for (int j = 0; j < n; ++j) {
-      if (j == js) continue;
-      const float2 xj = csub(F[j], cmul(conjf2(U[j]), S));
-      x[j] = make_float2(xj.x / d[j], xj.y / d[j]);
-      rest = cadd(rest, cmul(U[j], x[j]));
-    }
-    const float2 t = csub(make_float2(c2 * S.x, c2 * S.y), rest);  // U_js x_js
-    x[js] = make_float2((t.x * U[js].x + t.y * U[js].y) / u2, (t.y * U[js].x - t.x * U[js].y) / u2);
-  } else {
-    float2 num = make_float2(0.0f, 0.0f);
-    float den = c2;
-    for (int k = 0; k < n; ++k) {
-      const float ek = 1.0f / d[k];
-      num = cadd(num, make_float2(ek * (U[k].x * F[k].x - U[k].y * F[k].y), ek * (U[k].x * F[k].y + U[k].y * F[k].x)));
-      den += ek * (U[k].x * U[k].x + U[k].y * U[k].y);
-    }
-    const float2 S = make_float2(num.x / den, num.y / den);
-    for (int j = 0; j < n; ++j) {
-      const float2 xj = csub(F[j], cmul(conjf2(U[j]), S));
-      x[j] = make_float2(xj.x / d[j], xj.y / d[j]);
-    }
+// 2D DFT of a C x C block in registers: A[s][t] <- sum_{al, be} A[al][be] w_c^{al s + be t}.
+template <int C>
+__device__ __forceinline__ void dft2(float2 (&A)[C][C]) {
+#pragma unroll
+  for (int al = 0; al < C; ++al) {
+    float2 v[C];
+#pragma unroll
+    for (int be = 0; be < C; ++be) v[be] = A[al][be];
+    Dft<C>::run(v);
+#pragma unroll
+    for (int t = 0; t < C; ++t) A[al][t] = v[t];
   }
+#pragma unroll
+  for (int t = 0; t < C; ++t) {
+    float2 v[C];
+#pragma unroll
+    for (int al = 0; al < C; ++al) v[al] = A[al][t];
+    Dft<C>::run(v);
+#pragma unroll
+    for (int s = 0; s < C; ++s) A[s][t] = v[s];
+  }
+}
+
+// The per-cell work of the column pass for LR frequency (k1, k2): twiddle, C x C DFT to the group's c^2
+// frequencies, the group operation (store U, apply the data term, or solve with P), inverse C x C DFT (1/C^2),
+// conjugate twiddle; the result is left conjugated in LDS for the inverse column transforms.
+template <int C>
+__device__ __forceinline__ void cell_op(int op, const PcDesc& d, float2* pcsh, int h, int k1, int k2, float dscale) {
+  constexpr int N = C * C;
+  const int w = d.g.w;
+  float2 A[C][C];
+#pragma unroll
+  for (int al = 0; al < C; ++al)
+#pragma unroll
+    for (int be = 0; be < C; ++be)
+      A[al][be] = cmul(pcsh[pd(al * C + be, seq_stride(h), k1)], cmul(d.twH[al * k1], d.twW[be * k2]));
+  dft2<C>(A);
+  float2* uc = d.uhat + ((size_t)k1 * w + k2) * N;
+  if (op == kPcColsKernel) {
+#pragma unroll
+    for (int s = 0; s < C; ++s)
+#pragma unroll
+      for (int t = 0; t < C; ++t) uc[s * C + t] = A[s][t];
+    return;
+  }
+  float2 F[N], U[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    F[j] = A[j / C][j % C];
+    U[j] = uc[j];
+  }
+  if (op == kPcColsData) {  // B^T D^T D B in the Fourier domain: conj(U_j) / c^2 * sum_k U_k F_k
+    float2 S = make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int k = 0; k < N; ++k) S = cadd(S, cmul(U[k], F[k]));
+    S = make_float2(S.x / (float)N, S.y / (float)N);
+#pragma unroll
+    for (int j = 0; j < N; ++j) F[j] = cmul(conjf2(U[j]), S);
+  } else {
+    float dd[N];
+#pragma unroll
+    for (int s = 0; s < C; ++s)
+#pragma unroll
+      for (int t = 0; t < C; ++t) {
+        const float sym = 4.0f - 2.0f * d.twH[k1 + s * h].x - 2.0f * d.twW[k2 + t * w].x;
+        dd[s * C + t] = dscale * sym * sym;
+      }
+    group_solve<N>(F, U, dd);
+  }
+  // inverse C x C DFT by conjugation: A = conj(sum_{s,t} X w^{-(al s + be t)}); the value wanted is
+  // conj(A)/N * conj(tw), and it is stored conjugated: A tw / N
+#pragma unroll
+  for (int j = 0; j < N; ++j) A[j / C][j % C] = conjf2(F[j]);
+  dft2<C>(A);
+  const float inv = 1.0f / (float)N;
+#pragma unroll
+  for (int al = 0; al < C; ++al)
+#pragma unroll
+    for (int be = 0; be < C; ++be) {
+      const float2 v = cmul(A[al][be], cmul(d.twH[al * k1], d.twW[be * k2]));
+      pcsh[pd(al * C + be, seq_stride(h), k1)] = make_float2(v.x * inv, v.y * inv);
+    }
 }
 
 __device__ __forceinline__ bool band_runs(const ChanState* st, int band, int nbands) {
@@ -262,12 +359,119 @@ __device__ __forceinline__ bool band_runs(const ChanState* st, int band, int nba
 
 }  // namespace
 
+// C consecutive floats of a plane (16-byte aligned for C = 4, 8-byte for C = 2).
+template <int C>
+__device__ __forceinline__ void ldc(const float* p, float (&v)[C]) {
+  if constexpr (C == 4) {
+    const float4 t = *(const float4*)p;
+    v[0] = t.x, v[1] = t.y, v[2] = t.z, v[3] = t.w;
+  } else if constexpr (C == 2) {
+    const float2 t = *(const float2*)p;
+    v[0] = t.x, v[1] = t.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < C; ++k) v[k] = p[k];
+  }
+}
+template <int C>
+__device__ __forceinline__ void stc(float* p, const float (&v)[C]) {
+  if constexpr (C == 4) {
+    *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (C == 2) {
+    *(float2*)p = make_float2(v[0], v[1]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < C; ++k) p[k] = v[k];
+  }
+}
 // ------------------------------------------------------------------------------------------- row pass ---
 // op kPcRowsStart: the bands' residual r[prev] as it is; kPcRowsUpdate: r[cur] = r[prev] - alpha q and
 // z += alpha p[prev] first (the CG update of iteration k); kPcRowsKernel: the blur kernel embedded in an H x W
 // plane with its centre tap at (0, 0), in band a of pair 0.  Partial sums of |r|^2 per band go to slot 0 of
-// the band's partials (one per LR row).
+// the band's partials (one per LR row).  Each thread moves whole cells: the C x C pixels (c m + al, c n + be)
+// of LR pixel (m, n) on the way in, the c^2 spectral values of frequency (m, k2) on the way out.
 
+template <int C, bool MIXED>
+__device__ __forceinline__ void rows_fwd(int op, const PcDesc& d, const ChanState* sst, int pair, int m, int prev,
+                                         int cur, float2* pcsh, double* red) {
+  constexpr int C2 = C * C;
+  const Geom& g = d.g;
+  const int W = g.W, w = g.w;
+  const int ba = 2 * pair, bb = 2 * pair + 1;
+  const bool ra = op != kPcRowsKernel && band_runs(sst, ba, g.N);
+  const bool rb = op != kPcRowsKernel && band_runs(sst, bb, g.N);
+  const float al_a = ra ? (float)sst[ba].alpha : 0.0f, al_b = rb ? (float)sst[bb].alpha : 0.0f;
+  const size_t HW = (size_t)g.H * W;
+  const int Sw = seq_stride(w);
+  double acc_a = 0.0, acc_b = 0.0;
+  for (int n = threadIdx.x; n < w; n += T) {
+#pragma unroll
+    for (int al = 0; al < C; ++al) {
+      const int i = C * m + al;
+      const size_t e = (size_t)i * W + (size_t)C * n;
+      float va[C], vb[C];
+#pragma unroll
+      for (int be = 0; be < C; ++be) va[be] = vb[be] = 0.0f;
+      if (op == kPcRowsKernel) {
+#pragma unroll
+        for (int be = 0; be < C; ++be) {
+          // plane (i, j) holds u[(i + R) mod H][(j + R) mod W] where that is inside the kernel
+          int a = i + g.R, b = C * n + be + g.R;
+          if (a >= g.H) a -= g.H;
+          if (b >= W) b -= W;
+          if (a < g.n && b < g.n) va[be] = d.u[a * g.n + b];
+        }
+      } else {
+#pragma unroll
+        for (int band = 0; band < 2; ++band) {
+          if (!(band == 0 ? ra : rb)) continue;
+          const size_t o = (size_t)(band == 0 ? ba : bb) * HW + e;
+          const float al = band == 0 ? al_a : al_b;
+          float rv[C];
+          ldc<C>(d.r[prev] + o, rv);
+          if (op == kPcRowsUpdate) {
+            float qv[C], pv[C], zv[C];
+            ldc<C>(d.q + o, qv);
+            ldc<C>(d.p[prev] + o, pv);
+            ldc<C>(d.z + o, zv);
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+              rv[k] = fmaf(-al, qv[k], rv[k]);
+              zv[k] = fmaf(al, pv[k], zv[k]);
+            }
+            stc<C>(d.r[cur] + o, rv);
+            stc<C>(d.z + o, zv);
+          }
+          double ss = 0.0;
+#pragma unroll
+          for (int k = 0; k < C; ++k) ss += (double)rv[k] * rv[k];
+          if (band == 0) acc_a += ss;
+          else acc_b += ss;
+#pragma unroll
+          for (int k = 0; k < C; ++k) (band == 0 ? va : vb)[k] = rv[k];
+        }
+      }
+#pragma unroll
+      for (int be = 0; be < C; ++be) pcsh[pd(al * C + be, Sw, n)] = make_float2(va[be], vb[be]);
+    }
+  }
+  __syncthreads();
+  fft_lds<MIXED>(pcsh, w, C2, d.rw, d.nrw, d.tww);
+  float2* out = d.spec + ((size_t)pair * g.h + m) * (size_t)w * C2;
+  for (int e = threadIdx.x; e < w * C2; e += T) {  // consecutive threads: consecutive values of a cell row
+    const int k2 = e / C2, ph = e - k2 * C2;
+    out[e] = pcsh[pd(ph, Sw, k2)];
+  }
+  if (op == kPcRowsKernel) return;
+  double v[2] = {acc_a, acc_b};
+  block_sums<2, kPcWaves>(v, red);
+  if (threadIdx.x == 0) {
+    if (ra) d.partials[(size_t)ba * d.pstride * 3 + (size_t)m * 3 + 0] = v[0];
+    if (rb) d.partials[(size_t)bb * d.pstride * 3 + (size_t)m * 3 + 0] = v[1];
+  }
+}
+
+template <bool MIXED>
 __global__ __launch_bounds__(T) void k_pc_rows(int op, const PcDesc* __restrict__ t, int count,
                                                const ChanState* __restrict__ st, int prev, int cur) {
   extern __shared__ float2 pcsh[];
@@ -279,63 +483,13 @@ __global__ __launch_bounds__(T) void k_pc_rows(int op, const PcDesc* __restrict_
   const int npair = op == kPcRowsKernel ? 1 : d.npair;
   if (local >= npair * g.h) return;
   const int pair = local / g.h, m = local - pair * g.h;
-  const int c = g.c, c2 = c * c, W = g.W, w = g.w;
-  const int ba = 2 * pair, bb = 2 * pair + 1;
   const ChanState* sst = st + d.band0;
-  const bool ra = op != kPcRowsKernel && band_runs(sst, ba, g.N);
-  const bool rb = op != kPcRowsKernel && band_runs(sst, bb, g.N);
-  if (op != kPcRowsKernel && !ra && !rb) return;
-  const float al_a = ra ? (float)sst[ba].alpha : 0.0f, al_b = rb ? (float)sst[bb].alpha : 0.0f;
-  const size_t HW = (size_t)g.H * W;
-  double acc_a = 0.0, acc_b = 0.0;
-  for (int idx = threadIdx.x; idx < c * W; idx += T) {
-    const int al = idx / W, j = idx - al * W;
-    const int i = c * m + al;
-    const size_t e = (size_t)i * W + j;
-    float va = 0.0f, vb = 0.0f;
-    if (op == kPcRowsKernel) {
-      int a = i + g.R, b = j + g.R;  // plane (i, j) holds u[(i + R) mod H][(j + R) mod W] if inside the kernel
-      if (a >= g.H) a -= g.H;
-      if (b >= W) b -= W;
-      if (a < g.n && b < g.n) va = d.u[a * g.n + b];
-    } else {
-      if (ra) {
-        const size_t o = (size_t)ba * HW + e;
-        va = d.r[prev][o];
-        if (op == kPcRowsUpdate) {
-          va = fmaf(-al_a, d.q[o], va);
-          d.r[cur][o] = va;
-          d.z[o] = fmaf(al_a, d.p[prev][o], d.z[o]);
-        }
-        acc_a += (double)va * va;
-      }
-      if (rb) {
-        const size_t o = (size_t)bb * HW + e;
-        vb = d.r[prev][o];
-        if (op == kPcRowsUpdate) {
-          vb = fmaf(-al_b, d.q[o], vb);
-          d.r[cur][o] = vb;
-          d.z[o] = fmaf(al_b, d.p[prev][o], d.z[o]);
-        }
-        acc_b += (double)vb * vb;
-      }
-    }
-    const int be = j % c, n = j / c;
-    pcsh[(al * c + be) * w + n] = make_float2(va, vb);
-  }
-  __syncthreads();
-  fft_lds(pcsh, w, c2, d.rw, d.nrw, d.tww);
-  float2* out = d.spec + ((size_t)pair * g.h + m) * (size_t)w * c2;
-  for (int e = threadIdx.x; e < w * c2; e += T) {
-    const int k2 = e / c2, ph = e - k2 * c2;
-    out[e] = pcsh[ph * w + k2];
-  }
-  if (op == kPcRowsKernel) return;
-  double v[2] = {acc_a, acc_b};
-  block_sums<2, kPcWaves>(v, red);
-  if (threadIdx.x == 0) {
-    if (ra) d.partials[(size_t)ba * d.pstride * 3 + (size_t)m * 3 + 0] = v[0];
-    if (rb) d.partials[(size_t)bb * d.pstride * 3 + (size_t)m * 3 + 0] = v[1];
+  if (op != kPcRowsKernel && !band_runs(sst, 2 * pair, g.N) && !band_runs(sst, 2 * pair + 1, g.N)) return;
+  switch (g.c) {
+    case 4: rows_fwd<4, MIXED>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
+    case 3: rows_fwd<3, MIXED>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
+    case 2: rows_fwd<2, MIXED>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
+    default: rows_fwd<1, MIXED>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
   }
 }
 
@@ -343,8 +497,33 @@ __global__ __launch_bounds__(T) void k_pc_rows(int op, const PcDesc* __restrict_
 // op kPcColsSolve: forward length-h transforms, the group solve of every cell, inverse transforms (unscaled;
 // the inverse c x c DFT carries 1/c^2).  op kPcColsData: the same with the data term B^T D^T D B applied to
 // every group instead of P^{-1}.  op kPcColsKernel: forward transforms and the c x c DFT of pair 0 (the
-// embedded kernel), stored as U in the cell layout.
+// embedded kernel), stored as U in the cell layout.  Each thread moves whole cells.
 
+template <int C, bool MIXED>
+__device__ __forceinline__ void cols_body(int op, const PcDesc& d, int pair, int k2, float2* pcsh) {
+  constexpr int C2 = C * C;
+  const Geom& g = d.g;
+  const int h = g.h, w = g.w;
+  float2* sp = d.spec + (size_t)pair * h * w * C2;
+  const int Sh = seq_stride(h);
+  for (int e = threadIdx.x; e < h * C2; e += T) {  // consecutive threads: consecutive values of a cell
+    const int m = e / C2, ph = e - m * C2;
+    pcsh[pd(ph, Sh, m)] = sp[((size_t)m * w + k2) * C2 + ph];
+  }
+  __syncthreads();
+  fft_lds<MIXED>(pcsh, h, C2, d.rh, d.nrh, d.twh);
+  const float dscale = op == kPcColsSolve ? (float)((double)g.lam * d.mbar[0]) : 0.0f;
+  for (int k1 = threadIdx.x; k1 < h; k1 += T) cell_op<C>(op, d, pcsh, h, k1, k2, dscale);
+  if (op == kPcColsKernel) return;
+  __syncthreads();
+  fft_lds<MIXED>(pcsh, h, C2, d.rh, d.nrh, d.twh);
+  for (int e = threadIdx.x; e < h * C2; e += T) {
+    const int m = e / C2, ph = e - m * C2;
+    sp[((size_t)m * w + k2) * C2 + ph] = conjf2(pcsh[pd(ph, Sh, m)]);
+  }
+}
+
+template <bool MIXED>
 __global__ __launch_bounds__(T) void k_pc_cols(int op, const PcDesc* __restrict__ t, int count,
                                                const ChanState* __restrict__ st) {
   extern __shared__ float2 pcsh[];
@@ -355,71 +534,15 @@ __global__ __launch_bounds__(T) void k_pc_cols(int op, const PcDesc* __restrict_
   const int npair = op == kPcColsKernel ? 1 : d.npair;
   if (local >= npair * g.w) return;
   const int pair = local / g.w, k2 = local - pair * g.w;
-  const int c = g.c, c2 = c * c, h = g.h, w = g.w, H = g.H, W = g.W;
   if (op != kPcColsKernel) {
     const ChanState* sst = st + d.band0;
     if (!band_runs(sst, 2 * pair, g.N) && !band_runs(sst, 2 * pair + 1, g.N)) return;
   }
-  float2* sp = d.spec + (size_t)pair * h * w * c2;
-  for (int e = threadIdx.x; e < h * c2; e += T) {
-    const int m = e / c2, ph = e - m * c2;
-    pcsh[ph * h + m] = sp[((size_t)m * w + k2) * c2 + ph];
-  }
-  __syncthreads();
-  fft_lds(pcsh, h, c2, d.rh, d.nrh, d.twh);
-  const float dscale = op == kPcColsSolve ? (float)((double)g.lam * d.mbar[0]) : 0.0f;
-  const float inv_c2 = 1.0f / (float)c2;
-  for (int k1 = threadIdx.x; k1 < h; k1 += T) {
-    float2 Q[16], F[16];
-    // twiddle e^{-2 pi i (al k1 / H + be k2 / W)}
-    for (int al = 0; al < c; ++al)
-      for (int be = 0; be < c; ++be)
-        Q[al * c + be] = cmul(pcsh[(al * c + be) * h + k1], cmul(d.twH[al * k1], d.twW[be * k2]));
-    // c x c DFT: F[s c + t] = sum_{al, be} Q[al c + be] w_c^{al s + be t}
-    for (int s = 0; s < c; ++s)
-      for (int tt = 0; tt < c; ++tt) {
-        float2 acc = make_float2(0.0f, 0.0f);
-        for (int al = 0; al < c; ++al)
-          for (int be = 0; be < c; ++be) acc = cadd(acc, cmul(Q[al * c + be], root_c(c, al * s + be * tt)));
-        F[s * c + tt] = acc;
-      }
-    float2* uc = d.uhat + ((size_t)k1 * w + k2) * c2;
-    if (op == kPcColsKernel) {
-      for (int j = 0; j < c2; ++j) uc[j] = F[j];
-      continue;
-    }
-    float2 U[16], X[16];
-    for (int j = 0; j < c2; ++j) U[j] = uc[j];
-    if (op == kPcColsData) {  // B^T D^T D B in the Fourier domain: conj(U_j) / c^2 * sum_k U_k F_k
-      float2 S = make_float2(0.0f, 0.0f);
-      for (int k = 0; k < c2; ++k) S = cadd(S, cmul(U[k], F[k]));
-      S = make_float2(S.x * inv_c2, S.y * inv_c2);
-      for (int j = 0; j < c2; ++j) X[j] = cmul(conjf2(U[j]), S);
-    } else {
-      float dd[16];
-      for (int s = 0; s < c; ++s)
-        for (int tt = 0; tt < c; ++tt) {
-          const float sym = 4.0f - 2.0f * d.twH[k1 + s * h].x - 2.0f * d.twW[k2 + tt * w].x;
-          dd[s * c + tt] = dscale * sym * sym;
-        }
-      group_solve(c, F, U, dd, X);
-    }
-    // inverse c x c DFT (1/c^2), conjugate twiddle; stored conjugated for the inverse length-h transforms
-    for (int al = 0; al < c; ++al)
-      for (int be = 0; be < c; ++be) {
-        float2 acc = make_float2(0.0f, 0.0f);
-        for (int s = 0; s < c; ++s)
-          for (int tt = 0; tt < c; ++tt) acc = cadd(acc, cmul(X[s * c + tt], conjf2(root_c(c, al * s + be * tt))));
-        acc = cmul(acc, conjf2(cmul(d.twH[al * k1], d.twW[be * k2])));
-        pcsh[(al * c + be) * h + k1] = make_float2(acc.x * inv_c2, -acc.y * inv_c2);
-      }
-  }
-  if (op == kPcColsKernel) return;
-  __syncthreads();
-  fft_lds(pcsh, h, c2, d.rh, d.nrh, d.twh);
-  for (int e = threadIdx.x; e < h * c2; e += T) {
-    const int m = e / c2, ph = e - m * c2;
-    sp[((size_t)m * w + k2) * c2 + ph] = conjf2(pcsh[ph * h + m]);
+  switch (g.c) {
+    case 4: cols_body<4, MIXED>(op, d, pair, k2, pcsh); break;
+    case 3: cols_body<3, MIXED>(op, d, pair, k2, pcsh); break;
+    case 2: cols_body<2, MIXED>(op, d, pair, k2, pcsh); break;
+    default: cols_body<1, MIXED>(op, d, pair, k2, pcsh); break;
   }
 }
 
@@ -427,6 +550,63 @@ __global__ __launch_bounds__(T) void k_pc_cols(int op, const PcDesc* __restrict_
 // s = P^{-1} r for both bands of a pair (inverse length-w transforms, scale 1/(h w)), and the partial sums of
 // r[cur]^T s per band into slot 1 of the band's partials.
 
+template <int C, bool MIXED>
+__device__ __forceinline__ void rows_inv(const PcDesc& d, const ChanState* sst, int pair, int m, int cur,
+                                         float2* pcsh, double* red) {
+  constexpr int C2 = C * C;
+  const Geom& g = d.g;
+  const int W = g.W, w = g.w;
+  const int ba = 2 * pair, bb = 2 * pair + 1;
+  const bool ra = band_runs(sst, ba, g.N), rb = band_runs(sst, bb, g.N);
+  const float2* in = d.spec + ((size_t)pair * g.h + m) * (size_t)w * C2;
+  const int Sw = seq_stride(w);
+  for (int e = threadIdx.x; e < w * C2; e += T) {
+    const int k2 = e / C2, ph = e - k2 * C2;
+    pcsh[pd(ph, Sw, k2)] = conjf2(in[e]);
+  }
+  __syncthreads();
+  fft_lds<MIXED>(pcsh, w, C2, d.rw, d.nrw, d.tww);
+  const float scale = 1.0f / ((float)g.h * (float)w);
+  const size_t HW = (size_t)g.H * W;
+  double acc_a = 0.0, acc_b = 0.0;
+  for (int n = threadIdx.x; n < w; n += T) {
+#pragma unroll
+    for (int al = 0; al < C; ++al) {
+      const size_t e = (size_t)(C * m + al) * W + (size_t)C * n;
+      float sa[C], sb[C];
+#pragma unroll
+      for (int be = 0; be < C; ++be) {
+        const float2 v = pcsh[pd(al * C + be, Sw, n)];
+        sa[be] = v.x * scale;
+        sb[be] = -v.y * scale;
+      }
+      if (ra) {
+        const size_t o = (size_t)ba * HW + e;
+        float rv[C];
+        ldc<C>(d.r[cur] + o, rv);
+        stc<C>(d.s + o, sa);
+#pragma unroll
+        for (int k = 0; k < C; ++k) acc_a += (double)rv[k] * sa[k];
+      }
+      if (rb) {
+        const size_t o = (size_t)bb * HW + e;
+        float rv[C];
+        ldc<C>(d.r[cur] + o, rv);
+        stc<C>(d.s + o, sb);
+#pragma unroll
+        for (int k = 0; k < C; ++k) acc_b += (double)rv[k] * sb[k];
+      }
+    }
+  }
+  double v[2] = {acc_a, acc_b};
+  block_sums<2, kPcWaves>(v, red);
+  if (threadIdx.x == 0) {
+    if (ra) d.partials[(size_t)ba * d.pstride * 3 + (size_t)m * 3 + 1] = v[0];
+    if (rb) d.partials[(size_t)bb * d.pstride * 3 + (size_t)m * 3 + 1] = v[1];
+  }
+}
+
+template <bool MIXED>
 __global__ __launch_bounds__(T) void k_pc_rows_inv(const PcDesc* __restrict__ t, int count,
                                                    const ChanState* __restrict__ st, int cur) {
   extern __shared__ float2 pcsh[];
@@ -437,43 +617,13 @@ __global__ __launch_bounds__(T) void k_pc_rows_inv(const PcDesc* __restrict__ t,
   const int local = (int)blockIdx.x - d.row_block0;
   if (local >= d.npair * g.h) return;
   const int pair = local / g.h, m = local - pair * g.h;
-  const int c = g.c, c2 = c * c, W = g.W, w = g.w;
-  const int ba = 2 * pair, bb = 2 * pair + 1;
   const ChanState* sst = st + d.band0;
-  const bool ra = band_runs(sst, ba, g.N), rb = band_runs(sst, bb, g.N);
-  if (!ra && !rb) return;
-  const float2* in = d.spec + ((size_t)pair * g.h + m) * (size_t)w * c2;
-  for (int e = threadIdx.x; e < w * c2; e += T) {
-    const int k2 = e / c2, ph = e - k2 * c2;
-    pcsh[ph * w + k2] = conjf2(in[e]);
-  }
-  __syncthreads();
-  fft_lds(pcsh, w, c2, d.rw, d.nrw, d.tww);
-  const float scale = 1.0f / ((float)g.h * (float)w);
-  const size_t HW = (size_t)g.H * W;
-  double acc_a = 0.0, acc_b = 0.0;
-  for (int idx = threadIdx.x; idx < c * W; idx += T) {
-    const int al = idx / W, j = idx - al * W;
-    const size_t e = (size_t)(c * m + al) * W + j;
-    const float2 v = pcsh[(al * c + j % c) * w + j / c];
-    if (ra) {
-      const size_t o = (size_t)ba * HW + e;
-      const float sv = v.x * scale;
-      d.s[o] = sv;
-      acc_a += (double)d.r[cur][o] * sv;
-    }
-    if (rb) {
-      const size_t o = (size_t)bb * HW + e;
-      const float sv = -v.y * scale;
-      d.s[o] = sv;
-      acc_b += (double)d.r[cur][o] * sv;
-    }
-  }
-  double v[2] = {acc_a, acc_b};
-  block_sums<2, kPcWaves>(v, red);
-  if (threadIdx.x == 0) {
-    if (ra) d.partials[(size_t)ba * d.pstride * 3 + (size_t)m * 3 + 1] = v[0];
-    if (rb) d.partials[(size_t)bb * d.pstride * 3 + (size_t)m * 3 + 1] = v[1];
+  if (!band_runs(sst, 2 * pair, g.N) && !band_runs(sst, 2 * pair + 1, g.N)) return;
+  switch (g.c) {
+    case 4: rows_inv<4, MIXED>(d, sst, pair, m, cur, pcsh, red); break;
+    case 3: rows_inv<3, MIXED>(d, sst, pair, m, cur, pcsh, red); break;
+    case 2: rows_inv<2, MIXED>(d, sst, pair, m, cur, pcsh, red); break;
+    default: rows_inv<1, MIXED>(d, sst, pair, m, cur, pcsh, red); break;
   }
 }
 
@@ -516,8 +666,22 @@ __global__ __launch_bounds__(kBlock) void k_pc_mbar_fin(const PcDesc* __restrict
 // ------------------------------------------------------------------------------------------------ host ---
 
 int pc_radices(int L, int* rad) {
+  // the power of two 2^a as radix-8 passes plus at most two radix-4 passes (radix 2 only for a = 1)
+  int a = 0;
+  while (L % 2 == 0) {
+    L /= 2;
+    ++a;
+  }
   int n = 0;
-  for (int r : {8, 4, 2, 7, 5, 3})
+  const int e8 = a % 3 == 1 && a >= 4 ? a / 3 - 1 : a / 3;
+  for (int i = 0; i < e8; ++i) rad[n++] = 8;
+  int rest = a - 3 * e8;  // 0, 1, 2 or 4
+  while (rest >= 2) {
+    rad[n++] = 4;
+    rest -= 2;
+  }
+  if (rest == 1) rad[n++] = 2;
+  for (int r : {7, 5, 3})
     while (L % r == 0 && n < kPcMaxRad) {
       rad[n++] = r;
       L /= r;
@@ -525,11 +689,23 @@ int pc_radices(int L, int* rad) {
   return L == 1 ? n : -1;
 }
 
+// Whether a transform of length L needs a radix with the smaller per-thread budget.
+static bool pc_small_radix(int L) {
+  int rad[kPcMaxRad];
+  const int n = pc_radices(L, rad);
+  for (int i = 0; i < n; ++i)
+    if (rad[i] != 8 && rad[i] != 4) return true;
+  return false;
+}
+
 bool pc_supported(const Geom& g) {
   int rad[kPcMaxRad];
   if (g.c < 1 || g.c > 4 || g.r < 1 || !(g.lam > 0.0f)) return false;
   if ((size_t)g.c * g.W > (size_t)kPcMaxElems || (size_t)g.c * g.H > (size_t)kPcMaxElems) return false;
-  return pc_radices(g.w, rad) >= 0 && pc_radices(g.h, rad) >= 0;
+  if (pc_radices(g.w, rad) < 0 || pc_radices(g.h, rad) < 0) return false;
+  if (pc_small_radix(g.w) && (size_t)g.c * g.W > (size_t)kPcSmallElems) return false;
+  if (pc_small_radix(g.h) && (size_t)g.c * g.H > (size_t)kPcSmallElems) return false;
+  return true;
 }
 
 int pc_row_blocks(const Geom& g) { return ((g.N + 1) / 2) * g.h; }
@@ -562,18 +738,22 @@ void pc_fill(PcDesc& d, const Geom& g, float* tw_dev) {
 }
 
 hipError_t pc_prepare() {
-  const int bytes = kPcMaxElems * (int)sizeof(float2);
-  hipError_t e = hipFuncSetAttribute((const void*)k_pc_rows, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_pc_cols, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_pc_rows_inv, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const int bytes = (kPcMaxElems + kPcMaxElems / 16 + 16) * (int)sizeof(float2);  // c^2 padded sequences
+  const void* kernels[6] = {(const void*)k_pc_rows<false>,     (const void*)k_pc_rows<true>,
+                            (const void*)k_pc_cols<false>,     (const void*)k_pc_cols<true>,
+                            (const void*)k_pc_rows_inv<false>, (const void*)k_pc_rows_inv<true>};
+  for (const void* k : kernels) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 static size_t pc_row_lds(const PcDesc* h_tab, int count) {
   size_t m = 0;
   for (int i = 0; i < count; ++i) {
-    const size_t b = (size_t)h_tab[i].g.c * h_tab[i].g.W * sizeof(float2);
+    const Geom& g = h_tab[i].g;
+    const size_t b = (size_t)g.c * g.c * seq_stride(g.w) * sizeof(float2);
     if (b > m) m = b;
   }
   return m;
@@ -582,7 +762,8 @@ static size_t pc_row_lds(const PcDesc* h_tab, int count) {
 static size_t pc_col_lds(const PcDesc* h_tab, int count) {
   size_t m = 0;
   for (int i = 0; i < count; ++i) {
-    const size_t b = (size_t)h_tab[i].g.c * h_tab[i].g.H * sizeof(float2);
+    const Geom& g = h_tab[i].g;
+    const size_t b = (size_t)g.c * g.c * seq_stride(g.h) * sizeof(float2);
     if (b > m) m = b;
   }
   return m;
@@ -600,25 +781,35 @@ void pc_plan(PcDesc* h_tab, int count, PcPlan* plan) {
   }
   P.row_lds = pc_row_lds(h_tab, count);
   P.col_lds = pc_col_lds(h_tab, count);
+  for (int i = 0; i < count; ++i) P.mixed |= pc_small_radix(h_tab[i].g.w) || pc_small_radix(h_tab[i].g.h);
   *plan = P;
 }
 
 hipError_t launch_pc_rows(int op, const PcDesc* t, const PcPlan& P, const ChanState* st, int prev, int cur,
                           hipStream_t s) {
   if (P.row_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pc_rows, dim3(P.row_blocks), dim3(T), P.row_lds, s, op, t, P.count, st, prev, cur);
+  if (P.mixed)
+    hipLaunchKernelGGL(k_pc_rows<true>, dim3(P.row_blocks), dim3(T), P.row_lds, s, op, t, P.count, st, prev, cur);
+  else
+    hipLaunchKernelGGL(k_pc_rows<false>, dim3(P.row_blocks), dim3(T), P.row_lds, s, op, t, P.count, st, prev, cur);
   return hipGetLastError();
 }
 
 hipError_t launch_pc_cols(int op, const PcDesc* t, const PcPlan& P, const ChanState* st, hipStream_t s) {
   if (P.col_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pc_cols, dim3(P.col_blocks), dim3(T), P.col_lds, s, op, t, P.count, st);
+  if (P.mixed)
+    hipLaunchKernelGGL(k_pc_cols<true>, dim3(P.col_blocks), dim3(T), P.col_lds, s, op, t, P.count, st);
+  else
+    hipLaunchKernelGGL(k_pc_cols<false>, dim3(P.col_blocks), dim3(T), P.col_lds, s, op, t, P.count, st);
   return hipGetLastError();
 }
 
 hipError_t launch_pc_rows_inv(const PcDesc* t, const PcPlan& P, const ChanState* st, int cur, hipStream_t s) {
   if (P.row_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pc_rows_inv, dim3(P.row_blocks), dim3(T), P.row_lds, s, t, P.count, st, cur);
+  if (P.mixed)
+    hipLaunchKernelGGL(k_pc_rows_inv<true>, dim3(P.row_blocks), dim3(T), P.row_lds, s, t, P.count, st, cur);
+  else
+    hipLaunchKernelGGL(k_pc_rows_inv<false>, dim3(P.row_blocks), dim3(T), P.row_lds, s, t, P.count, st, cur);
   return hipGetLastError();
 }
 

@@ -23,8 +23,9 @@ namespace {
 
 constexpr int kChunkE = kBlock * 16;  // elements per workgroup in the elementwise launch
 constexpr int kYRows = 4;             // D B x: LR rows per tile (one wave each), 64 LR columns per tile
-constexpr int kResTH = 8;             // residual tile: HR rows
 constexpr int kResTW = 64;            // residual tile: HR columns
+constexpr int kResThreads = 1024;     // residual tile: threads (one workgroup per CU: its LDS; 16 waves hide it)
+
 
 __device__ __forceinline__ int wrapr(int i, int n) {
   if (i >= -n && i < 2 * n) return i < 0 ? i + n : (i >= n ? i - n : i);
@@ -49,9 +50,6 @@ __device__ __forceinline__ int find_scene(const RefDesc* t, int count, int bid, 
 }
 
 __host__ __device__ __forceinline__ int res_tiles_x(const Geom& g) { return (g.W + kResTW - 1) / kResTW; }
-__host__ __device__ __forceinline__ int res_tiles(const Geom& g) {
-  return ((g.H + kResTH - 1) / kResTH) * res_tiles_x(g);
-}
 __host__ __device__ __forceinline__ int y_tiles_x(const Geom& g) { return (g.w + 63) / 64; }
 __host__ __device__ __forceinline__ int y_tiles(const Geom& g) { return ((g.h + kYRows - 1) / kYRows) * y_tiles_x(g); }
 __host__ __device__ __forceinline__ int lr_span(int t, int R, int c) { return (t - 1 + 2 * R) / c + 2; }
@@ -60,14 +58,14 @@ __host__ __device__ __forceinline__ int lr_span(int t, int R, int c) { return (t
 
 // ------------------------------------------------------------------------------------------- elementwise ---
 
-__global__ __launch_bounds__(kBlock) void k_ref_elem(int op, const RefDesc* __restrict__ t, int count,
-                                                     const ChanState* __restrict__ st, int force) {
-  const int si = find_scene(t, count, (int)blockIdx.x, [](const RefDesc& d) { return d.e_block0; });
+__device__ __forceinline__ void ref_elem_block(int op, const RefDesc* __restrict__ t, int count,
+                                               const ChanState* __restrict__ st, int force, int vb) {
+  const int si = find_scene(t, count, vb, [](const RefDesc& d) { return d.e_block0; });
   const RefDesc& d = t[si];
   const Geom& g = d.g;
   const size_t HW = (size_t)g.H * g.W;
   const int per_band = (int)((HW + kChunkE - 1) / kChunkE);
-  const int local = (int)blockIdx.x - d.e_block0;
+  const int local = vb - d.e_block0;
   if (local >= per_band * g.N) return;
   const int ch = local / per_band, blk = local - ch * per_band;
   if (op == kRefFlush && !rep_selected(st[d.band0 + ch], force)) return;
@@ -91,18 +89,24 @@ __global__ __launch_bounds__(kBlock) void k_ref_elem(int op, const RefDesc* __re
   }
 }
 
+// The launches below run a bounded grid that strides over the virtual blocks of every scene and band: a pass
+// in which no band is selected costs a few state reads per workgroup, whatever the image sizes.
+__global__ __launch_bounds__(kBlock) void k_ref_elem(int op, const RefDesc* __restrict__ t, int count, int total,
+                                                     const ChanState* __restrict__ st, int force) {
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) ref_elem_block(op, t, count, st, force, vb);
+}
+
 // ------------------------------------------------------------------------------------------- D B x (FP64) ---
 // y[m][k] = sum_{a,b} u[a][b] x[c m + R - a][c k + R - b] (true convolution, then decimation at phase 0).
 // One workgroup per band and tile of kYRows x 64 LR points; the x region the taps reach is staged in LDS.
 
-__global__ __launch_bounds__(kBlock) void k_ref_y(const RefDesc* __restrict__ t, int count,
-                                                  const ChanState* __restrict__ st, int force) {
-  extern __shared__ double ysh[];
-  const int si = find_scene(t, count, (int)blockIdx.x, [](const RefDesc& d) { return d.y_block0; });
+__device__ __forceinline__ void ref_y_block(const RefDesc* __restrict__ t, int count,
+                                            const ChanState* __restrict__ st, int force, int vb, double* ysh) {
+  const int si = find_scene(t, count, vb, [](const RefDesc& d) { return d.y_block0; });
   const RefDesc& d = t[si];
   const Geom& g = d.g;
   const int nt = y_tiles(g);
-  const int local = (int)blockIdx.x - d.y_block0;
+  const int local = vb - d.y_block0;
   if (local >= nt * g.N) return;
   const int ch = local / nt, tile = local - ch * nt;
   if (!rep_selected(st[d.band0 + ch], force)) return;
@@ -132,155 +136,261 @@ __global__ __launch_bounds__(kBlock) void k_ref_y(const RefDesc* __restrict__ t,
   d.y64[((size_t)ch * g.h + m) * g.w + k] = s;
 }
 
+__global__ __launch_bounds__(kBlock) void k_ref_y(const RefDesc* __restrict__ t, int count, int total,
+                                                  const ChanState* __restrict__ st, int force) {
+  extern __shared__ double ysh[];
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    ref_y_block(t, count, st, force, vb, ysh);
+    __syncthreads();  // the next block's staging overwrites the region
+  }
+}
+
 // ------------------------------------------------------------------------------------ residual tile (FP64) ---
-// r = b - (B^T D^T y + lambda L M L x) on a kResTH x kResTW tile, with M l = |w| l - G (.) S(a) - S(b),
-// a = (S(G l)/|w| - mu S(l)/|w|) dinv, b = S(l)/|w| - a mu (S the periodic (2r+1)^2 window sum), and G = L Y,
-// mu = S(G)/|w|, var = S(G^2)/|w| - mu^2, dinv = 1/(eps/|w| + var) (0 where that is 0), all in FP64 from the
-// float32 PAN image.  Regions, as offsets from the tile's corner:
+// r = b - (B^T D^T y + lambda L M L x) on a tile of TH x kResTW pixels, for every selected band of the scene:
+// M l = |w| l - G (.) S(a) - S(b), a = (S(G l)/|w| - mu S(l)/|w|) dinv, b = S(l)/|w| - a mu (S the periodic
+// (2r+1)^2 window sum), with G = L Y, mu = S(G)/|w|, var = S(G^2)/|w| - mu^2 and dinv = 1/(eps/|w| + var) (0 where
+// that is 0) computed once per tile in FP64 from the float32 PAN image.  Window sums are separable: a
+// horizontal pass into row sums, then a vertical pass.  Regions, as offsets from the tile's corner:
 //   X (x and Y):    halo E = 2r + 2     L (G, l = L x, G l): halo 2r + 1
 //   A (a, b):       halo r + 1          M (M l):             halo 1
 // and the LR samples of y the tile's B^T D^T taps reach.
 
-__global__ __launch_bounds__(kBlock) void k_ref_res(const RefDesc* __restrict__ t, int count,
-                                                    const ChanState* __restrict__ st, int force, int rpar,
-                                                    int write_r) {
-  extern __shared__ double rsh[];
-  __shared__ double red[kWaves];
-  const int si = find_scene(t, count, (int)blockIdx.x, [](const RefDesc& d) { return d.r_block0; });
+namespace {
+struct ResLayout {  // LDS layout of the residual tile (doubles; Ys in floats at the end)
+  int TH, E, XH, XW, LH, LW, AH, AW, MH, MW, YH, YW;
+  int oG, oMU, oDI, oR0, oL, oR1, oB, oYl, oU, oYs, total_doubles;
+  __host__ __device__ ResLayout(const Geom& g, int th) {
+    const int r = g.r;
+    TH = th;
+    E = 2 * r + 2;
+    XH = TH + 2 * E, XW = kResTW + 2 * E;
+    LH = TH + 2 * (2 * r + 1), LW = kResTW + 2 * (2 * r + 1);
+    AH = TH + 2 * (r + 1), AW = kResTW + 2 * (r + 1);
+    MH = TH + 2, MW = kResTW + 2;
+    YH = lr_span(TH, g.R, g.c), YW = lr_span(kResTW, g.R, g.c);
+    const int R1 = 2 * (LH * AW > AH * MW ? LH * AW : AH * MW);
+    oG = 0;                       // G (L region), kept for all bands
+    oMU = oG + LH * LW;           // mu, dinv (A region), kept for all bands
+    oDI = oMU + AH * AW;
+    oR0 = oDI + AH * AW;          // x (X region), then a (A region), then M l (M region)
+    oL = oR0 + XH * XW;           // l = L x (L region)
+    oR1 = oL + LH * LW;           // row sums: (G, G^2) or (l, G l) over L rows x A columns; (a, b) over A rows x M columns
+    oB = oR1 + R1;                // b (A region)
+    oYl = oB + AH * AW;           // y (LR samples)
+    oU = oYl + YH * YW;           // taps
+    oYs = oU + g.n * g.n;         // PAN (X region), floats
+    total_doubles = oYs + (XH * XW + 1) / 2;
+  }
+};
+
+// Residual tile height: 16 rows, or 8 or 4 where the FP64 regions of a taller tile do not fit in LDS.
+__host__ __device__ __forceinline__ int res_th(const Geom& g) {
+  for (int th = 16; th > 4; th /= 2)
+    if ((size_t)ResLayout(g, th).total_doubles * sizeof(double) <= kRefMaxLds) return th;
+  return 4;
+}
+__host__ __device__ __forceinline__ ResLayout res_layout(const Geom& g) { return ResLayout(g, res_th(g)); }
+__host__ __device__ __forceinline__ int res_tiles(const Geom& g) {
+  return ((g.H + res_th(g) - 1) / res_th(g)) * res_tiles_x(g);
+}
+}  // namespace
+
+__device__ __forceinline__ void ref_res_block(const RefDesc* __restrict__ t, int count,
+                                              const ChanState* __restrict__ st, int force, int rpar, int write_r,
+                                              int vb, double* rsh, double* red) {
+  const int si = find_scene(t, count, vb, [](const RefDesc& d) { return d.r_block0; });
   const RefDesc& d = t[si];
   const Geom& g = d.g;
   const int nt = res_tiles(g);
-  const int local = (int)blockIdx.x - d.r_block0;
-  if (local >= nt * g.N) return;
-  const int ch = local / nt, tile = local - ch * nt;
-  const ChanState& cs = st[d.band0 + ch];
-  if (!rep_selected(cs, force)) return;
-  const int H = g.H, W = g.W, r = g.r, c = g.c, n = g.n, R = g.R;
+  const int tile = vb - d.r_block0;
+  if (tile >= nt) return;
+  bool any = false;
+  for (int ch = 0; ch < g.N; ++ch) any |= rep_selected(st[d.band0 + ch], force);
+  if (!any) return;
+  const ResLayout Lo = res_layout(g);
+  const int TH = Lo.TH, XH = Lo.XH, XW = Lo.XW, LH = Lo.LH, LW = Lo.LW, AH = Lo.AH, AW = Lo.AW, MH = Lo.MH,
+            MW = Lo.MW, YH = Lo.YH, YW = Lo.YW, E = Lo.E;
+  const int H = g.H, W = g.W, r = g.r, c = g.c, n = g.n, R = g.R, K = 2 * r + 1;
   const int tx = res_tiles_x(g);
-  const int i0 = (tile / tx) * kResTH, j0 = (tile % tx) * kResTW;
-  const int E = 2 * r + 2, h1 = 2 * r + 1, h2 = r + 1;
-  const int XH = kResTH + 2 * E, XW = kResTW + 2 * E;
-  const int LH = kResTH + 2 * h1, LW = kResTW + 2 * h1;
-  const int AH = kResTH + 2 * h2, AW = kResTW + 2 * h2;
-  const int MH = kResTH + 2, MW = kResTW + 2;
+  const int i0 = (tile / tx) * TH, j0 = (tile % tx) * kResTW;
   const int mlo = floor_div(i0 - R, c), klo = floor_div(j0 - R, c);
-  const int YH = lr_span(kResTH, R, c), YW = lr_span(kResTW, R, c);
-  double* Xs = rsh;               // x, later M l
-  double* Gs = Xs + XH * XW;      // G = L Y
-  double* Ls = Gs + LH * LW;      // l = L x
-  double* GLs = Ls + LH * LW;     // G l
-  double* As = GLs + LH * LW;     // a
-  double* Bs = As + AH * AW;      // b
-  double* Yl = Bs + AH * AW;      // y (LR)
-  double* Us = Yl + YH * YW;      // taps
-  float* Ys = (float*)(Us + n * n);  // PAN
-
+  double* Gs = rsh + Lo.oG;
+  double* MUs = rsh + Lo.oMU;
+  double* DIs = rsh + Lo.oDI;
+  double* R0 = rsh + Lo.oR0;
+  double* Ls = rsh + Lo.oL;
+  double* R1 = rsh + Lo.oR1;
+  double* Bs = rsh + Lo.oB;
+  double* Yl = rsh + Lo.oYl;
+  double* Us = rsh + Lo.oU;
+  float* Ys = (float*)(rsh + Lo.oYs);
   const size_t HW = (size_t)H * W;
-  const double* xb = d.xacc + (size_t)ch * HW;
-  for (int idx = threadIdx.x; idx < XH * XW; idx += kBlock) {
-    const int li = idx / XW, lj = idx - li * XW;
-    const size_t e = (size_t)wrapr(i0 - E + li, H) * W + wrapr(j0 - E + lj, W);
-    Xs[idx] = xb[e];
-    Ys[idx] = d.Y[e];
-  }
-  const double* yb = d.y64 + (size_t)ch * g.h * g.w;
-  for (int idx = threadIdx.x; idx < YH * YW; idx += kBlock) {
-    const int li = idx / YW, lj = idx - li * YW;
-    Yl[idx] = yb[(size_t)wrapr(mlo + li, g.h) * g.w + wrapr(klo + lj, g.w)];
-  }
-  for (int idx = threadIdx.x; idx < n * n; idx += kBlock) Us[idx] = (double)d.u[idx];
-  __syncthreads();
+  const double nw = (double)(K * K), inv_nw = 1.0 / nw;
+  const double epsw = (double)g.eps * inv_nw;
 
-  // L region: G = L Y, l = L x, G l (5-point stencil of eq. reg2).
-  for (int idx = threadIdx.x; idx < LH * LW; idx += kBlock) {
+  // Once per tile: PAN, taps, G = L Y, and the window statistics mu, dinv.
+  for (int idx = threadIdx.x; idx < XH * XW; idx += kResThreads) {
+    const int li = idx / XW, lj = idx - li * XW;
+    Ys[idx] = d.Y[(size_t)wrapr(i0 - E + li, H) * W + wrapr(j0 - E + lj, W)];
+  }
+  for (int idx = threadIdx.x; idx < n * n; idx += kResThreads) Us[idx] = (double)d.u[idx];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < LH * LW; idx += kResThreads) {
     const int li = idx / LW, lj = idx - li * LW;
     const int o = (li + 1) * XW + lj + 1;
-    const double gv = 4.0 * (double)Ys[o] - (double)Ys[o - XW] - (double)Ys[o + XW] - (double)Ys[o - 1] -
-                      (double)Ys[o + 1];
-    const double lv = 4.0 * Xs[o] - Xs[o - XW] - Xs[o + XW] - Xs[o - 1] - Xs[o + 1];
-    Gs[idx] = gv;
-    Ls[idx] = lv;
-    GLs[idx] = gv * lv;
+    Gs[idx] = 4.0 * (double)Ys[o] - (double)Ys[o - XW] - (double)Ys[o + XW] - (double)Ys[o - 1] - (double)Ys[o + 1];
   }
   __syncthreads();
-
-  // A region: window statistics of G and the local linear coefficients (a, b) of l on G.
-  const double nw = (double)((2 * r + 1) * (2 * r + 1));
-  const double epsw = (double)g.eps / nw;
-  for (int idx = threadIdx.x; idx < AH * AW; idx += kBlock) {
+  double* hA = R1;
+  double* hB = R1 + LH * AW;
+  for (int idx = threadIdx.x; idx < LH * AW; idx += kResThreads) {  // row sums of G and G^2
+    const int li = idx / AW, aj = idx - li * AW;
+    const double* gr = Gs + li * LW + aj;
+    double s1 = 0.0, s2 = 0.0;
+    for (int dx = 0; dx < K; ++dx) {
+      s1 += gr[dx];
+      s2 += gr[dx] * gr[dx];
+    }
+    hA[idx] = s1;
+    hB[idx] = s2;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < AH * AW; idx += kResThreads) {
     const int ai = idx / AW, aj = idx - ai * AW;
-    double sg = 0.0, sg2 = 0.0, sl = 0.0, sgl = 0.0;
-    for (int dy = 0; dy <= 2 * r; ++dy) {
-      const int o = (ai + dy) * LW + aj;
-      for (int dx = 0; dx <= 2 * r; ++dx) {
-        const double gv = Gs[o + dx];
-        sg += gv;
-        sg2 += gv * gv;
-        sl += Ls[o + dx];
-        sgl += GLs[o + dx];
-      }
+    double sg = 0.0, sg2 = 0.0;
+    for (int dy = 0; dy < K; ++dy) {
+      sg += hA[(ai + dy) * AW + aj];
+      sg2 += hB[(ai + dy) * AW + aj];
     }
-    const double mu = sg / nw;
-    const double var = sg2 / nw - mu * mu;
-    const double den = epsw + var;
-    const double di = den != 0.0 ? 1.0 / den : 0.0;
-    const double m1 = sl / nw, m2 = sgl / nw;
-    const double a = (m2 - mu * m1) * di;
-    As[idx] = a;
-    Bs[idx] = m1 - a * mu;
+    const double mu = sg * inv_nw;
+    const double den = epsw + (sg2 * inv_nw - mu * mu);
+    MUs[idx] = mu;
+    DIs[idx] = den != 0.0 ? 1.0 / den : 0.0;
   }
   __syncthreads();
 
-  // M region: M l = |w| l - G S(a) - S(b)  (into the x buffer, no longer needed).
-  double* Ms = Xs;
-  for (int idx = threadIdx.x; idx < MH * MW; idx += kBlock) {
-    const int mi = idx / MW, mj = idx - mi * MW;
-    double sa = 0.0, sb = 0.0;
-    for (int dy = 0; dy <= 2 * r; ++dy) {
-      const int o = (mi + dy) * AW + mj;
-      for (int dx = 0; dx <= 2 * r; ++dx) {
-        sa += As[o + dx];
-        sb += Bs[o + dx];
-      }
-    }
-    const int lo = (mi + 2 * r) * LW + mj + 2 * r;
-    Ms[idx] = nw * Ls[lo] - Gs[lo] * sa - sb;
-  }
-  __syncthreads();
-
-  // Tile: r = b - (B^T D^T y + lambda L (M l)).
   const double lam = (double)g.lam;
-  const float* bb = d.b + (size_t)ch * HW;
-  const int bpar = cs.iters & 1;  // the buffers holding this band's r_k and p_k
-  float* rout = d.r[rpar] + (size_t)ch * HW;
-  const float* pin = d.p[bpar] + (size_t)ch * HW;
-  float* pout = d.p[rpar] + (size_t)ch * HW;
-  double acc = 0.0;
-  for (int idx = threadIdx.x; idx < kResTH * kResTW; idx += kBlock) {
-    const int pi = idx / kResTW, pj = idx - pi * kResTW;
-    const int i = i0 + pi, j = j0 + pj;
-    if (i >= H || j >= W) continue;
-    const int o = (pi + 1) * MW + pj + 1;
-    const double llp = 4.0 * Ms[o] - Ms[o - MW] - Ms[o + MW] - Ms[o - 1] - Ms[o + 1];
-    // B^T D^T y: taps (a, b) with i + a - R = c m and j + b - R = c k.
-    const int a0 = pos_mod(R - i, c), b0 = pos_mod(R - j, c);
-    const int mr = (i + a0 - R) / c - mlo, kr = (j + b0 - R) / c - klo;
-    double dat = 0.0;
-    for (int a = a0, m = mr; a < n; a += c, ++m) {
-      const double* yr = Yl + m * YW;
-      const double* ur = Us + a * n;
-      for (int b = b0, k = kr; b < n; b += c, ++k) dat = fma(ur[b], yr[k], dat);
+  for (int ch = 0; ch < g.N; ++ch) {
+    const ChanState& cs = st[d.band0 + ch];
+    if (!rep_selected(cs, force)) continue;  // uniform over the workgroup
+    double* Xs = R0;
+    const double* xb = d.xacc + (size_t)ch * HW;
+    for (int idx = threadIdx.x; idx < XH * XW; idx += kResThreads) {
+      const int li = idx / XW, lj = idx - li * XW;
+      Xs[idx] = xb[(size_t)wrapr(i0 - E + li, H) * W + wrapr(j0 - E + lj, W)];
     }
-    const size_t e = (size_t)i * W + j;
-    const double res = (double)bb[e] - (dat + lam * llp);
-    acc += res * res;
-    if (write_r) {
-      rout[e] = (float)res;
-      if (bpar != rpar) pout[e] = pin[e];
+    const double* yb = d.y64 + (size_t)ch * g.h * g.w;
+    for (int idx = threadIdx.x; idx < YH * YW; idx += kResThreads) {
+      const int li = idx / YW, lj = idx - li * YW;
+      Yl[idx] = yb[(size_t)wrapr(mlo + li, g.h) * g.w + wrapr(klo + lj, g.w)];
     }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < LH * LW; idx += kResThreads) {  // l = L x
+      const int li = idx / LW, lj = idx - li * LW;
+      const int o = (li + 1) * XW + lj + 1;
+      Ls[idx] = 4.0 * Xs[o] - Xs[o - XW] - Xs[o + XW] - Xs[o - 1] - Xs[o + 1];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < LH * AW; idx += kResThreads) {  // row sums of l and G l
+      const int li = idx / AW, aj = idx - li * AW;
+      const double* lr = Ls + li * LW + aj;
+      const double* gr = Gs + li * LW + aj;
+      double s1 = 0.0, s2 = 0.0;
+      for (int dx = 0; dx < K; ++dx) {
+        s1 += lr[dx];
+        s2 += gr[dx] * lr[dx];
+      }
+      hA[idx] = s1;
+      hB[idx] = s2;
+    }
+    __syncthreads();
+    double* As = R0;  // x is no longer needed
+    for (int idx = threadIdx.x; idx < AH * AW; idx += kResThreads) {  // a, b of every window
+      const int ai = idx / AW, aj = idx - ai * AW;
+      double sl = 0.0, sgl = 0.0;
+      for (int dy = 0; dy < K; ++dy) {
+        sl += hA[(ai + dy) * AW + aj];
+        sgl += hB[(ai + dy) * AW + aj];
+      }
+      const double mu = MUs[idx];
+      const double m1 = sl * inv_nw, m2 = sgl * inv_nw;
+      const double a = (m2 - mu * m1) * DIs[idx];
+      As[idx] = a;
+      Bs[idx] = m1 - a * mu;
+    }
+    __syncthreads();
+    double* hA2 = R1;
+    double* hB2 = R1 + AH * MW;
+    for (int idx = threadIdx.x; idx < AH * MW; idx += kResThreads) {  // row sums of a and b
+      const int ai = idx / MW, mj = idx - ai * MW;
+      const double* ar = As + ai * AW + mj;
+      const double* br = Bs + ai * AW + mj;
+      double s1 = 0.0, s2 = 0.0;
+      for (int dx = 0; dx < K; ++dx) {
+        s1 += ar[dx];
+        s2 += br[dx];
+      }
+      hA2[idx] = s1;
+      hB2[idx] = s2;
+    }
+    __syncthreads();
+    double* Ms = R0;  // a is no longer needed
+    for (int idx = threadIdx.x; idx < MH * MW; idx += kResThreads) {  // M l = |w| l - G S(a) - S(b)
+      const int mi = idx / MW, mj = idx - mi * MW;
+      double sa = 0.0, sb = 0.0;
+      for (int dy = 0; dy < K; ++dy) {
+        sa += hA2[(mi + dy) * MW + mj];
+        sb += hB2[(mi + dy) * MW + mj];
+      }
+      const int lo = (mi + 2 * r) * LW + mj + 2 * r;
+      Ms[idx] = nw * Ls[lo] - Gs[lo] * sa - sb;
+    }
+    __syncthreads();
+    // Tile: r = b - (B^T D^T y + lambda L (M l)).
+    const float* bb = d.b + (size_t)ch * HW;
+    const int bpar = cs.iters & 1;  // the buffers holding this band's r_k and p_k
+    float* rout = d.r[rpar] + (size_t)ch * HW;
+    const float* pin = d.p[bpar] + (size_t)ch * HW;
+    float* pout = d.p[rpar] + (size_t)ch * HW;
+    double acc = 0.0;
+    for (int idx = threadIdx.x; idx < TH * kResTW; idx += kResThreads) {
+      const int pi = idx / kResTW, pj = idx - pi * kResTW;
+      const int i = i0 + pi, j = j0 + pj;
+      if (i >= H || j >= W) continue;
+      const int o = (pi + 1) * MW + pj + 1;
+      const double llp = 4.0 * Ms[o] - Ms[o - MW] - Ms[o + MW] - Ms[o - 1] - Ms[o + 1];
+      // B^T D^T y: taps (a, b) with i + a - R = c m and j + b - R = c k.
+      const int a0 = pos_mod(R - i, c), b0 = pos_mod(R - j, c);
+      const int mr = (i + a0 - R) / c - mlo, kr = (j + b0 - R) / c - klo;
+      double dat = 0.0;
+      for (int a = a0, m = mr; a < n; a += c, ++m) {
+        const double* yr = Yl + m * YW;
+        const double* ur = Us + a * n;
+        for (int b = b0, k = kr; b < n; b += c, ++k) dat = fma(ur[b], yr[k], dat);
+      }
+      const size_t e = (size_t)i * W + j;
+      const double res = (double)bb[e] - (dat + lam * llp);
+      acc += res * res;
+      if (write_r) {
+        rout[e] = (float)res;
+        if (bpar != rpar) pout[e] = pin[e];
+      }
+    }
+    double v[1] = {acc};
+    block_partials<1, kResThreads / 64>(v, red, d.partials + (size_t)ch * d.pstride * 3 + tile);
+    __syncthreads();  // the next band's staging overwrites the regions
   }
-  double v[1] = {acc};
-  block_partials<1>(v, red, d.partials + (size_t)ch * d.pstride * 3 + tile);
+}
+
+__global__ __launch_bounds__(kResThreads) void k_ref_res(const RefDesc* __restrict__ t, int count, int total,
+                                                         const ChanState* __restrict__ st, int force, int rpar,
+                                                         int write_r) {
+  extern __shared__ double rsh[];
+  __shared__ double red[kResThreads / 64];
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    ref_res_block(t, count, st, force, rpar, write_r, vb, rsh, red);
+    __syncthreads();  // the next tile's staging overwrites the regions
+  }
 }
 
 // ---------------------------------------------------------------------------------------------- finalise ---
@@ -346,21 +456,14 @@ int ref_elem_blocks(const Geom& g) {
   return (int)((HW + kChunkE - 1) / kChunkE) * g.N;
 }
 int ref_y_blocks(const Geom& g) { return y_tiles(g) * g.N; }
-int ref_res_blocks(const Geom& g) { return res_tiles(g) * g.N; }
+int ref_res_blocks(const Geom& g) { return res_tiles(g); }  // one workgroup per tile, for all bands
 
 size_t ref_y_lds(const Geom& g) {
   const size_t RH = (size_t)(kYRows - 1) * g.c + 2 * g.R + 1, RW = (size_t)63 * g.c + 2 * g.R + 1;
   return (RH * RW + (size_t)g.n * g.n) * sizeof(double);
 }
 
-size_t ref_res_lds(const Geom& g) {
-  const int r = g.r, E = 2 * r + 2, h1 = 2 * r + 1, h2 = r + 1;
-  const size_t X = (size_t)(kResTH + 2 * E) * (kResTW + 2 * E);
-  const size_t L = (size_t)(kResTH + 2 * h1) * (kResTW + 2 * h1);
-  const size_t A = (size_t)(kResTH + 2 * h2) * (kResTW + 2 * h2);
-  const size_t Y = (size_t)lr_span(kResTH, g.R, g.c) * lr_span(kResTW, g.R, g.c);
-  return (X + 3 * L + 2 * A + Y + (size_t)g.n * g.n) * sizeof(double) + X * sizeof(float);
-}
+size_t ref_res_lds(const Geom& g) { return (size_t)res_layout(g).total_doubles * sizeof(double); }
 
 hipError_t ref_prepare() {
   hipError_t e = hipFuncSetAttribute((const void*)k_ref_y, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -369,24 +472,29 @@ hipError_t ref_prepare() {
   return hipFuncSetAttribute((const void*)k_ref_res, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRefMaxLds);
 }
 
+constexpr int kRefGrid = 2048;  // workgroups of a replacement launch (they stride over the virtual blocks)
+
 hipError_t launch_ref_elem(int op, const RefDesc* t, int count, int blocks, const ChanState* st, int force,
                            hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ref_elem, dim3(blocks), dim3(kBlock), 0, s, op, t, count, st, force);
+  hipLaunchKernelGGL(k_ref_elem, dim3(blocks < kRefGrid ? blocks : kRefGrid), dim3(kBlock), 0, s, op, t, count,
+                     blocks, st, force);
   return hipGetLastError();
 }
 
 hipError_t launch_ref_y(const RefDesc* t, int count, int blocks, size_t lds, const ChanState* st, int force,
                         hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ref_y, dim3(blocks), dim3(kBlock), lds, s, t, count, st, force);
+  hipLaunchKernelGGL(k_ref_y, dim3(blocks < kRefGrid ? blocks : kRefGrid), dim3(kBlock), lds, s, t, count, blocks,
+                     st, force);
   return hipGetLastError();
 }
 
 hipError_t launch_ref_res(const RefDesc* t, int count, int blocks, size_t lds, const ChanState* st, int force,
                           int rpar, int write_r, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ref_res, dim3(blocks), dim3(kBlock), lds, s, t, count, st, force, rpar, write_r);
+  hipLaunchKernelGGL(k_ref_res, dim3(blocks < kRefGrid ? blocks : kRefGrid), dim3(kResThreads), lds, s, t, count,
+                     blocks, st, force, rpar, write_r);
   return hipGetLastError();
 }
 

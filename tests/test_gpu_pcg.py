@@ -124,12 +124,12 @@ def scene0():
 
 
 def test_pcg_parity_scene_fixed_iterations(ctx, torch_dev, scene0):
-    """The 256^2 x 4 parity scene, 40 preconditioned iterations (one residual replacement at 32 on the way)."""
+    """The 256^2 x 4 parity scene, 70 preconditioned iterations (one residual replacement at 64 on the way)."""
     sc, st, prob, b = scene0
     Z, rep, status = ctx.pansharpen(dev(torch_dev, sc.X), dev(torch_dev, sc.Y), dev(torch_dev, sc.u), r=st.r,
-                                    lam=st.lam, eps=st.eps, max_iters=40, tol=0.0, precond=1)
+                                    lam=st.lam, eps=st.eps, max_iters=70, tol=0.0, precond=1)
     assert status == B.OK
-    want, _ = oracle.pcg(prob, b, max_iters=40)
+    want, _ = oracle.pcg(prob, b, max_iters=70)
     err = rel_l2(host(Z), want)
     assert np.all(err < 1e-5), err
 
