@@ -295,8 +295,18 @@ llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params*
 typedef struct {
   double apply_ms;          /* summed device time of the operator launches (q = A p and its dot products) */
   long long apply_launches;
-  double dir_ms;            /* summed device time of the update launches (x, r, new direction, D B p, r^T r) */
+  double dir_ms;            /* summed device time of the direction launches (plain: x, r, p, D B p, r^T r;
+                               preconditioned: p = s + beta p, D B p) */
   long long dir_launches;
+  double pc_rows_ms;        /* preconditioned: forward row transforms with the update of x and r */
+  long long pc_rows_launches;
+  double pc_cols_ms;        /* preconditioned: column transforms with the group solve */
+  long long pc_cols_launches;
+  double pc_rows_inv_ms;    /* preconditioned: inverse row transforms, s = P^{-1} r and r^T s */
+  long long pc_rows_inv_launches;
+  double ref_ms;            /* FP64 residual replacement passes (all launches of a pass, also passes that find
+                               no band due) */
+  long long ref_passes;
 } llp_kernel_times;
 
 /* Enable (1) or disable (0) timing of the CG kernels of later llp_pansharpen and llp_pansharpen_batch calls on

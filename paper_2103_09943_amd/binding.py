@@ -40,7 +40,11 @@ class Report(ctypes.Structure):
 
 class KernelTimes(ctypes.Structure):
     _fields_ = [("apply_ms", ctypes.c_double), ("apply_launches", ctypes.c_longlong),
-                ("dir_ms", ctypes.c_double), ("dir_launches", ctypes.c_longlong)]
+                ("dir_ms", ctypes.c_double), ("dir_launches", ctypes.c_longlong),
+                ("pc_rows_ms", ctypes.c_double), ("pc_rows_launches", ctypes.c_longlong),
+                ("pc_cols_ms", ctypes.c_double), ("pc_cols_launches", ctypes.c_longlong),
+                ("pc_rows_inv_ms", ctypes.c_double), ("pc_rows_inv_launches", ctypes.c_longlong),
+                ("ref_ms", ctypes.c_double), ("ref_passes", ctypes.c_longlong)]
 
 
 class TuneResult(ctypes.Structure):

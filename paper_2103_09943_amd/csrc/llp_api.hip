@@ -204,25 +204,40 @@ llp_status ensure_workspace(llp_ctx* ctx, const Geom& g, bool precond) {
   return LLP_OK;
 }
 
-// Timing event number i of the current call (grown on demand).
-hipEvent_t timing_event(llp_ctx* ctx) {
-  if (ctx->tev_used == ctx->tev.size()) {
+int timing_begin(llp_ctx* ctx, hipStream_t s) {
+  if (!ctx->profiling) return -1;
+  const size_t i = ctx->tev_used;
+  while (ctx->tev.size() < 2 * (i + 1)) {
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
     ctx->tev.push_back(e);
   }
-  return ctx->tev[ctx->tev_used++];
+  if (ctx->tslot.size() < i + 1) ctx->tslot.resize(i + 1);
+  if (hipEventRecord(ctx->tev[2 * i], s) != hipSuccess) return -1;
+  ctx->tslot[i] = -1;
+  ctx->tev_used = i + 1;
+  return (int)i;
+}
+
+void timing_end(llp_ctx* ctx, hipStream_t s, int pair, int slot) {
+  if (pair < 0) return;
+  if (hipEventRecord(ctx->tev[2 * pair + 1], s) == hipSuccess) ctx->tslot[pair] = slot;
 }
 
 llp_status collect_times(llp_ctx* ctx) {
-  for (size_t i = 0; i + 3 < ctx->tev_used; i += 4) {
-    float a = 0.0f, b = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&a, ctx->tev[i], ctx->tev[i + 1]));
-    HIP_TRY(hipEventElapsedTime(&b, ctx->tev[i + 2], ctx->tev[i + 3]));
-    ctx->times.apply_ms += a;
-    ctx->times.dir_ms += b;
-    ctx->times.apply_launches += 1;
-    ctx->times.dir_launches += 1;
+  for (size_t i = 0; i < ctx->tev_used; ++i) {
+    if (ctx->tslot[i] < 0) continue;
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->tev[2 * i], ctx->tev[2 * i + 1]));
+    llp_kernel_times& t = ctx->times;
+    switch (ctx->tslot[i]) {
+      case kTApply: t.apply_ms += ms, ++t.apply_launches; break;
+      case kTDir: t.dir_ms += ms, ++t.dir_launches; break;
+      case kTPcRows: t.pc_rows_ms += ms, ++t.pc_rows_launches; break;
+      case kTPcCols: t.pc_cols_ms += ms, ++t.pc_cols_launches; break;
+      case kTPcRowsInv: t.pc_rows_inv_ms += ms, ++t.pc_rows_inv_launches; break;
+      default: t.ref_ms += ms, ++t.ref_passes; break;
+    }
   }
   ctx->tev_used = 0;
   return LLP_OK;
@@ -409,38 +424,41 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
     const int todo = max_iters - k + 1 < kCheckEvery ? max_iters - k + 1 : kCheckEvery;
     for (int t = 0; t < todo; ++t, ++k) {
       const int prev = (k - 1) & 1, cur = k & 1;
-      hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
-      if (ctx->profiling) {
-        for (auto& ev : e)
-          if (!(ev = timing_event(ctx))) return LLP_E_HIP;
-        HIP_TRY(hipEventRecord(e[0], s));
-      }
+      int tp = timing_begin(ctx, s);
       HIP_TRY(launch_apply(g, cfg, 1, ctx->p[prev], ctx->r[prev], ctx->y, kernel, ctx->G, ctx->MU, ctx->DI,
                            ctx->q, ctx->partials, ctx->st, s));
-      if (ctx->profiling) HIP_TRY(hipEventRecord(e[1], s));
+      timing_end(ctx, s, tp, kTApply);
       if (pc) {
         HIP_TRY(launch_finalize(g, kFinPcgAlpha, ctx->partials, nb_apply, ctx->st, nullptr, 0, 0, 0, 0.0f, s));
-        if (ctx->profiling) HIP_TRY(hipEventRecord(e[2], s));
+        tp = timing_begin(ctx, s);
         HIP_TRY(launch_pc_rows(kPcRowsUpdate, ctx->d_pc, PP, ctx->st, prev, cur, s));
+        timing_end(ctx, s, tp, kTPcRows);
+        tp = timing_begin(ctx, s);
         HIP_TRY(launch_pc_cols(kPcColsSolve, ctx->d_pc, PP, ctx->st, s));
+        timing_end(ctx, s, tp, kTPcCols);
+        tp = timing_begin(ctx, s);
         HIP_TRY(launch_pc_rows_inv(ctx->d_pc, PP, ctx->st, cur, s));
+        timing_end(ctx, s, tp, kTPcRowsInv);
         HIP_TRY(launch_finalize(g, kFinPcgBeta, ctx->partials, g.h, ctx->st, nullptr, 0, 0, 0, 0.0f, s));
+        tp = timing_begin(ctx, s);
         HIP_TRY(launch_dir(g, cfg, 3, 0, k, ctx->s, nullptr, ctx->p[prev], nullptr, ctx->p[cur], hrms, ctx->y,
                            kernel, ctx->partials, ctx->st, max_iters, tol, s));
-        if (ctx->profiling) HIP_TRY(hipEventRecord(e[3], s));
+        timing_end(ctx, s, tp, kTDir);
         HIP_TRY(launch_finalize(g, kFinPcgStop, ctx->partials, 0, ctx->st, nullptr, 0, -1, max_iters, tol, s));
         continue;
       }
       HIP_TRY(launch_finalize(g, kFinApply, ctx->partials, nb_apply, ctx->st, nullptr, 0, 0, 0, 0.0f, s));
-      if (ctx->profiling) HIP_TRY(hipEventRecord(e[2], s));
+      tp = timing_begin(ctx, s);
       HIP_TRY(launch_dir(g, cfg, 2, k == max_iters, k, ctx->r[prev], ctx->q, ctx->p[prev], ctx->r[cur],
                          ctx->p[cur], hrms, ctx->y, kernel, ctx->partials, ctx->st, max_iters, tol, s));
-      if (ctx->profiling) HIP_TRY(hipEventRecord(e[3], s));
+      timing_end(ctx, s, tp, kTDir);
       HIP_TRY(launch_finalize(g, kFinDir, ctx->partials, nb_dir, ctx->st, nullptr, 0, -1, max_iters, tol, s));
     }
     // the next iteration (k) reads the buffers of parity (k - 1) & 1
+    const int tr = timing_begin(ctx, s);
     v = ref_pass(ctx->d_ref, P, ctx->st, ctx->results, kRefStep, 0, (k - 1) & 1, 1, max_iters, tol, pc ? 0 : 1, s);
     if (v != LLP_OK) return v;
+    timing_end(ctx, s, tr, kTRef);
     if (!tol_mode) continue;
     // Poll the band states of the chunk before last while this one runs (at most two chunks in flight).
     const int slot = chunk_no & 1;
@@ -750,7 +768,7 @@ llp_status llp_set_profiling(llp_ctx* ctx, int enable) {
 llp_status llp_get_kernel_times(llp_ctx* ctx, llp_kernel_times* out, int reset) {
   if (!ctx || !out) return LLP_E_ARG;
   *out = ctx->times;
-  if (reset) ctx->times = llp_kernel_times{0.0, 0, 0.0, 0};
+  if (reset) ctx->times = llp_kernel_times{};
   return LLP_OK;
 }
 

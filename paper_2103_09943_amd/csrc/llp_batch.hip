@@ -79,34 +79,34 @@ llp_status enqueue_batch_iters(const std::vector<BatchClass>& classes, const Sce
                                int nbands, ChanState* st, char* ws, const float* taps, int count, int parity,
                                int max_iters, float tol, hipStream_t s, llp_ctx* prof, const RefDesc* d_ref,
                                const RefPlan& rplan, double* results) {
-  std::vector<hipEvent_t> ev(prof ? 4 * classes.size() : 0);
   for (int j = 0; j < count; ++j) {
     const int par = (parity + j) & 1;
-    for (auto& e : ev)
-      if (!(e = timing_event(prof))) return LLP_E_HIP;
     for (size_t c = 0; c < classes.size(); ++c) {
       const BatchClass& k = classes[c];
-      if (prof) HIP_TRY(hipEventRecord(ev[4 * c], s));
+      const int tp = prof ? timing_begin(prof, s) : -1;
       if (k.variant == kSweepVariant)
         HIP_TRY(launch_apply_sweep_batch(d_table + k.first, k.count, k.data_blocks, k.apply_blocks, k.C, k.R, k.r,
                                          par, st, ws, taps, s));
       else
         HIP_TRY(launch_apply_fast_batch(d_table + k.first, k.count, k.apply_blocks, k.C, k.R, k.r, k.variant, par,
                                         st, ws, taps, s));
-      if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 1], s));
+      if (prof) timing_end(prof, s, tp, kTApply);
     }
     HIP_TRY(launch_finalize_batch(kFinApply, d_table, nscenes, nbands, st, ws, max_iters, tol, s));
     for (size_t c = 0; c < classes.size(); ++c) {
       const BatchClass& k = classes[c];
-      if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 2], s));
+      const int tp = prof ? timing_begin(prof, s) : -1;
       HIP_TRY(launch_dir_fast_batch(d_table + k.first, k.count, k.dir_blocks, k.C, k.R, k.dir_rows, par, st, ws,
                                     taps, 2, s));
-      if (prof) HIP_TRY(hipEventRecord(ev[4 * c + 3], s));
+      if (prof) timing_end(prof, s, tp, kTDir);
     }
     HIP_TRY(launch_finalize_batch(kFinDir, d_table, nscenes, nbands, st, ws, max_iters, tol, s));
   }
   // residual replacement for the bands that are due; the next iteration reads the buffers of parity + count
-  return ref_pass(d_ref, rplan, st, results, kRefStep, 0, (parity + count) & 1, 1, max_iters, tol, 1, s);
+  const int tr = prof ? timing_begin(prof, s) : -1;
+  const llp_status v = ref_pass(d_ref, rplan, st, results, kRefStep, 0, (parity + count) & 1, 1, max_iters, tol, 1, s);
+  if (prof) timing_end(prof, s, tr, kTRef);
+  return v;
 }
 }  // namespace
 

@@ -43,7 +43,11 @@ bool pick_config(const Geom& g, OpConfig* cfg, bool allow_fast = true, int want_
 // batched entry of the class if there is one, then the single-scene entry), else the default.
 bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg, bool batched = false);
 llp_status ensure_workspace(llp_ctx* ctx, const Geom& g, bool precond = false);
-hipEvent_t timing_event(llp_ctx* ctx);
+// Kernel timing (llp_set_profiling): timing_begin records a start event on s and returns its pair's index (or
+// -1 when not profiling or on failure), timing_end records the end event and the pair's slot.
+enum TimeSlot { kTApply = 0, kTDir = 1, kTPcRows = 2, kTPcCols = 3, kTPcRowsInv = 4, kTRef = 5, kTSlots = 6 };
+int timing_begin(llp_ctx* ctx, hipStream_t s);
+void timing_end(llp_ctx* ctx, hipStream_t s, int pair, int slot);
 llp_status collect_times(llp_ctx* ctx);
 llp_status check_inputs(llp_ctx* ctx, const Geom& g, const float* lrms, const float* pan, const float* kernel,
                         hipStream_t s);
@@ -126,9 +130,10 @@ struct llp_ctx {
   hipEvent_t ev[2] = {nullptr, nullptr};
   // kernel timing (llp_set_profiling)
   bool profiling = false;
-  std::vector<hipEvent_t> tev;  // timing events, 4 per iteration (around k_apply and around k_dir)
-  size_t tev_used = 0;
-  llp_kernel_times times = {0.0, 0, 0.0, 0};
+  std::vector<hipEvent_t> tev;  // timing events, in start/end pairs
+  std::vector<int> tslot;       // slot of every pair
+  size_t tev_used = 0;          // pairs in use
+  llp_kernel_times times = {};
   // llp_pansharpen_batch: own stream, workspace, pinned mirrors and the cached graph of an iteration chunk
   hipStream_t bstream = nullptr;
   hipEvent_t bev_in = nullptr;

@@ -186,11 +186,17 @@ llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* 
     double us = 0.0;
     v = time_config(ctx, g, c, params, lrms, pan, kernel, scratch, iters, stream, &us);
     if (v != LLP_OK) break;
+    if (!(us > 0.0)) continue;  // no valid measurement for this candidate
     if (same(c, def)) def_us = us;
-    if (best_us == 0.0 || us < best_us) {
+    if (!have_best || us < best_us) {
+      have_best = true;
       best_us = us;
       best = c;
     }
+  }
+  if (v == LLP_OK && !have_best) {  // nothing measured: the default, no table entry
+    best = def;
+    best_us = 0.0;
   }
   if (v == LLP_OK && def_us > 0.0 && !(best_us < kMargin * def_us)) {  // measured gain within noise: default
     best = def;
@@ -203,7 +209,7 @@ llp_status llp_autotune(llp_ctx* ctx, const llp_shape* shape, const llp_params* 
     (void)hipFree(own);
   }
   if (v != LLP_OK) return v;
-  keep_entry(ctx, TuneEntry{g.c, g.R, g.r, area_bucket(g), best, best_us, 0});
+  if (have_best) keep_entry(ctx, TuneEntry{g.c, g.R, g.r, area_bucket(g), best, best_us, 0});
   if (out) {
     out->fast = best.fast;
     out->dir_rows = best.dir_rows;
