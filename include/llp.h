@@ -284,6 +284,17 @@ llp_status llp_precond_apply(llp_ctx* ctx, const llp_shape* shape, const llp_par
 llp_status llp_apply_data_fourier(llp_ctx* ctx, const llp_shape* shape, const llp_params* params,
                                   const float* kernel, const float* z, float* out, hipStream_t stream);
 
+/* The product of llp_apply_A for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): no context, no allocation.  The PAN statistics and
+ * y = D B z live in a library-owned device array of LLP_NOALLOC_SCRATCH_FLOATS floats per device (64 MiB), held
+ * until the process ends: 3 H W + N h w must fit (LLP_E_UNSUPPORTED otherwise).  Every call on a device shares
+ * that device's array, so calls that overlap on one device (on different streams or threads) race.  The untuned
+ * default launch configuration is used (the same kernels as a fresh context's llp_apply_A).  Runs on the current
+ * device; asynchronous on `stream`.  z, Az [N][H][W] device, 16-byte aligned, must not alias. */
+#define LLP_NOALLOC_SCRATCH_FLOATS (16u << 20)
+llp_status llp_apply_A_noalloc(const llp_shape* shape, const llp_params* params, const float* pan,
+                               const float* kernel, const float* z, float* Az, hipStream_t stream);
+
 /* Objective of eq. (initialize_z_fast) for every band of z: obj host [N] (FP64).  The LLP part is summed
  * window by window in the form of eq. (pansharp) with the optimal (a, c) of each window. */
 llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,

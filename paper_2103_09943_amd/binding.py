@@ -77,6 +77,7 @@ _SIGS = {
                                          _vp]),
     "llp_apply_data_fourier": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp,
                                               _vp]),
+    "llp_apply_A_noalloc": (ctypes.c_int, [ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
     "llp_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "llp_get_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
     "llp_objective": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
@@ -152,6 +153,20 @@ def _stream(stream) -> Optional[int]:
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return s.cuda_stream
+
+
+def apply_A_noalloc(z, pan, kernel, *, c: int, r: int, lam: float, eps: float, out=None, stream=None):
+    """A z with llp_apply_A_noalloc (no context, no device allocation by the library).  `out` may be given so
+    that nothing is allocated on this side either."""
+    import torch
+    N, H, W = z.shape
+    shp = Shape(N, H // c, W // c, c, kernel.shape[0])
+    prm = Params(int(r), float(lam), float(eps), 0, 0.0, 0)
+    if out is None:
+        out = torch.empty_like(z)
+    _check(lib().llp_apply_A_noalloc(ctypes.byref(shp), ctypes.byref(prm), _ptr(pan), _ptr(kernel), _ptr(z),
+                                     _ptr(out), _stream(stream)), "llp_apply_A_noalloc")
+    return out
 
 
 def shape_of(lrms, pan, kernel) -> Shape:
