@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="budget of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="skip the comparison legs and the profiled step")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="skip the comparison legs but keep the profiled step (every call is then the same solve)")
     return ap.parse_args()
 
 
@@ -240,7 +242,7 @@ def main():
     }
     roofline = None
     if not args.no_legs:
-        if init == "cnn":
+        if init == "cnn" and not args.profile_only:
             call(None, 1)
             cold_s, creps, _ = timed(None, 1, 1)
             citers = [r["iters"] for rs in creps for r in rs]
@@ -249,12 +251,13 @@ def main():
             cfg["cold_iters_min_mean_max"] = [min(citers), round(float(np.mean(citers)), 1), max(citers)]
             cfg["network_starts_rejected"] = sum(r["init"] == B.INIT_NET_REJECTED for rs in reps for r in rs)
             log(f"cold preconditioned leg: {cold_s * 1e3:.1f} ms")
-        call(None, 0)
-        cg_s, greps, _ = timed(None, 0, 1)
-        giters = [r["iters"] for rs in greps for r in rs]
-        cfg["cg_cold_value"] = round(pxb / cg_s / 1e6, 3)
-        cfg["cg_cold_iters_min_mean_max"] = [min(giters), round(float(np.mean(giters)), 1), max(giters)]
-        log(f"unpreconditioned cold leg: {cg_s * 1e3:.1f} ms")
+        if not args.profile_only:
+            call(None, 0)
+            cg_s, greps, _ = timed(None, 0, 1)
+            giters = [r["iters"] for rs in greps for r in rs]
+            cfg["cg_cold_value"] = round(pxb / cg_s / 1e6, 3)
+            cfg["cg_cold_iters_min_mean_max"] = [min(giters), round(float(np.mean(giters)), 1), max(giters)]
+            log(f"unpreconditioned cold leg: {cg_s * 1e3:.1f} ms")
         # one profiled step (events around every launch): per-kernel device times
         ctx.set_profiling(True)
         ctx.kernel_times(reset=True)

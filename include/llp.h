@@ -79,8 +79,9 @@ typedef struct {
   int precond;   /* 0: plain conjugate gradients; 1: preconditioned by P = B^T D^T D B + lambda mbar L^T L,
                     mbar the mean of diag(M_LY), applied exactly in the Fourier domain (not in the paper; the
                     same minimiser, fewer iterations).  Needs r >= 1, lambda > 0, h and w with prime factors in
-                    {2, 3, 5, 7} and c W, c H <= 16384 (LLP_E_UNSUPPORTED otherwise) and a kernel with nonzero
-                    sum (LLP_E_BREAKDOWN otherwise) */
+                    {2, 3, 5, 7}, c W, c H <= 16384 and, at c <= 2, W, H <= 7776 (c = 2) or 9898 (c = 1)
+                    (LLP_E_UNSUPPORTED otherwise; a workgroup holds c^2 transforms and their twiddles in LDS),
+                    and a kernel with nonzero sum (LLP_E_BREAKDOWN otherwise) */
 } llp_params;
 
 typedef struct {
@@ -277,7 +278,7 @@ llp_status llp_apply_llp(llp_ctx* ctx, const llp_shape* shape, const llp_params*
  *   llp_apply_data_fourier: out = B^T D^T D B z, the data term of eq. (Z_ini_matting), applied in the Fourier
  *                           domain (Sec. II-A: B circular, so DFT(B z) = DFT(u) DFT(z); D aliases the c^2
  *                           frequencies (k1 + s h, k2 + t w) onto one); params selects nothing but is validated.
- * Both need h and w with prime factors in {2, 3, 5, 7} and c W, c H <= 16384 (LLP_E_UNSUPPORTED otherwise);
+ * Both need the sizes that precond = 1 needs (llp_params) (LLP_E_UNSUPPORTED otherwise);
  * llp_precond_apply also r >= 1 and lambda > 0.  r, z, out [N][H][W] device, must not alias.  Asynchronous. */
 llp_status llp_precond_apply(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* pan,
                              const float* kernel, const float* r, float* out, hipStream_t stream);

@@ -207,10 +207,12 @@ hipError_t launch_ref_fin(int op, const RefDesc* t, int count, int bands, ChanSt
                           int force, int plain_cg, int max_iters, float tol, hipStream_t s);
 
 // ---- Fourier-domain preconditioner (llp_precond.hip) -------------------------------------------------------------
-constexpr int kPcThreads = 1024;   // threads per workgroup of the transform passes
+constexpr int kPcThreads = 1024;   // threads per workgroup of the row transform passes
+constexpr int kPcColThreads = 512; // threads per workgroup of the column pass
 constexpr int kPcMaxElems = 16384; // complex values a workgroup holds in LDS: c W and c H at most this
 constexpr int kPcSmallElems = 4096; // the same where a transform needs radix 2, 3, 5 or 7
 constexpr int kPcMaxRad = 16;      // radix passes per transform length
+constexpr int kPcMaxLds = 160 * 1024 - 512;  // dynamic LDS of a transform pass (sequences and twiddles)
 constexpr int kPcMbarBlocks = 64;  // workgroups per scene of the mbar reduction
 // One scene of the preconditioner's launches.
 struct PcDesc {
@@ -240,6 +242,7 @@ struct PcDesc {
 struct PcPlan {
   int count = 0, bands = 0, row_blocks = 0, col_blocks = 0;
   size_t row_lds = 0, col_lds = 0;
+  int cus = 256;       // compute units of the device (persistent column workgroups)
   bool mixed = false;  // some transform length needs radix 2, 3, 5 or 7 (the kernels for short transforms)
 };
 enum PcRowsOp { kPcRowsStart = 0, kPcRowsUpdate = 1, kPcRowsKernel = 2 };
@@ -247,7 +250,7 @@ enum PcColsOp { kPcColsSolve = 0, kPcColsKernel = 1, kPcColsData = 2 };
 // Radices of a transform length (8, 4, 2, 7, 5, 3 in that order) into rad; -1 if L has another prime factor.
 int pc_radices(int L, int* rad);
 // Whether geometry g can be preconditioned: c <= 4, r >= 1, lambda > 0, h and w with prime factors 2, 3, 5, 7
-// only, and c W, c H <= kPcMaxElems.
+// only, c W, c H <= kPcMaxElems, and the c^2 padded sequences with their twiddle table within kPcMaxLds.
 bool pc_supported(const Geom& g);
 size_t pc_spec_floats(const Geom& g);
 size_t pc_uhat_floats(const Geom& g);

@@ -30,14 +30,15 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace llp {
 using namespace dev;
 
 namespace {
 
-constexpr int T = kPcThreads;
-constexpr int kMaxPerThread = kPcMaxElems / T;    // complex values per thread in one pass (radix 8 and 4)
-constexpr int kSmallPerThread = kPcSmallElems / T;  // the same for radix 2, 3, 5 and 7
+constexpr int T = kPcThreads;      // threads of the row passes
+constexpr int TC = kPcColThreads;  // threads of the column pass (more registers per thread for the group solve)
 constexpr int kPcWaves = T / 64;
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -47,6 +48,34 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // -i a
+
+// threadIdx.x behind an optimisation barrier: the persistent column loop would otherwise hoist every address
+// derived from it out of the loop and keep them all live, beyond the register budget.
+__device__ __forceinline__ int opaque_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Loads and stores through pointers taken from a descriptor: in the global address space, so that they are
+// issued as global (not flat) memory instructions and waits on LDS accesses do not wait for them.
+#define LLP_G __attribute__((address_space(1)))
+typedef float gf2 __attribute__((ext_vector_type(2)));
+typedef float gf4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float gld(const float* p) { return *(const LLP_G float*)p; }
+__device__ __forceinline__ float2 gld(const float2* p) {
+  const gf2 v = *(const LLP_G gf2*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float4 gld(const float4* p) {
+  const gf4 v = *(const LLP_G gf4*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst(float* p, float v) { *(LLP_G float*)p = v; }
+__device__ __forceinline__ void gst(double* p, double v) { *(LLP_G double*)p = v; }
+__device__ __forceinline__ void gst(float2* p, float2 v) { *(LLP_G gf2*)p = gf2{v.x, v.y}; }
+__device__ __forceinline__ void gst(float4* p, float4 v) { *(LLP_G gf4*)p = gf4{v.x, v.y, v.z, v.w}; }
+#undef LLP_G
 
 // Forward DFT of R points in registers: X_m = sum_t v_t e^{-2 pi i m t / R}.
 template <int R>
@@ -144,29 +173,44 @@ struct Dft<7> {
 // slots apart, so that the strided accesses of the early passes (stride R Ns) and the accesses across
 // sequences (stride S, odd modulo the banks for the lengths used) spread over the banks.
 __host__ __device__ __forceinline__ int seq_stride(int L) { return L + (L >> 4) + 1; }
-__device__ __forceinline__ int pd(int seq, int S, int i) { return seq * S + i + (i >> 4); }
+__device__ __forceinline__ int pd(int seq, int S, int i) { return __mul24(seq, S) + i + (i >> 4); }
 
 // One Stockham pass of radix R over nseq sequences of length L stored back to back in buf; Ns is the length of
-// the sub-transforms already done.  tw[m] = e^{-2 pi i m / L}.
-template <int R, int PER>
-__device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, const float2* __restrict__ tw) {
+// the sub-transforms already done.  tw[m] = e^{-2 pi i m / L} (in LDS).  POW2: L is a power of two and every
+// index is taken with shifts and masks.
+template <int TH, int R, int PER, bool POW2>
+__device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, const float2* tw) {
   constexpr int NB = (PER + R - 1) / R;  // butterflies per thread: PER values per thread at most
-  const int M = L / R, total = nseq * M, stride = L / (Ns * R), S = seq_stride(L);
+  constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
+  const int M = POW2 ? L >> LR : L / R, total = nseq * M, S = seq_stride(L);
+  const int lgM = POW2 ? __builtin_ctz(M) : 0, lgNs = POW2 ? __builtin_ctz(Ns) : 0;
+  const int stride = POW2 ? M >> lgNs : L / (Ns * R);  // tw index step of k: L / (Ns R)
   float2 v[NB][R];
   int ob[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int j = (int)threadIdx.x + b * T;
+    const int j = opaque_tid() + b * TH;
     ob[b] = -1;
     if (j < total) {
-      const int seq = j / M, jj = j - seq * M;
-      const int k = jj % Ns;
+      int seq, jj, k, o;
+      if (POW2) {
+        seq = j >> lgM;
+        jj = j & (M - 1);
+        k = jj & (Ns - 1);
+        o = ((jj >> lgNs) << (lgNs + LR)) | k;
+      } else {
+        seq = j / M;
+        jj = j - seq * M;
+        k = jj % Ns;
+        o = (jj / Ns) * Ns * R + k;
+      }
 #pragma unroll
       for (int t = 0; t < R; ++t) v[b][t] = buf[pd(seq, S, jj + t * M)];
+      const int ks = __mul24(k, stride);
 #pragma unroll
-      for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], tw[t * k * stride]);
+      for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], tw[t * ks]);
       Dft<R>::run(v[b]);
-      ob[b] = (seq << 16) | ((jj / Ns) * Ns * R + k);  // sequence and element offset (L <= 16384)
+      ob[b] = (seq << 16) | o;  // sequence and element offset (L <= 16384)
     }
   }
   __syncthreads();
@@ -180,33 +224,124 @@ __device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, c
   __syncthreads();
 }
 
-// Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L).  MIXED = false: radices 8
-// and 4 only, up to kMaxPerThread values per thread; MIXED = true: every radix, up to kSmallPerThread values per
-// thread (short transforms only, see pc_supported).  Splitting the two keeps every pass within the register
-// budget of a 1024-thread workgroup.
-template <bool MIXED>
-__device__ __forceinline__ void fft_lds(float2* buf, int L, int nseq, const int* rad, int nrad,
-                                        const float2* __restrict__ tw) {
-  constexpr int PER = MIXED ? kSmallPerThread : kMaxPerThread;
+// The same pass for L a power of two (R = 8 or 4), with every LDS index an offset from one base per butterfly:
+// when M = L / R is a multiple of 16 (LIN) the R inputs jj + t M sit (M + M / 16) slots apart, and the outputs
+// o + t Ns always sit t Ns + (t Ns) / 16 slots from o (the padding of a block of R Ns outputs is linear in t, as
+// the block starts on a multiple of min(R Ns, 16)).  TW = false for the first pass (Ns = 1: every twiddle is 1).
+template <int TH, int R, int PER, bool LIN, bool TW>
+__device__ __forceinline__ void fft_pass_p2(float2* buf, int L, int nseq, int Ns, const float2* tw) {
+  constexpr int NB = (PER + R - 1) / R;
+  constexpr int LR = R == 8 ? 3 : 2;
+  const int M = L >> LR, total = nseq * M, S = seq_stride(L);
+  const int lgM = __builtin_ctz(M), lgNs = __builtin_ctz(Ns);
+  const int stride = M >> lgNs, rstep = M + (M >> 4);
+  float2 v[NB][R];
+  int wb[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = opaque_tid() + b * TH;
+    wb[b] = -1;
+    if (j < total) {
+      const int seq = j >> lgM, jj = j & (M - 1), k = jj & (Ns - 1);
+      const int sb = __mul24(seq, S);
+      if (LIN) {
+        const int rb = sb + jj + (jj >> 4);
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[b][t] = buf[rb + t * rstep];
+      } else {
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int i = jj + t * M;
+          v[b][t] = buf[sb + i + (i >> 4)];
+        }
+      }
+      if (TW) {
+        const int ks = __mul24(k, stride);
+#pragma unroll
+        for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], tw[t * ks]);
+      }
+      Dft<R>::run(v[b]);
+      const int o = ((jj >> lgNs) << (lgNs + LR)) | k;
+      wb[b] = sb + o + (o >> 4);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (wb[b] >= 0) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int tn = t * Ns;
+        buf[wb[b] + tn + (tn >> 4)] = v[b][t];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int TH, int R, int PER>
+__device__ __forceinline__ void fft_pass_p2_any(float2* buf, int L, int nseq, int Ns, const float2* tw) {
+  const bool lin = (L / R) % 16 == 0;
+  if (Ns == 1) {
+    if (lin) fft_pass_p2<TH, R, PER, true, false>(buf, L, nseq, Ns, tw);
+    else fft_pass_p2<TH, R, PER, false, false>(buf, L, nseq, Ns, tw);
+  } else {
+    if (lin) fft_pass_p2<TH, R, PER, true, true>(buf, L, nseq, Ns, tw);
+    else fft_pass_p2<TH, R, PER, false, true>(buf, L, nseq, Ns, tw);
+  }
+}
+
+// Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L; twiddles tw in LDS).
+// TH threads.  MIXED = false: radices 8 and 4 only (L a power of two), up to kPcMaxElems / TH values per
+// thread; MIXED = true: every radix, up to kPcSmallElems / TH values per thread (short transforms only, see
+// pc_supported).  Splitting the two keeps every pass within the register budget.
+template <int TH, bool MIXED>
+__device__ __forceinline__ void fft_lds(float2* buf, int L, int nseq, const int* rad, int nrad, const float2* tw) {
+  constexpr int PER = (MIXED ? kPcSmallElems : kPcMaxElems) / TH;
   int Ns = 1;
   for (int p = 0; p < nrad; ++p) {
     const int R = rad[p];
     if (MIXED) {
       switch (R) {
-        case 8: fft_pass<8, PER>(buf, L, nseq, Ns, tw); break;
-        case 4: fft_pass<4, PER>(buf, L, nseq, Ns, tw); break;
-        case 2: fft_pass<2, PER>(buf, L, nseq, Ns, tw); break;
-        case 3: fft_pass<3, PER>(buf, L, nseq, Ns, tw); break;
-        case 5: fft_pass<5, PER>(buf, L, nseq, Ns, tw); break;
-        default: fft_pass<7, PER>(buf, L, nseq, Ns, tw); break;
+        case 8: fft_pass<TH, 8, PER, false>(buf, L, nseq, Ns, tw); break;
+        case 4: fft_pass<TH, 4, PER, false>(buf, L, nseq, Ns, tw); break;
+        case 2: fft_pass<TH, 2, PER, false>(buf, L, nseq, Ns, tw); break;
+        case 3: fft_pass<TH, 3, PER, false>(buf, L, nseq, Ns, tw); break;
+        case 5: fft_pass<TH, 5, PER, false>(buf, L, nseq, Ns, tw); break;
+        default: fft_pass<TH, 7, PER, false>(buf, L, nseq, Ns, tw); break;
       }
     } else if (R == 8) {
-      fft_pass<8, PER>(buf, L, nseq, Ns, tw);
+      fft_pass_p2_any<TH, 8, PER>(buf, L, nseq, Ns, tw);
     } else {
-      fft_pass<4, PER>(buf, L, nseq, Ns, tw);
+      fft_pass_p2_any<TH, 4, PER>(buf, L, nseq, Ns, tw);
     }
     Ns *= R;
   }
+}
+
+// Element e < n (n >= 1) goes from src(e) to dst(e, value) for every e, with K loads per thread issued before
+// the first of their stores: a global-to-LDS copy keeps K loads in flight instead of waiting on each one.  The
+// loads are unconditional (indexes past the end read element n - 1 again), so no branch separates them.
+template <int TH, int K, typename Src, typename Dst>
+__device__ __forceinline__ void copy_elems(int n, Src src, Dst dst) {
+  for (int base = 0; base < n; base += TH * K) {
+    float2 v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = src(min(base + k * TH + opaque_tid(), n - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = base + k * TH + opaque_tid();
+      if (e < n) dst(e, v[k]);
+    }
+  }
+}
+
+// The twiddle table of a length-L transform, copied from global memory into LDS after the c^2 sequences.
+template <int TH>
+__device__ __forceinline__ float2* stage_twiddles(float2* pcsh, int nseq, int L, const float2* tw) {
+  float2* t = pcsh + (size_t)nseq * seq_stride(L);
+  copy_elems<TH, 4>(L, [&](int i) { return gld(tw + i); }, [&](int i, float2 v) { t[i] = v; });
+  return t;
 }
 
 template <typename F>
@@ -220,20 +355,31 @@ __device__ __forceinline__ int find_pc(const PcDesc* t, int count, int bid, F fi
   return lo;
 }
 
-// Solve (diag(d) + conj(U) U^T / c^2) x = F on one group of N = c^2 members, in place (F becomes x).  The member
-// with the smallest d is eliminated through the rank-one equation when the rank-one term dominates its row (the
-// frequency nearest 0, where d is tiny or, at K = 0, zero): there the Sherman-Morrison form would cancel
-// catastrophically.  Every array index is a compile-time constant (the pivot is selected, never indexed).
-template <int N>
-__device__ __forceinline__ void group_solve(float2 (&F)[N], const float2 (&U)[N], const float (&d)[N]) {
+// Solve (diag(d) + conj(U) U^T / c^2) x = F on one group of N = c^2 members, in place (F becomes x), with
+// d_{s c + t} = dscale (eh[s] + ew[t])^2: eh, ew the symbols 2 - 2 cos of the stencil along each axis at the
+// member's frequencies.  The member with the smallest d is eliminated through the rank-one equation when the
+// rank-one term dominates its row (the frequency nearest 0, where d is tiny or, at K = 0, zero): there the
+// Sherman-Morrison form would cancel catastrophically.  Every array index is a compile-time constant (the
+// pivot is selected, never indexed).  Reciprocals are the hardware's (1 ulp); d = 0 occurs only at the pivot
+// member, whose reciprocal is unused.
+template <int C>
+__device__ __forceinline__ void group_solve(float2 (&F)[C * C], const float2 (&U)[C * C], const float (&eh)[C],
+                                            const float (&ew)[C], float dscale) {
+  constexpr int N = C * C;
   const float c2 = (float)N;
+  // d_j and its reciprocal are recomputed where needed rather than held (register pressure)
+  auto dof = [&](int j) {
+    const float sym = eh[j / C] + ew[j % C];
+    return dscale * sym * sym;
+  };
   int js = 0;
-  float dmin = d[0];
+  float dmin = 0.0f;
   float2 Uj = U[0];
 #pragma unroll
-  for (int j = 1; j < N; ++j) {
-    if (d[j] < dmin) {
-      dmin = d[j];
+  for (int j = 0; j < N; ++j) {
+    const float dj = dof(j);
+    if (j == 0 || dj < dmin) {
+      dmin = dj;
       js = j;
       Uj = U[j];
     }
@@ -245,111 +391,119 @@ __device__ __forceinline__ void group_solve(float2 (&F)[N], const float2 (&U)[N]
   float den = pivot ? c2 * dmin : c2;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const float wk = pivot ? (k == js ? 1.0f : dmin / d[k]) : 1.0f / d[k];
+    const float rk = __builtin_amdgcn_rcpf(dof(k));
+    const float wk = pivot ? (k == js ? 1.0f : dmin * rk) : rk;
     num = cadd(num, make_float2(wk * (U[k].x * F[k].x - U[k].y * F[k].y), wk * (U[k].x * F[k].y + U[k].y * F[k].x)));
     den += wk * (U[k].x * U[k].x + U[k].y * U[k].y);
   }
-  const float2 S = make_float2(num.x / den, num.y / den);
+  const float rden = __builtin_amdgcn_rcpf(den);
+  const float2 S = make_float2(num.x * rden, num.y * rden);
   // x_j = (F_j - conj(U_j) S) / d_j; in the pivot case x_js instead from c^2 S = sum_j U_j x_j
   float2 rest = make_float2(0.0f, 0.0f);
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const bool piv = pivot && j == js;
-    const float dj = piv ? 1.0f : d[j];
+    const float rj = piv ? 1.0f : __builtin_amdgcn_rcpf(dof(j));
     const float2 t = csub(F[j], cmul(conjf2(U[j]), S));
-    F[j] = make_float2(t.x / dj, t.y / dj);
+    F[j] = make_float2(t.x * rj, t.y * rj);
     if (!piv) rest = cadd(rest, cmul(U[j], F[j]));
   }
   if (pivot) {
     const float2 t = csub(make_float2(c2 * S.x, c2 * S.y), rest);  // U_js x_js
-    const float2 xs = make_float2((t.x * Uj.x + t.y * Uj.y) / u2, (t.y * Uj.x - t.x * Uj.y) / u2);
+    const float ru2 = __builtin_amdgcn_rcpf(u2);
+    const float2 xs = make_float2((t.x * Uj.x + t.y * Uj.y) * ru2, (t.y * Uj.x - t.x * Uj.y) * ru2);
 #pragma unroll
     for (int j = 0; j < N; ++j)
       if (j == js) F[j] = xs;
   }
 }
 
-// 2D DFT of a C x C block in registers: A[s][t] <- sum_{al, be} A[al][be] w_c^{al s + be t}.
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+
+// 2D DFT of a C x C block in registers (A[al C + be]): A[s C + t] <- sum_{al, be} A[al C + be] w_c^{al s + be t}.
 template <int C>
-__device__ __forceinline__ void dft2(float2 (&A)[C][C]) {
+__device__ __forceinline__ void dft2(float2 (&A)[C * C]) {
 #pragma unroll
   for (int al = 0; al < C; ++al) {
     float2 v[C];
 #pragma unroll
-    for (int be = 0; be < C; ++be) v[be] = A[al][be];
+    for (int be = 0; be < C; ++be) v[be] = A[al * C + be];
     Dft<C>::run(v);
 #pragma unroll
-    for (int t = 0; t < C; ++t) A[al][t] = v[t];
+    for (int t = 0; t < C; ++t) A[al * C + t] = v[t];
   }
 #pragma unroll
   for (int t = 0; t < C; ++t) {
     float2 v[C];
 #pragma unroll
-    for (int al = 0; al < C; ++al) v[al] = A[al][t];
+    for (int al = 0; al < C; ++al) v[al] = A[al * C + t];
     Dft<C>::run(v);
 #pragma unroll
-    for (int s = 0; s < C; ++s) A[s][t] = v[s];
+    for (int s = 0; s < C; ++s) A[s * C + t] = v[s];
   }
 }
 
 // The per-cell work of the column pass for LR frequency (k1, k2): twiddle, C x C DFT to the group's c^2
 // frequencies, the group operation (store U, apply the data term, or solve with P), inverse C x C DFT (1/C^2),
-// conjugate twiddle; the result is left conjugated in LDS for the inverse column transforms.
+// conjugate twiddle; the result is left conjugated in LDS for the inverse column transforms.  The twiddle
+// e^{-2 pi i (al k1 / H + be k2 / W)} is applied as its two factors.
 template <int C>
 __device__ __forceinline__ void cell_op(int op, const PcDesc& d, float2* pcsh, int h, int k1, int k2, float dscale) {
   constexpr int N = C * C;
-  const int w = d.g.w;
-  float2 A[C][C];
+  const int w = d.g.w, Sh = seq_stride(h);
+  float2 ta[C], tb[C];  // tb (k2 is the workgroup's) is kept in scalar registers
+#pragma unroll
+  for (int a = 0; a < C; ++a) {
+    ta[a] = gld(d.twH + a * k1);
+    const float2 t = gld(d.twW + a * k2);
+    tb[a] = make_float2(uniform(t.x), uniform(t.y));
+  }
+  float2 A[N];
 #pragma unroll
   for (int al = 0; al < C; ++al)
 #pragma unroll
-    for (int be = 0; be < C; ++be)
-      A[al][be] = cmul(pcsh[pd(al * C + be, seq_stride(h), k1)], cmul(d.twH[al * k1], d.twW[be * k2]));
+    for (int be = 0; be < C; ++be) A[al * C + be] = cmul(cmul(pcsh[pd(al * C + be, Sh, k1)], ta[al]), tb[be]);
   dft2<C>(A);
   float2* uc = d.uhat + ((size_t)k1 * w + k2) * N;
   if (op == kPcColsKernel) {
 #pragma unroll
-    for (int s = 0; s < C; ++s)
-#pragma unroll
-      for (int t = 0; t < C; ++t) uc[s * C + t] = A[s][t];
+    for (int j = 0; j < N; ++j) gst(uc + j, A[j]);
     return;
   }
-  float2 F[N], U[N];
+  float2 U[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    F[j] = A[j / C][j % C];
-    U[j] = uc[j];
-  }
+  for (int j = 0; j < N; ++j) U[j] = gld(uc + j);
   if (op == kPcColsData) {  // B^T D^T D B in the Fourier domain: conj(U_j) / c^2 * sum_k U_k F_k
     float2 S = make_float2(0.0f, 0.0f);
 #pragma unroll
-    for (int k = 0; k < N; ++k) S = cadd(S, cmul(U[k], F[k]));
+    for (int k = 0; k < N; ++k) S = cadd(S, cmul(U[k], A[k]));
     S = make_float2(S.x / (float)N, S.y / (float)N);
 #pragma unroll
-    for (int j = 0; j < N; ++j) F[j] = cmul(conjf2(U[j]), S);
+    for (int j = 0; j < N; ++j) A[j] = cmul(conjf2(U[j]), S);
   } else {
-    float dd[N];
+    float eh[C], ew[C];
 #pragma unroll
-    for (int s = 0; s < C; ++s)
-#pragma unroll
-      for (int t = 0; t < C; ++t) {
-        const float sym = 4.0f - 2.0f * d.twH[k1 + s * h].x - 2.0f * d.twW[k2 + t * w].x;
-        dd[s * C + t] = dscale * sym * sym;
-      }
-    group_solve<N>(F, U, dd);
+    for (int s = 0; s < C; ++s) {
+      eh[s] = 2.0f - 2.0f * gld(d.twH + k1 + s * h).x;
+      ew[s] = uniform(2.0f - 2.0f * gld(d.twW + k2 + s * w).x);
+    }
+    group_solve<C>(A, U, eh, ew, dscale);
   }
   // inverse C x C DFT by conjugation: A = conj(sum_{s,t} X w^{-(al s + be t)}); the value wanted is
   // conj(A)/N * conj(tw), and it is stored conjugated: A tw / N
 #pragma unroll
-  for (int j = 0; j < N; ++j) A[j / C][j % C] = conjf2(F[j]);
+  for (int j = 0; j < N; ++j) A[j] = conjf2(A[j]);
   dft2<C>(A);
   const float inv = 1.0f / (float)N;
 #pragma unroll
   for (int al = 0; al < C; ++al)
 #pragma unroll
     for (int be = 0; be < C; ++be) {
-      const float2 v = cmul(A[al][be], cmul(d.twH[al * k1], d.twW[be * k2]));
-      pcsh[pd(al * C + be, seq_stride(h), k1)] = make_float2(v.x * inv, v.y * inv);
+      const float2 v = cmul(cmul(A[al * C + be], ta[al]), tb[be]);
+      pcsh[pd(al * C + be, Sh, k1)] = make_float2(v.x * inv, v.y * inv);
     }
 }
 
@@ -363,25 +517,25 @@ __device__ __forceinline__ bool band_runs(const ChanState* st, int band, int nba
 template <int C>
 __device__ __forceinline__ void ldc(const float* p, float (&v)[C]) {
   if constexpr (C == 4) {
-    const float4 t = *(const float4*)p;
+    const float4 t = gld((const float4*)p);
     v[0] = t.x, v[1] = t.y, v[2] = t.z, v[3] = t.w;
   } else if constexpr (C == 2) {
-    const float2 t = *(const float2*)p;
+    const float2 t = gld((const float2*)p);
     v[0] = t.x, v[1] = t.y;
   } else {
 #pragma unroll
-    for (int k = 0; k < C; ++k) v[k] = p[k];
+    for (int k = 0; k < C; ++k) v[k] = gld(p + k);
   }
 }
 template <int C>
 __device__ __forceinline__ void stc(float* p, const float (&v)[C]) {
   if constexpr (C == 4) {
-    *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
+    gst((float4*)p, make_float4(v[0], v[1], v[2], v[3]));
   } else if constexpr (C == 2) {
-    *(float2*)p = make_float2(v[0], v[1]);
+    gst((float2*)p, make_float2(v[0], v[1]));
   } else {
 #pragma unroll
-    for (int k = 0; k < C; ++k) p[k] = v[k];
+    for (int k = 0; k < C; ++k) gst(p + k, v[k]);
   }
 }
 // ------------------------------------------------------------------------------------------- row pass ---
@@ -419,7 +573,7 @@ __device__ __forceinline__ void rows_fwd(int op, const PcDesc& d, const ChanStat
           int a = i + g.R, b = C * n + be + g.R;
           if (a >= g.H) a -= g.H;
           if (b >= W) b -= W;
-          if (a < g.n && b < g.n) va[be] = d.u[a * g.n + b];
+          if (a < g.n && b < g.n) va[be] = gld(d.u + a * g.n + b);
         }
       } else {
 #pragma unroll
@@ -455,19 +609,19 @@ __device__ __forceinline__ void rows_fwd(int op, const PcDesc& d, const ChanStat
       for (int be = 0; be < C; ++be) pcsh[pd(al * C + be, Sw, n)] = make_float2(va[be], vb[be]);
     }
   }
+  const float2* twl = stage_twiddles<T>(pcsh, C2, w, d.tww);
   __syncthreads();
-  fft_lds<MIXED>(pcsh, w, C2, d.rw, d.nrw, d.tww);
+  fft_lds<T, MIXED>(pcsh, w, C2, d.rw, d.nrw, twl);
   float2* out = d.spec + ((size_t)pair * g.h + m) * (size_t)w * C2;
-  for (int e = threadIdx.x; e < w * C2; e += T) {  // consecutive threads: consecutive values of a cell row
-    const int k2 = e / C2, ph = e - k2 * C2;
-    out[e] = pcsh[pd(ph, Sw, k2)];
-  }
+  // consecutive threads: consecutive values of a cell row
+  copy_elems<T, 8>(
+      w * C2, [&](int e) { return pcsh[pd(e % C2, Sw, e / C2)]; }, [&](int e, float2 v) { gst(out + e, v); });
   if (op == kPcRowsKernel) return;
   double v[2] = {acc_a, acc_b};
   block_sums<2, kPcWaves>(v, red);
   if (threadIdx.x == 0) {
-    if (ra) d.partials[(size_t)ba * d.pstride * 3 + (size_t)m * 3 + 0] = v[0];
-    if (rb) d.partials[(size_t)bb * d.pstride * 3 + (size_t)m * 3 + 0] = v[1];
+    if (ra) gst(d.partials + (size_t)ba * d.pstride * 3 + (size_t)m * 3 + 0, v[0]);
+    if (rb) gst(d.partials + (size_t)bb * d.pstride * 3 + (size_t)m * 3 + 0, v[1]);
   }
 }
 
@@ -498,51 +652,112 @@ __global__ __launch_bounds__(T) void k_pc_rows(int op, const PcDesc* __restrict_
 // the inverse c x c DFT carries 1/c^2).  op kPcColsData: the same with the data term B^T D^T D B applied to
 // every group instead of P^{-1}.  op kPcColsKernel: forward transforms and the c x c DFT of pair 0 (the
 // embedded kernel), stored as U in the cell layout.  Each thread moves whole cells.
+//
+// Persistent workgroups, one per compute unit (the c^2 sequences fill its LDS): workgroup b takes a contiguous
+// range of items (scene, LR column k2, pair), pairs fastest, so that the items of one column follow each other
+// and reuse its U from the L2 cache.  The next item's column is loaded into registers while the current one
+// is transformed, so the loads overlap the LDS passes.
 
+constexpr int kColPf = kPcMaxElems / TC;  // complex values per thread of one item's column
+
+// Issue the loads of the column (h cells of C^2 values) of pair `pair`, LR column k2 into registers.
+template <int C>
+__device__ __forceinline__ void col_prefetch(const PcDesc& d, int pair, int k2, float2 (&pf)[kColPf]) {
+  constexpr int C2 = C * C;
+  const int n = d.g.h * C2, w = d.g.w;
+  const float2* sp = d.spec + (size_t)pair * d.g.h * w * C2 + (size_t)k2 * C2;
+#pragma unroll
+  for (int k = 0; k < kColPf; ++k) {
+    if (k * TC < n) {  // uniform
+      const int e = min(k * TC + opaque_tid(), n - 1);
+      pf[k] = gld(sp + (size_t)(e / C2) * w * C2 + e % C2);
+    }
+  }
+}
+
+// The prefetched column into the LDS sequences.
+template <int C>
+__device__ __forceinline__ void col_stage(const PcDesc& d, const float2 (&pf)[kColPf], float2* pcsh) {
+  constexpr int C2 = C * C;
+  const int n = d.g.h * C2, Sh = seq_stride(d.g.h);
+#pragma unroll
+  for (int k = 0; k < kColPf; ++k) {
+    const int e = k * TC + opaque_tid();
+    if (k * TC < n && e < n) pcsh[pd(e % C2, Sh, e / C2)] = pf[k];
+  }
+}
+
+// Transforms, cell operations and the store of one item whose column is in LDS (twl: the length-h twiddles).
 template <int C, bool MIXED>
-__device__ __forceinline__ void cols_body(int op, const PcDesc& d, int pair, int k2, float2* pcsh) {
+__device__ __forceinline__ void cols_body(int op, const PcDesc& d, int pair, int k2, float2* pcsh, const float2* twl) {
   constexpr int C2 = C * C;
   const Geom& g = d.g;
   const int h = g.h, w = g.w;
   float2* sp = d.spec + (size_t)pair * h * w * C2;
   const int Sh = seq_stride(h);
-  for (int e = threadIdx.x; e < h * C2; e += T) {  // consecutive threads: consecutive values of a cell
-    const int m = e / C2, ph = e - m * C2;
-    pcsh[pd(ph, Sh, m)] = sp[((size_t)m * w + k2) * C2 + ph];
-  }
-  __syncthreads();
-  fft_lds<MIXED>(pcsh, h, C2, d.rh, d.nrh, d.twh);
+  fft_lds<TC, MIXED>(pcsh, h, C2, d.rh, d.nrh, twl);
   const float dscale = op == kPcColsSolve ? (float)((double)g.lam * d.mbar[0]) : 0.0f;
-  for (int k1 = threadIdx.x; k1 < h; k1 += T) cell_op<C>(op, d, pcsh, h, k1, k2, dscale);
+#pragma unroll 1
+  for (int k1 = opaque_tid(); k1 < h; k1 += TC) cell_op<C>(op, d, pcsh, h, k1, k2, dscale);
   if (op == kPcColsKernel) return;
   __syncthreads();
-  fft_lds<MIXED>(pcsh, h, C2, d.rh, d.nrh, d.twh);
-  for (int e = threadIdx.x; e < h * C2; e += T) {
-    const int m = e / C2, ph = e - m * C2;
-    sp[((size_t)m * w + k2) * C2 + ph] = conjf2(pcsh[pd(ph, Sh, m)]);
+  fft_lds<TC, MIXED>(pcsh, h, C2, d.rh, d.nrh, twl);
+  copy_elems<TC, 8>(
+      h * C2, [&](int e) { return conjf2(pcsh[pd(e % C2, Sh, e / C2)]); },
+      [&](int e, float2 v) { gst(sp + ((size_t)(e / C2) * w + k2) * C2 + e % C2, v); });
+}
+
+// Items lo .. hi - 1 of one scene (local index k2 npair + pair), the next item's column in flight while the
+// current one is transformed.
+template <int C, bool MIXED>
+__device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanState* sst, int lo, int hi,
+                                           float2* pcsh) {
+  const int np = d.npair;
+  auto runs = [&](int l) {
+    const int pair = l % np;
+    return op == kPcColsKernel ? pair == 0
+                               : band_runs(sst, 2 * pair, d.g.N) || band_runs(sst, 2 * pair + 1, d.g.N);
+  };
+  auto next = [&](int l) {
+    for (; l < hi; ++l)
+      if (runs(l)) break;
+    return l;
+  };
+  int l = next(lo);
+  if (l >= hi) return;
+  float2 pf[kColPf];
+  col_prefetch<C>(d, l % np, l / np, pf);
+  __syncthreads();  // the LDS of a previous scene is no longer read
+  const float2* twl = stage_twiddles<TC>(pcsh, C * C, d.g.h, d.twh);
+  while (l < hi) {
+    col_stage<C>(d, pf, pcsh);
+    const int nx = next(l + 1);
+    if (nx < hi) col_prefetch<C>(d, nx % np, nx / np, pf);
+    __syncthreads();
+    cols_body<C, MIXED>(op, d, l % np, l / np, pcsh, twl);
+    __syncthreads();  // the LDS reads of this item are done
+    l = nx;
   }
 }
 
 template <bool MIXED>
-__global__ __launch_bounds__(T) void k_pc_cols(int op, const PcDesc* __restrict__ t, int count,
-                                               const ChanState* __restrict__ st) {
+__global__ __launch_bounds__(TC) void k_pc_cols(int op, const PcDesc* __restrict__ t, int count,
+                                               const ChanState* __restrict__ st, int nitems) {
   extern __shared__ float2 pcsh[];
-  const int si = find_pc(t, count, (int)blockIdx.x, [](const PcDesc& d) { return d.col_block0; });
-  const PcDesc& d = t[si];
-  const Geom& g = d.g;
-  const int local = (int)blockIdx.x - d.col_block0;
-  const int npair = op == kPcColsKernel ? 1 : d.npair;
-  if (local >= npair * g.w) return;
-  const int pair = local / g.w, k2 = local - pair * g.w;
-  if (op != kPcColsKernel) {
+  const int per = (nitems + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int i1 = min((int)blockIdx.x * per + per, nitems);
+  for (int it = (int)blockIdx.x * per; it < i1;) {
+    const PcDesc& d = t[find_pc(t, count, it, [](const PcDesc& x) { return x.col_block0; })];
+    const int end = min(i1, d.col_block0 + d.npair * d.g.w);
+    const int lo = it - d.col_block0, hi = end - d.col_block0;
     const ChanState* sst = st + d.band0;
-    if (!band_runs(sst, 2 * pair, g.N) && !band_runs(sst, 2 * pair + 1, g.N)) return;
-  }
-  switch (g.c) {
-    case 4: cols_body<4, MIXED>(op, d, pair, k2, pcsh); break;
-    case 3: cols_body<3, MIXED>(op, d, pair, k2, pcsh); break;
-    case 2: cols_body<2, MIXED>(op, d, pair, k2, pcsh); break;
-    default: cols_body<1, MIXED>(op, d, pair, k2, pcsh); break;
+    switch (d.g.c) {
+      case 4: cols_scene<4, MIXED>(op, d, sst, lo, hi, pcsh); break;
+      case 3: cols_scene<3, MIXED>(op, d, sst, lo, hi, pcsh); break;
+      case 2: cols_scene<2, MIXED>(op, d, sst, lo, hi, pcsh); break;
+      default: cols_scene<1, MIXED>(op, d, sst, lo, hi, pcsh); break;
+    }
+    it = end;
   }
 }
 
@@ -560,12 +775,11 @@ __device__ __forceinline__ void rows_inv(const PcDesc& d, const ChanState* sst, 
   const bool ra = band_runs(sst, ba, g.N), rb = band_runs(sst, bb, g.N);
   const float2* in = d.spec + ((size_t)pair * g.h + m) * (size_t)w * C2;
   const int Sw = seq_stride(w);
-  for (int e = threadIdx.x; e < w * C2; e += T) {
-    const int k2 = e / C2, ph = e - k2 * C2;
-    pcsh[pd(ph, Sw, k2)] = conjf2(in[e]);
-  }
+  copy_elems<T, 16>(
+      w * C2, [&](int e) { return conjf2(gld(in + e)); }, [&](int e, float2 v) { pcsh[pd(e % C2, Sw, e / C2)] = v; });
+  const float2* twl = stage_twiddles<T>(pcsh, C2, w, d.tww);
   __syncthreads();
-  fft_lds<MIXED>(pcsh, w, C2, d.rw, d.nrw, d.tww);
+  fft_lds<T, MIXED>(pcsh, w, C2, d.rw, d.nrw, twl);
   const float scale = 1.0f / ((float)g.h * (float)w);
   const size_t HW = (size_t)g.H * W;
   double acc_a = 0.0, acc_b = 0.0;
@@ -601,8 +815,8 @@ __device__ __forceinline__ void rows_inv(const PcDesc& d, const ChanState* sst, 
   double v[2] = {acc_a, acc_b};
   block_sums<2, kPcWaves>(v, red);
   if (threadIdx.x == 0) {
-    if (ra) d.partials[(size_t)ba * d.pstride * 3 + (size_t)m * 3 + 1] = v[0];
-    if (rb) d.partials[(size_t)bb * d.pstride * 3 + (size_t)m * 3 + 1] = v[1];
+    if (ra) gst(d.partials + (size_t)ba * d.pstride * 3 + (size_t)m * 3 + 1, v[0]);
+    if (rb) gst(d.partials + (size_t)bb * d.pstride * 3 + (size_t)m * 3 + 1, v[1]);
   }
 }
 
@@ -698,10 +912,14 @@ static bool pc_small_radix(int L) {
   return false;
 }
 
+// Dynamic LDS of a pass over transforms of length L: c^2 padded sequences and the twiddle table.
+static size_t pc_lds_bytes(int c, int L) { return ((size_t)c * c * seq_stride(L) + L) * sizeof(float2); }
+
 bool pc_supported(const Geom& g) {
   int rad[kPcMaxRad];
   if (g.c < 1 || g.c > 4 || g.r < 1 || !(g.lam > 0.0f)) return false;
   if ((size_t)g.c * g.W > (size_t)kPcMaxElems || (size_t)g.c * g.H > (size_t)kPcMaxElems) return false;
+  if (pc_lds_bytes(g.c, g.w) > (size_t)kPcMaxLds || pc_lds_bytes(g.c, g.h) > (size_t)kPcMaxLds) return false;
   if (pc_radices(g.w, rad) < 0 || pc_radices(g.h, rad) < 0) return false;
   if (pc_small_radix(g.w) && (size_t)g.c * g.W > (size_t)kPcSmallElems) return false;
   if (pc_small_radix(g.h) && (size_t)g.c * g.H > (size_t)kPcSmallElems) return false;
@@ -738,7 +956,7 @@ void pc_fill(PcDesc& d, const Geom& g, float* tw_dev) {
 }
 
 hipError_t pc_prepare() {
-  const int bytes = (kPcMaxElems + kPcMaxElems / 16 + 16) * (int)sizeof(float2);  // c^2 padded sequences
+  const int bytes = kPcMaxLds;
   const void* kernels[6] = {(const void*)k_pc_rows<false>,     (const void*)k_pc_rows<true>,
                             (const void*)k_pc_cols<false>,     (const void*)k_pc_cols<true>,
                             (const void*)k_pc_rows_inv<false>, (const void*)k_pc_rows_inv<true>};
@@ -753,7 +971,7 @@ static size_t pc_row_lds(const PcDesc* h_tab, int count) {
   size_t m = 0;
   for (int i = 0; i < count; ++i) {
     const Geom& g = h_tab[i].g;
-    const size_t b = (size_t)g.c * g.c * seq_stride(g.w) * sizeof(float2);
+    const size_t b = pc_lds_bytes(g.c, g.w);
     if (b > m) m = b;
   }
   return m;
@@ -763,7 +981,7 @@ static size_t pc_col_lds(const PcDesc* h_tab, int count) {
   size_t m = 0;
   for (int i = 0; i < count; ++i) {
     const Geom& g = h_tab[i].g;
-    const size_t b = (size_t)g.c * g.c * seq_stride(g.h) * sizeof(float2);
+    const size_t b = pc_lds_bytes(g.c, g.h);
     if (b > m) m = b;
   }
   return m;
@@ -779,6 +997,10 @@ void pc_plan(PcDesc* h_tab, int count, PcPlan* plan) {
     P.col_blocks += pc_col_blocks(h_tab[i].g);
     P.bands += h_tab[i].g.N;
   }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&P.cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess || P.cus < 1)
+    P.cus = 256;
   P.row_lds = pc_row_lds(h_tab, count);
   P.col_lds = pc_col_lds(h_tab, count);
   for (int i = 0; i < count; ++i) P.mixed |= pc_small_radix(h_tab[i].g.w) || pc_small_radix(h_tab[i].g.h);
@@ -797,10 +1019,11 @@ hipError_t launch_pc_rows(int op, const PcDesc* t, const PcPlan& P, const ChanSt
 
 hipError_t launch_pc_cols(int op, const PcDesc* t, const PcPlan& P, const ChanState* st, hipStream_t s) {
   if (P.col_blocks <= 0) return hipSuccess;
+  const int grid = std::max(1, std::min(P.col_blocks, P.cus));  // one persistent workgroup per compute unit
   if (P.mixed)
-    hipLaunchKernelGGL(k_pc_cols<true>, dim3(P.col_blocks), dim3(T), P.col_lds, s, op, t, P.count, st);
+    hipLaunchKernelGGL(k_pc_cols<true>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st, P.col_blocks);
   else
-    hipLaunchKernelGGL(k_pc_cols<false>, dim3(P.col_blocks), dim3(T), P.col_lds, s, op, t, P.count, st);
+    hipLaunchKernelGGL(k_pc_cols<false>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st, P.col_blocks);
   return hipGetLastError();
 }
 
