@@ -220,9 +220,9 @@ struct PcDesc {
   int npair;            // band pairs (N + 1) / 2: band 2i in the real part, band 2i + 1 in the imaginary part
   float2* spec;         // spectra [npair][h][w][c^2]
   float2* uhat;         // kernel DFT at the group members [h][w][c^2]: U[k1 + s h][k2 + t w] at s c + t
-  const float2* twh;    // e^{-2 pi i m / h}, m < h (FP64 evaluated, rounded once); likewise tww, twH, twW
+  const float2* twh;    // pass-major twiddles of the length-h transform (h values); likewise tww (length w)
   const float2* tww;
-  const float2* twH;
+  const float2* twH;    // e^{-2 pi i m / H}, m < H (FP64 evaluated, rounded once); likewise twW
   const float2* twW;
   const float* u;       // kernel taps [n][n]
   const float* DI;      // dinv plane of the PAN statistics [H][W]
@@ -255,7 +255,7 @@ bool pc_supported(const Geom& g);
 size_t pc_spec_floats(const Geom& g);
 size_t pc_uhat_floats(const Geom& g);
 size_t pc_tw_floats(const Geom& g);
-void pc_twiddles(const Geom& g, float* out);  // the four twiddle tables of g (host, FP64 evaluated)
+void pc_twiddles(const Geom& g, float* out);  // the twiddle tables of g (host, FP64 evaluated)
 void pc_fill(PcDesc& d, const Geom& g, float* tw_dev);  // geometry, radices and twiddle pointers
 void pc_plan(PcDesc* h_tab, int count, PcPlan* plan);   // block offsets and launch sizes
 hipError_t pc_prepare();  // dynamic-LDS limits of the transform launches (once per device)

@@ -175,16 +175,13 @@ struct Dft<7> {
 __host__ __device__ __forceinline__ int seq_stride(int L) { return L + (L >> 4) + 1; }
 __device__ __forceinline__ int pd(int seq, int S, int i) { return __mul24(seq, S) + i + (i >> 4); }
 
-// One Stockham pass of radix R over nseq sequences of length L stored back to back in buf; Ns is the length of
-// the sub-transforms already done.  tw[m] = e^{-2 pi i m / L} (in LDS).  POW2: L is a power of two and every
-// index is taken with shifts and masks.
-template <int TH, int R, int PER, bool POW2>
+// One Stockham pass of radix R (any of 2, 3, 4, 5, 7, 8) over nseq sequences of length L stored back to back in
+// buf; Ns is the length of the sub-transforms already done.  tw: this pass's twiddles in LDS, tw[(t - 1) Ns + k]
+// = e^{-2 pi i t k / (Ns R)} for k < Ns, 0 < t < R (consecutive k, read by consecutive lanes, side by side).
+template <int TH, int R, int PER>
 __device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, const float2* tw) {
   constexpr int NB = (PER + R - 1) / R;  // butterflies per thread: PER values per thread at most
-  constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
-  const int M = POW2 ? L >> LR : L / R, total = nseq * M, S = seq_stride(L);
-  const int lgM = POW2 ? __builtin_ctz(M) : 0, lgNs = POW2 ? __builtin_ctz(Ns) : 0;
-  const int stride = POW2 ? M >> lgNs : L / (Ns * R);  // tw index step of k: L / (Ns R)
+  const int M = L / R, total = nseq * M, S = seq_stride(L);
   float2 v[NB][R];
   int ob[NB];
 #pragma unroll
@@ -192,23 +189,12 @@ __device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, c
     const int j = opaque_tid() + b * TH;
     ob[b] = -1;
     if (j < total) {
-      int seq, jj, k, o;
-      if (POW2) {
-        seq = j >> lgM;
-        jj = j & (M - 1);
-        k = jj & (Ns - 1);
-        o = ((jj >> lgNs) << (lgNs + LR)) | k;
-      } else {
-        seq = j / M;
-        jj = j - seq * M;
-        k = jj % Ns;
-        o = (jj / Ns) * Ns * R + k;
-      }
+      const int seq = j / M, jj = j - seq * M, k = jj % Ns;
+      const int o = (jj / Ns) * Ns * R + k;
 #pragma unroll
       for (int t = 0; t < R; ++t) v[b][t] = buf[pd(seq, S, jj + t * M)];
-      const int ks = __mul24(k, stride);
 #pragma unroll
-      for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], tw[t * ks]);
+      for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], tw[(t - 1) * Ns + k]);
       Dft<R>::run(v[b]);
       ob[b] = (seq << 16) | o;  // sequence and element offset (L <= 16384)
     }
@@ -229,12 +215,20 @@ __device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, c
 // o + t Ns always sit t Ns + (t Ns) / 16 slots from o (the padding of a block of R Ns outputs is linear in t, as
 // the block starts on a multiple of min(R Ns, 16)).  TW = false for the first pass (Ns = 1: every twiddle is 1).
 template <int TH, int R, int PER, bool LIN, bool TW>
-__device__ __forceinline__ void fft_pass_p2(float2* buf, int L, int nseq, int Ns, const float2* tw) {
+__device__ __forceinline__ void fft_pass_p2(float2* gbuf, int L, int nseq, int Ns, const float2* gtw) {
+  // LDS-typed pointers (32-bit index arithmetic) to plain two-float vectors
+  typedef __attribute__((address_space(3))) gf2 lds_f2;
+  lds_f2* buf = (lds_f2*)gbuf;
+  const lds_f2* tw = (const lds_f2*)gtw;
+  auto ld = [](const lds_f2* p) {
+    const gf2 x = *p;
+    return make_float2(x.x, x.y);
+  };
   constexpr int NB = (PER + R - 1) / R;
   constexpr int LR = R == 8 ? 3 : 2;
   const int M = L >> LR, total = nseq * M, S = seq_stride(L);
   const int lgM = __builtin_ctz(M), lgNs = __builtin_ctz(Ns);
-  const int stride = M >> lgNs, rstep = M + (M >> 4);
+  const int rstep = M + (M >> 4);
   float2 v[NB][R];
   int wb[NB];
 #pragma unroll
@@ -247,18 +241,18 @@ __device__ __forceinline__ void fft_pass_p2(float2* buf, int L, int nseq, int Ns
       if (LIN) {
         const int rb = sb + jj + (jj >> 4);
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[b][t] = buf[rb + t * rstep];
+        for (int t = 0; t < R; ++t) v[b][t] = ld(buf + rb + t * rstep);
       } else {
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const int i = jj + t * M;
-          v[b][t] = buf[sb + i + (i >> 4)];
+          v[b][t] = ld(buf + sb + i + (i >> 4));
         }
       }
       if (TW) {
-        const int ks = __mul24(k, stride);
+        const lds_f2* twk = tw + k;
 #pragma unroll
-        for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], tw[t * ks]);
+        for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], ld(twk + (t - 1) * Ns));
       }
       Dft<R>::run(v[b]);
       const int o = ((jj >> lgNs) << (lgNs + LR)) | k;
@@ -272,7 +266,7 @@ __device__ __forceinline__ void fft_pass_p2(float2* buf, int L, int nseq, int Ns
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         const int tn = t * Ns;
-        buf[wb[b] + tn + (tn >> 4)] = v[b][t];
+        buf[wb[b] + tn + (tn >> 4)] = gf2{v[b][t].x, v[b][t].y};
       }
     }
   }
@@ -291,30 +285,32 @@ __device__ __forceinline__ void fft_pass_p2_any(float2* buf, int L, int nseq, in
   }
 }
 
-// Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L; twiddles tw in LDS).
+// Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L; tw: the pass-major
+// twiddle table of the transform in LDS, see pass_twiddles).
 // TH threads.  MIXED = false: radices 8 and 4 only (L a power of two), up to kPcMaxElems / TH values per
 // thread; MIXED = true: every radix, up to kPcSmallElems / TH values per thread (short transforms only, see
 // pc_supported).  Splitting the two keeps every pass within the register budget.
 template <int TH, bool MIXED>
 __device__ __forceinline__ void fft_lds(float2* buf, int L, int nseq, const int* rad, int nrad, const float2* tw) {
   constexpr int PER = (MIXED ? kPcSmallElems : kPcMaxElems) / TH;
-  int Ns = 1;
+  int Ns = 1, off = 0;
   for (int p = 0; p < nrad; ++p) {
     const int R = rad[p];
     if (MIXED) {
       switch (R) {
-        case 8: fft_pass<TH, 8, PER, false>(buf, L, nseq, Ns, tw); break;
-        case 4: fft_pass<TH, 4, PER, false>(buf, L, nseq, Ns, tw); break;
-        case 2: fft_pass<TH, 2, PER, false>(buf, L, nseq, Ns, tw); break;
-        case 3: fft_pass<TH, 3, PER, false>(buf, L, nseq, Ns, tw); break;
-        case 5: fft_pass<TH, 5, PER, false>(buf, L, nseq, Ns, tw); break;
-        default: fft_pass<TH, 7, PER, false>(buf, L, nseq, Ns, tw); break;
+        case 8: fft_pass<TH, 8, PER>(buf, L, nseq, Ns, tw + off); break;
+        case 4: fft_pass<TH, 4, PER>(buf, L, nseq, Ns, tw + off); break;
+        case 2: fft_pass<TH, 2, PER>(buf, L, nseq, Ns, tw + off); break;
+        case 3: fft_pass<TH, 3, PER>(buf, L, nseq, Ns, tw + off); break;
+        case 5: fft_pass<TH, 5, PER>(buf, L, nseq, Ns, tw + off); break;
+        default: fft_pass<TH, 7, PER>(buf, L, nseq, Ns, tw + off); break;
       }
     } else if (R == 8) {
-      fft_pass_p2_any<TH, 8, PER>(buf, L, nseq, Ns, tw);
+      fft_pass_p2_any<TH, 8, PER>(buf, L, nseq, Ns, tw + off);
     } else {
-      fft_pass_p2_any<TH, 4, PER>(buf, L, nseq, Ns, tw);
+      fft_pass_p2_any<TH, 4, PER>(buf, L, nseq, Ns, tw + off);
     }
+    off += Ns * (R - 1);
     Ns *= R;
   }
 }
@@ -933,8 +929,32 @@ size_t pc_spec_floats(const Geom& g) { return (size_t)((g.N + 1) / 2) * g.H * g.
 size_t pc_uhat_floats(const Geom& g) { return (size_t)g.H * g.W * 2; }
 size_t pc_tw_floats(const Geom& g) { return (size_t)2 * (g.h + g.w + g.H + g.W); }
 
+// The pass-major twiddles of a length-L transform (L complex values): pass p, of radix R over sub-transforms of
+// length Ns, holds e^{-2 pi i t k / (Ns R)} for k < Ns, 0 < t < R at sum_{q < p} Ns_q (R_q - 1) + (t - 1) Ns +
+// k; the passes use L - 1 entries and the last is unused.  FP64 evaluated, rounded once.
+static float* pass_twiddles(int L, float* out) {
+  int rad[kPcMaxRad];
+  const int n = pc_radices(L, rad);
+  float* end = out + 2 * (size_t)L;
+  int Ns = 1;
+  for (int p = 0; p < n; ++p) {
+    const int R = rad[p];
+    for (int t = 1; t < R; ++t)
+      for (int k = 0; k < Ns; ++k) {
+        const double a = -2.0 * M_PI * (double)t * (double)k / ((double)Ns * (double)R);
+        *out++ = (float)cos(a);
+        *out++ = (float)sin(a);
+      }
+    Ns *= R;
+  }
+  while (out < end) *out++ = 0.0f;
+  return end;
+}
+
 void pc_twiddles(const Geom& g, float* out) {
-  const int lens[4] = {g.h, g.w, g.H, g.W};
+  out = pass_twiddles(g.h, out);
+  out = pass_twiddles(g.w, out);
+  const int lens[2] = {g.H, g.W};
   for (int L : lens)
     for (int m = 0; m < L; ++m) {
       const double a = -2.0 * M_PI * (double)m / (double)L;
