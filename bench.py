@@ -104,8 +104,9 @@ KERNEL_NAMES = {
     "pc_cols": "k_pc_cols (column transforms, per-group solve of P, inverse column transforms)",
     "pc_rows_inv": "k_pc_rows_inv (inverse row transforms, s = P^-1 r, r^T s)",
 }
-PROF_PREFIX = {"pc_cols": "llp::k_pc_cols", "pc_rows": "llp::k_pc_rows<", "pc_rows_inv": "llp::k_pc_rows_inv",
-               "dir": "void llp::k_dir_fast<4, 8, 4, 3>", "apply": "void llp::(anonymous namespace)::k_llp<2, 1, 4, 8>"}
+# kernel names in the traffic record (namespace and template arguments, no parameter list)
+PROF_PREFIX = {"pc_cols": "llp::k_pc_cols<", "pc_rows": "llp::k_pc_rows<", "pc_rows_inv": "llp::k_pc_rows_inv<",
+               "dir": "llp::k_dir_fast<4, 8, 4, 3>", "apply": "llp::k_llp<2, 1, 4, 8>"}
 
 
 def measured_traffic(kernel):
