@@ -31,3 +31,4 @@ from .llp import (  # noqa: F401
     solve,
     window_sum,
 )
+from . import polish  # noqa: F401,E402  (the A, C step and the Z step of Algorithm "Fast Pansharpening")
