@@ -285,6 +285,18 @@ llp_status llp_precond_apply(llp_ctx* ctx, const llp_shape* shape, const llp_par
 llp_status llp_apply_data_fourier(llp_ctx* ctx, const llp_shape* shape, const llp_params* params,
                                   const float* kernel, const float* z, float* out, hipStream_t stream);
 
+/* The last two steps of Algorithm "Fast Pansharpening" (Sec. III-B) on a given Z0 (normally llp_pansharpen's
+ * output): the A, C step of eq. (ac_h_compute) (guided filtering of L Z0 with L Y as the guide, slope denominator
+ * sigma^2 + eps/|w|) and the Z step of eq. (Z_solution), solved exactly in the Fourier domain (per aliasing group)
+ * with the LLP weight lambda |w|: eq. (pansharp) counts every pixel in |w| = (2r+1)^2 windows, and with this weight
+ * the two steps are one round of exact alternating minimisation of eq. (pansharp), whose minimiser (the solution
+ * of eq. Z_ini_matting) is a fixed point.  Computed as z = z0 + P1^{-1} (b - A z0), P1 = B^T D^T D B +
+ * lambda |w| L^T L (the same values; A, C are not stored).  Needs the sizes that precond = 1 needs (llp_params)
+ * (LLP_E_UNSUPPORTED otherwise); lrms [N][h][w], pan [H][W], kernel [n][n], z0, z [N][H][W] device, z0 and z
+ * 16-byte aligned, must not alias.  Asynchronous on `stream`. */
+llp_status llp_polish(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
+                      const float* pan, const float* kernel, const float* z0, float* z, hipStream_t stream);
+
 /* The product of llp_apply_A for callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): no context, no allocation.  The PAN statistics and
  * y = D B z live in a library-owned device array of LLP_NOALLOC_SCRATCH_FLOATS floats per device (64 MiB), held

@@ -77,6 +77,7 @@ _SIGS = {
                                          _vp]),
     "llp_apply_data_fourier": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp,
                                               _vp]),
+    "llp_polish": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp]),
     "llp_apply_A_noalloc": (ctypes.c_int, [ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
     "llp_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "llp_get_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
@@ -368,6 +369,18 @@ class Context:
         out = torch.empty_like(z)
         _check(lib().llp_apply_A(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(pan), _ptr(kernel), _ptr(z),
                                  _ptr(out), _stream(stream)), "llp_apply_A")
+        return out
+
+    def polish(self, z0, lrms, pan, kernel, *, r: int, lam: float, eps: float, stream=None):
+        """A, C step and FFT Z step of Algorithm Fast Pansharpening on z0 (llp_polish); returns the new HRMS."""
+        import torch
+        N, H, W = z0.shape
+        c = H // lrms.shape[1]
+        shp = Shape(N, H // c, W // c, c, kernel.shape[0])
+        prm = Params(int(r), float(lam), float(eps), 0, 0.0, 0)
+        out = torch.empty_like(z0)
+        _check(lib().llp_polish(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(lrms), _ptr(pan), _ptr(kernel),
+                                _ptr(z0), _ptr(out), _stream(stream)), "llp_polish")
         return out
 
     def apply_data(self, z, kernel, *, c: int, r: int, stream=None):

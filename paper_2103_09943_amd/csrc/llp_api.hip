@@ -722,6 +722,43 @@ llp_status llp_apply_data_fourier(llp_ctx* ctx, const llp_shape* shape, const ll
   return fourier_apply(ctx, shape, params, nullptr, kernel, z, out, kPcColsData, stream);
 }
 
+// Algorithm "Fast Pansharpening" after Z^0 (Sec. III-B): the A, C step of eq. (ac_h_compute) and the Z step of
+// eq. (Z_solution) with weight lambda |w|.  The guided filter's output is Lhat = l - (M l)/|w| (l = L Z0, M the
+// matting matrix of L Y), so the Z step's normal equations P1 Z = B^T D^T X + lambda |w| L^T Lhat, with
+// P1 = B^T D^T D B + lambda |w| L^T L, have the solution Z = Z0 + P1^{-1} (b - A Z0): A, C never need to be
+// stored.  b - A Z0 is formed with the solve's operator kernels, P1^{-1} with the preconditioner's transforms
+// (its scalar mbar set to |w|).
+llp_status llp_polish(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
+                      const float* pan, const float* kernel, const float* z0, float* z, hipStream_t stream) {
+  if (!ctx || !params || !lrms || !pan || !kernel || !z0 || !z || z0 == z) return LLP_E_ARG;
+  if (!aligned16(z0) || !aligned16(z)) return LLP_E_ARG;
+  Geom g;
+  llp_status v = validate(shape, params, &g);
+  if (v != LLP_OK) return v;
+  if (!pc_supported(g)) return LLP_E_UNSUPPORTED;
+  OpConfig cfg;
+  if (!ctx_config(ctx, g, &cfg)) return LLP_E_UNSUPPORTED;
+  HIP_TRY(hipSetDevice(ctx->device));
+  v = ensure_workspace(ctx, g, true);
+  if (v != LLP_OK) return v;
+  const size_t NHW = (size_t)g.N * g.H * g.W;
+  HIP_TRY(launch_pan_stats(g, pan, ctx->G, ctx->MU, ctx->DI, stream));
+  HIP_TRY(launch_rhs(g, lrms, kernel, ctx->b, ctx->partials, ctx->st, stream));
+  v = apply_A_into(ctx, g, cfg, z0, kernel, ctx->q, stream);
+  if (v != LLP_OK) return v;
+  HIP_TRY(launch_pc_axpy(ctx->b, ctx->q, ctx->r[0], -1.0f, NHW, stream));  // r = b - A Z0
+  HIP_TRY(launch_init(g, 1, ctx->b, ctx->r[0], ctx->st, stream));           // every band active; r untouched
+  PcPlan PP;
+  v = pc_setup(ctx, g, kernel, ctx->q, ctx->s, &PP, stream);
+  if (v != LLP_OK) return v;
+  HIP_TRY(launch_pc_set_mbar(ctx->d_pc, 1, (double)((2 * g.r + 1) * (2 * g.r + 1)), stream));
+  HIP_TRY(launch_pc_rows(kPcRowsStart, ctx->d_pc, PP, ctx->st, 0, 0, stream));
+  HIP_TRY(launch_pc_cols(kPcColsSolve, ctx->d_pc, PP, ctx->st, stream));
+  HIP_TRY(launch_pc_rows_inv(ctx->d_pc, PP, ctx->st, 0, stream));
+  HIP_TRY(launch_pc_axpy(z0, ctx->s, z, 1.0f, NHW, stream));  // Z = Z0 + P1^{-1} r
+  return LLP_OK;
+}
+
 llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, const float* lrms,
                          const float* pan, const float* kernel, const float* z, double* obj, hipStream_t stream) {
   if (!ctx || !params || !lrms || !pan || !kernel || !z || !obj) return LLP_E_ARG;

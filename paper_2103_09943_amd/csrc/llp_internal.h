@@ -264,6 +264,9 @@ hipError_t launch_pc_rows(int op, const PcDesc* t, const PcPlan& P, const ChanSt
 hipError_t launch_pc_cols(int op, const PcDesc* t, const PcPlan& P, const ChanState* st, hipStream_t s);
 hipError_t launch_pc_rows_inv(const PcDesc* t, const PcPlan& P, const ChanState* st, int cur, hipStream_t s);
 // mbar of every scene of the table (part: count * kPcMbarBlocks doubles of scratch).
+// out = a + sb * b (n floats); the solve's scalar weight mbar set to v for every scene of the table.
+hipError_t launch_pc_axpy(const float* a, const float* b, float* out, float sb, size_t n, hipStream_t s);
+hipError_t launch_pc_set_mbar(const PcDesc* t, int count, double v, hipStream_t s);
 hipError_t launch_pc_mbar(const PcDesc* t, int count, double* part, hipStream_t s);
 
 // k_finalize (kFinDir / kFinApply) for all `bands` bands of the `count` scenes of a table; kFinDir advances each

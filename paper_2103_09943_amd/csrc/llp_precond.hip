@@ -873,6 +873,19 @@ __global__ __launch_bounds__(kBlock) void k_pc_mbar_fin(const PcDesc* __restrict
   }
 }
 
+// -------------------------------------------------------------------------------- polish (Z step) helpers ---
+// out = a + sb * b over n floats.
+__global__ __launch_bounds__(kBlock) void k_pc_axpy(const float* __restrict__ a, const float* __restrict__ b,
+                                                    float* __restrict__ out, float sb, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock)
+    out[e] = fmaf(sb, b[e], a[e]);
+}
+
+// Sets the scalar weight of the Fourier solve of every scene (mbar in P = B^T D^T D B + lambda mbar L^T L).
+__global__ void k_pc_set_mbar(const PcDesc* __restrict__ t, int count, double v) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) t[i].mbar[0] = v;
+}
+
 // ------------------------------------------------------------------------------------------------ host ---
 
 int pc_radices(int L, int* rad) {
@@ -1053,6 +1066,18 @@ hipError_t launch_pc_rows_inv(const PcDesc* t, const PcPlan& P, const ChanState*
     hipLaunchKernelGGL(k_pc_rows_inv<true>, dim3(P.row_blocks), dim3(T), P.row_lds, s, t, P.count, st, cur);
   else
     hipLaunchKernelGGL(k_pc_rows_inv<false>, dim3(P.row_blocks), dim3(T), P.row_lds, s, t, P.count, st, cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_pc_axpy(const float* a, const float* b, float* out, float sb, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_pc_axpy, dim3((unsigned)blocks), dim3(kBlock), 0, s, a, b, out, sb, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pc_set_mbar(const PcDesc* t, int count, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_pc_set_mbar, dim3(1), dim3(64), 0, s, t, count, v);
   return hipGetLastError();
 }
 
