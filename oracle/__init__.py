@@ -32,3 +32,4 @@ from .llp import (  # noqa: F401
     window_sum,
 )
 from . import polish  # noqa: F401,E402  (the A, C step and the Z step of Algorithm "Fast Pansharpening")
+from . import tgv  # noqa: F401,E402  (Algorithm "Blur Kernel Estimation", host side)
