@@ -598,6 +598,8 @@ void llp_destroy(llp_ctx* ctx) {
   if (ctx->h_bflags) (void)hipHostFree(ctx->h_bflags);
   if (ctx->h_table) (void)hipHostFree(ctx->h_table);
   if (ctx->h_rtable) (void)hipHostFree(ctx->h_rtable);
+  if (ctx->h_ptable) (void)hipHostFree(ctx->h_ptable);
+  if (ctx->h_btw) (void)hipHostFree(ctx->h_btw);
   if (ctx->bev_in) (void)hipEventDestroy(ctx->bev_in);
   if (ctx->bstream) (void)hipStreamDestroy(ctx->bstream);
   cnn_free(ctx->cnn);

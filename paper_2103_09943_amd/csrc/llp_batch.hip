@@ -58,9 +58,11 @@ llp_status ensure_batch_mirrors(llp_ctx* ctx, int bands, int scenes) {
     if (ctx->h_bflags) (void)hipHostFree(ctx->h_bflags);
     if (ctx->h_table) (void)hipHostFree(ctx->h_table);
     if (ctx->h_rtable) (void)hipHostFree(ctx->h_rtable);
+    if (ctx->h_ptable) (void)hipHostFree(ctx->h_ptable);
     ctx->h_bflags = nullptr;
     ctx->h_table = nullptr;
     ctx->h_rtable = nullptr;
+    ctx->h_ptable = nullptr;
     ctx->hb_scenes = 0;
     if (hipHostMalloc((void**)&ctx->h_bflags, sizeof(int) * scenes, hipHostMallocDefault) != hipSuccess)
       return LLP_E_OOM;
@@ -68,19 +70,66 @@ llp_status ensure_batch_mirrors(llp_ctx* ctx, int bands, int scenes) {
       return LLP_E_OOM;
     if (hipHostMalloc((void**)&ctx->h_rtable, sizeof(RefDesc) * scenes, hipHostMallocDefault) != hipSuccess)
       return LLP_E_OOM;
+    if (hipHostMalloc((void**)&ctx->h_ptable, sizeof(PcDesc) * scenes, hipHostMallocDefault) != hipSuccess)
+      return LLP_E_OOM;
     ctx->hb_scenes = scenes;
   }
   return LLP_OK;
 }
 
+llp_status ensure_batch_twiddles(llp_ctx* ctx, size_t floats) {
+  if (ctx->h_btw_cap >= floats) return LLP_OK;
+  if (ctx->h_btw) (void)hipHostFree(ctx->h_btw);
+  ctx->h_btw = nullptr;
+  ctx->h_btw_cap = 0;
+  if (hipHostMalloc((void**)&ctx->h_btw, floats * sizeof(float), hipHostMallocDefault) != hipSuccess) return LLP_E_OOM;
+  ctx->h_btw_cap = floats;
+  return LLP_OK;
+}
+
 // Enqueues `count` CG iterations of every class; the first reads the buffers of `parity`.  With `prof` set,
 // every class launch is bracketed by timing events of that context.
+// Preconditioned (d_pc, PP given): after the operator, alpha; the update and forward rows, the columns with the
+// group solve, the inverse rows (s = P^{-1} r), beta; p = s + beta p and y = D B p; the stopping rule.
 llp_status enqueue_batch_iters(const std::vector<BatchClass>& classes, const SceneDesc* d_table, int nscenes,
                                int nbands, ChanState* st, char* ws, const float* taps, int count, int parity,
                                int max_iters, float tol, hipStream_t s, llp_ctx* prof, const RefDesc* d_ref,
-                               const RefPlan& rplan, double* results) {
+                               const RefPlan& rplan, double* results, const PcDesc* d_pc, const PcPlan* PP) {
   for (int j = 0; j < count; ++j) {
     const int par = (parity + j) & 1;
+    if (d_pc) {
+      for (size_t c = 0; c < classes.size(); ++c) {
+        const BatchClass& k = classes[c];
+        const int tp = prof ? timing_begin(prof, s) : -1;
+        if (k.variant == kSweepVariant)
+          HIP_TRY(launch_apply_sweep_batch(d_table + k.first, k.count, k.data_blocks, k.apply_blocks, k.C, k.R, k.r,
+                                           par, st, ws, taps, s));
+        else
+          HIP_TRY(launch_apply_fast_batch(d_table + k.first, k.count, k.apply_blocks, k.C, k.R, k.r, k.variant, par,
+                                          st, ws, taps, s));
+        if (prof) timing_end(prof, s, tp, kTApply);
+      }
+      HIP_TRY(launch_finalize_batch(kFinPcgAlpha, d_table, nscenes, nbands, st, ws, max_iters, tol, s));
+      int tp = prof ? timing_begin(prof, s) : -1;
+      HIP_TRY(launch_pc_rows(kPcRowsUpdate, d_pc, *PP, st, par, 1 - par, s));
+      if (prof) timing_end(prof, s, tp, kTPcRows);
+      tp = prof ? timing_begin(prof, s) : -1;
+      HIP_TRY(launch_pc_cols(kPcColsSolve, d_pc, *PP, st, s));
+      if (prof) timing_end(prof, s, tp, kTPcCols);
+      tp = prof ? timing_begin(prof, s) : -1;
+      HIP_TRY(launch_pc_rows_inv(d_pc, *PP, st, 1 - par, s));
+      if (prof) timing_end(prof, s, tp, kTPcRowsInv);
+      HIP_TRY(launch_finalize_batch(kFinPcgBeta, d_table, nscenes, nbands, st, ws, max_iters, tol, s));
+      for (size_t c = 0; c < classes.size(); ++c) {
+        const BatchClass& k = classes[c];
+        tp = prof ? timing_begin(prof, s) : -1;
+        HIP_TRY(launch_dir_fast_batch(d_table + k.first, k.count, k.dir_blocks, k.C, k.R, k.dir_rows, par, st, ws,
+                                      taps, 3, s));
+        if (prof) timing_end(prof, s, tp, kTDir);
+      }
+      HIP_TRY(launch_finalize_batch(kFinPcgStop, d_table, nscenes, nbands, st, ws, max_iters, tol, s));
+      continue;
+    }
     for (size_t c = 0; c < classes.size(); ++c) {
       const BatchClass& k = classes[c];
       const int tp = prof ? timing_begin(prof, s) : -1;
@@ -104,7 +153,8 @@ llp_status enqueue_batch_iters(const std::vector<BatchClass>& classes, const Sce
   }
   // residual replacement for the bands that are due; the next iteration reads the buffers of parity + count
   const int tr = prof ? timing_begin(prof, s) : -1;
-  const llp_status v = ref_pass(d_ref, rplan, st, results, kRefStep, 0, (parity + count) & 1, 1, max_iters, tol, 1, s);
+  const llp_status v =
+      ref_pass(d_ref, rplan, st, results, kRefStep, 0, (parity + count) & 1, 1, max_iters, tol, d_pc ? 0 : 1, s);
   if (prof) timing_end(prof, s, tr, kTRef);
   return v;
 }
@@ -161,7 +211,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     if (!ctx_config(ctx, b.g, &b.cfg, batched)) return LLP_E_UNSUPPORTED;
     b.cls = class_key(b.g, b.cfg);
     total_bands += b.g.N;
-    if (b.cfg.fast && !(flags & LLP_BATCH_SERIAL) && !params->precond) fast.push_back(b);
+    if (b.cfg.fast && !(flags & LLP_BATCH_SERIAL)) fast.push_back(b);
     else slow.push_back(b);
   }
   HIP_TRY(hipSetDevice(ctx->device));
@@ -181,14 +231,15 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     if (st > 0 && worst == LLP_OK) worst = (llp_status)st;
   };
 
+  const bool pc = params->precond != 0;  // validate() has checked that every scene supports it
   if (!fast.empty()) {
     std::stable_sort(fast.begin(), fast.end(),
                      [](const BatchScene& a, const BatchScene& b) { return a.cls < b.cls; });
     const int nf = (int)fast.size();
     // Workspace: per scene the planes and partials of the single-scene solve, then the band states, the
     // result slots, the input flags and the scene table.
-    std::vector<size_t> o_pl(nf), o_part(nf);
-    size_t off = 0;
+    std::vector<size_t> o_pl(nf), o_part(nf), o_pcs(nf), tw_off(nf);
+    size_t off = 0, tw_total = 0;
     int nbands = 0;
     for (int i = 0; i < nf; ++i) {
       const Geom& g = fast[i].g;
@@ -198,6 +249,14 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       // FP64 part and D B x in FP64
       off = align_up(off + (3 * HW + 7 * (size_t)g.N * HW + (size_t)g.N * g.h * g.w) * sizeof(float), 256);
       off = align_up(off + ((size_t)g.N * HW + (size_t)g.N * g.h * g.w) * sizeof(double), 256);
+      if (pc) {  // s, the spectra of the band pairs, U
+        o_pcs[i] = off;
+        off = align_up(off + (size_t)g.N * HW * sizeof(float), 256);
+        off = align_up(off + pc_spec_floats(g) * sizeof(float), 256);
+        off = align_up(off + pc_uhat_floats(g) * sizeof(float), 256);
+        tw_off[i] = tw_total;
+        tw_total += pc_tw_floats(g);
+      }
       o_part[i] = off;
       off = align_up(off + (size_t)g.N * max_partials_per_band(g) * 3 * sizeof(double), 256);
       nbands += g.N;
@@ -214,6 +273,12 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     off = align_up(off + (size_t)nf * kTapStride * sizeof(float), 256);
     const size_t o_ref = off;
     off = align_up(off + (size_t)nf * sizeof(RefDesc), 256);
+    const size_t o_pct = off;  // preconditioned: the transform table, mbar and its partials, the twiddles
+    if (pc) off = align_up(off + (size_t)nf * sizeof(PcDesc), 256);
+    const size_t o_mbar = off;
+    if (pc) off = align_up(off + (size_t)nf * (1 + kPcMbarBlocks) * sizeof(double), 256);
+    const size_t o_tw = off;
+    if (pc) off = align_up(off + tw_total * sizeof(float), 256);
     if (off > ctx->bws_bytes) {
       if (ctx->bws) {
         HIP_TRY(hipStreamSynchronize(s));
@@ -234,6 +299,10 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     }
     llp_status v = ensure_batch_mirrors(ctx, nbands, nf);
     if (v != LLP_OK) return v;
+    if (pc) {
+      v = ensure_batch_twiddles(ctx, tw_total);
+      if (v != LLP_OK) return v;
+    }
     char* base = (char*)ctx->bws;
     ChanState* st = (ChanState*)(base + o_st);
     double* results = (double*)(base + o_res);
@@ -241,8 +310,12 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     SceneDesc* d_table = (SceneDesc*)(base + o_table);
     float* d_taps = (float*)(base + o_taps);
     RefDesc* d_ref = (RefDesc*)(base + o_ref);
+    PcDesc* d_pc = pc ? (PcDesc*)(base + o_pct) : nullptr;
+    double* d_mbar = (double*)(base + o_mbar);
+    float* d_tw = (float*)(base + o_tw);
     SceneDesc* tab = ctx->h_table;
     RefDesc* rtab = ctx->h_rtable;
+    PcDesc* ptab = ctx->h_ptable;
     std::vector<BatchClass> classes;
     int band = 0;
     for (int i = 0; i < nf; ++i) {
@@ -297,6 +370,31 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       d.o_MU = rel(d.MU);
       d.o_DI = rel(d.DI);
       d.o_partials = rel(d.partials);
+      if (pc) {
+        float* sv = (float*)(base + o_pcs[i]);
+        float* spec = (float*)(base + align_up(o_pcs[i] + NHW * sizeof(float), 256));
+        float* uhat = (float*)((char*)spec + align_up(pc_spec_floats(g) * sizeof(float), 256));
+        d.o_s = rel(sv);
+        PcDesc& pd = ptab[i];
+        memset(&pd, 0, sizeof(pd));
+        pc_fill(pd, g, d_tw + tw_off[i]);
+        pd.spec = (float2*)spec;
+        pd.uhat = (float2*)uhat;
+        pd.u = d.u;
+        pd.DI = d.DI;
+        pd.mbar = d_mbar + i;
+        for (int j = 0; j < 2; ++j) {
+          pd.r[j] = d.r[j];
+          pd.p[j] = d.p[j];
+        }
+        pd.q = d.q;
+        pd.z = d.x;
+        pd.s = sv;
+        pd.partials = d.partials;
+        pd.pstride = (int)max_partials_per_band(g);
+        pd.band0 = band;
+        pc_twiddles(g, ctx->h_btw + tw_off[i]);
+      }
       d.taps_index = i;
       d.pstride = (int)max_partials_per_band(g);
       d.band0 = band;
@@ -334,6 +432,12 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     }
     RefPlan rplan;
     ref_plan(rtab, nf, &rplan);
+    PcPlan pplan;
+    if (pc) {
+      pc_plan(ptab, nf, &pplan);
+      HIP_TRY(hipMemcpyAsync(d_pc, ptab, sizeof(PcDesc) * nf, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(d_tw, ctx->h_btw, tw_total * sizeof(float), hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(hipMemcpyAsync(d_table, tab, sizeof(SceneDesc) * nf, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_ref, rtab, sizeof(RefDesc) * nf, hipMemcpyHostToDevice, s));
     for (int i = 0; i < nf; ++i)
@@ -361,6 +465,11 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       }
       HIP_TRY(launch_init(g, from_init || net_init, d.b, d.r[0], sst, s));
     }
+    if (pc) {  // every scene's kernel spectrum U in the cell layout, and mbar (from the statistics)
+      HIP_TRY(launch_pc_rows(kPcRowsKernel, d_pc, pplan, st, 0, 0, s));
+      HIP_TRY(launch_pc_cols(kPcColsKernel, d_pc, pplan, st, s));
+      HIP_TRY(launch_pc_mbar(d_pc, nf, d_mbar + nf, s));
+    }
     // All scenes: the iterate's FP64 part from the start; for a given start r_0 = b - A Z0 in FP64.
     HIP_TRY(launch_ref_elem((from_init || net_init) ? kRefStartFrom : kRefStartZero, d_ref, nf, rplan.eblocks, st, 1,
                             s));
@@ -368,17 +477,28 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       v = ref_pass(d_ref, rplan, st, results, kRefStart, 1, 0, 1, max_iters, tol, 1, s);
       if (v != LLP_OK) return v;
     }
-    // Per scene: network-start check, then p_0, y = D B p_0 and rho_0.
+    // Per scene: network-start check.  Then p_0, y = D B p_0 and rho_0; preconditioned, s_0 = P^{-1} r_0 for all
+    // scenes first, rho_0 = r_0^T s_0 and p_0 = s_0.
+    if (net_init)
+      for (int i = 0; i < nf; ++i) {
+        const SceneDesc& d = tab[i];
+        HIP_TRY(launch_fallback(d.g, results + (size_t)d.band0 * kResultSlots, st + d.band0, d.b, d.r[0],
+                                rtab[i].xacc, s));
+      }
+    if (pc) {
+      HIP_TRY(launch_pc_rows(kPcRowsStart, d_pc, pplan, st, 0, 0, s));
+      HIP_TRY(launch_pc_cols(kPcColsSolve, d_pc, pplan, st, s));
+      HIP_TRY(launch_pc_rows_inv(d_pc, pplan, st, 0, s));
+      HIP_TRY(launch_finalize_batch(kFinPcgStart, d_table, nf, nbands, st, base, max_iters, tol, s));
+    }
     for (int i = 0; i < nf; ++i) {
       const SceneDesc& d = tab[i];
       const Geom& g = d.g;
       const OpConfig& cfg = fast[i].cfg;
       ChanState* sst = st + d.band0;
-      if (net_init)
-        HIP_TRY(launch_fallback(g, results + (size_t)d.band0 * kResultSlots, sst, d.b, d.r[0], rtab[i].xacc, s));
-      HIP_TRY(launch_dir(g, cfg, 1, 0, 0, d.r[0], nullptr, nullptr, nullptr, d.p[0], d.x, d.y, d.u, d.partials,
-                         sst, max_iters, tol, s));
-      HIP_TRY(launch_finalize(g, kFinDir, d.partials, d.dir_ntiles, sst, nullptr, 0, 0, max_iters, tol, s));
+      HIP_TRY(launch_dir(g, cfg, 1, 0, 0, pc ? (const float*)(base + d.o_s) : d.r[0], nullptr, nullptr, nullptr,
+                         d.p[0], d.x, d.y, d.u, d.partials, sst, max_iters, tol, s));
+      if (!pc) HIP_TRY(launch_finalize(g, kFinDir, d.partials, d.dir_ntiles, sst, nullptr, 0, 0, max_iters, tol, s));
     }
 
     // CG iterations of all bands together, in chunks of kCheckEvery (even: every chunk starts on parity 0).
@@ -390,7 +510,12 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       memcpy(&tol_bits, &tol, sizeof(tol_bits));
       std::vector<long long> key = {(long long)(uintptr_t)d_table, (long long)(uintptr_t)st, nf, nbands, max_iters,
                                     (long long)tol_bits, (long long)(uintptr_t)d_ref, rplan.eblocks, rplan.yblocks,
-                                    rplan.rblocks, (long long)rplan.ylds, (long long)rplan.rlds};
+                                    rplan.rblocks, (long long)rplan.ylds, (long long)rplan.rlds, (long long)pc};
+      if (pc)
+        for (long long x : {(long long)(uintptr_t)d_pc, (long long)pplan.row_blocks, (long long)pplan.col_blocks,
+                            (long long)pplan.row_lds, (long long)pplan.col_lds, (long long)pplan.mixed,
+                            (long long)pplan.cus})
+          key.push_back(x);
       for (const BatchClass& k : classes)
         for (long long x : {(long long)k.C, (long long)k.R, (long long)k.r, (long long)k.dir_rows,
                             (long long)k.variant, (long long)k.first, (long long)k.count, (long long)k.dir_blocks,
@@ -406,7 +531,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         for (const BatchClass& k : classes) {  // LDS limits are set outside the capture
           if (k.variant != kSweepVariant)
             HIP_TRY(launch_apply_fast_batch(d_table, k.count, 0, k.C, k.R, k.r, k.variant, 0, st, base, d_taps, s));
-          HIP_TRY(launch_dir_fast_batch(d_table, k.count, 0, k.C, k.R, k.dir_rows, 0, st, base, d_taps, 2, s));
+          HIP_TRY(launch_dir_fast_batch(d_table, k.count, 0, k.C, k.R, k.dir_rows, 0, st, base, d_taps, pc ? 3 : 2,
+                                        s));
         }
         hipStream_t cs = nullptr;
         HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -415,7 +541,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) cv = LLP_E_HIP;
         if (cv == LLP_OK)
           cv = enqueue_batch_iters(classes, d_table, nf, nbands, st, base, d_taps, kCheckEvery, 0, max_iters, tol, cs,
-                                   nullptr, d_ref, rplan, results);
+                                   nullptr, d_ref, rplan, results, d_pc, pc ? &pplan : nullptr);
         if (hipStreamEndCapture(cs, &graph) != hipSuccess && cv == LLP_OK) cv = LLP_E_HIP;
         (void)hipStreamDestroy(cs);
         if (cv == LLP_OK && hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -432,7 +558,7 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
       if (use_graph) HIP_TRY(hipGraphLaunch(ctx->gexec, s));
       else {
         v = enqueue_batch_iters(classes, d_table, nf, nbands, st, base, d_taps, kCheckEvery, 0, max_iters, tol, s,
-                                prof, d_ref, rplan, results);
+                                prof, d_ref, rplan, results, d_pc, pc ? &pplan : nullptr);
         if (v != LLP_OK) return v;
       }
       if (!tol_mode) continue;

@@ -144,7 +144,10 @@ struct llp_ctx {
   int* h_bflags = nullptr;
   llp::SceneDesc* h_table = nullptr;
   llp::RefDesc* h_rtable = nullptr;
+  llp::PcDesc* h_ptable = nullptr;  // preconditioned batches: the transform table
   int hb_bands = 0, hb_scenes = 0;  // capacities of the batch mirrors
+  float* h_btw = nullptr;           // preconditioned batches: pinned twiddle staging of all scenes
+  size_t h_btw_cap = 0;
   hipGraphExec_t gexec = nullptr;
   std::vector<long long> gkey;  // what the cached graph was captured for
   // launch configurations chosen by the autotuner (llp_autotune), by geometry class
