@@ -209,6 +209,7 @@ hipError_t launch_ref_fin(int op, const RefDesc* t, int count, int bands, ChanSt
 // ---- Fourier-domain preconditioner (llp_precond.hip) -------------------------------------------------------------
 constexpr int kPcThreads = 1024;   // threads per workgroup of the row transform passes
 constexpr int kPcColThreads = 512; // threads per workgroup of the column pass
+constexpr int kPcSmallRowThreads = 256;  // row passes of tables whose rows hold at most kPcSmallElems values
 constexpr int kPcMaxElems = 16384; // complex values a workgroup holds in LDS: c W and c H at most this
 constexpr int kPcSmallElems = 4096; // the same where a transform needs radix 2, 3, 5 or 7
 constexpr int kPcMaxRad = 16;      // radix passes per transform length
@@ -237,6 +238,7 @@ struct PcDesc {
   int band0;
   int row_block0, col_block0;  // first workgroup of the scene in the row and column launches
   int nrw, nrh;                // radix passes of the length-w and length-h transforms
+  int mixed_w, mixed_h;        // the length-w (length-h) transform needs a radix other than 8 and 4
   int rw[kPcMaxRad], rh[kPcMaxRad];
 };
 struct PcPlan {
@@ -244,6 +246,7 @@ struct PcPlan {
   size_t row_lds = 0, col_lds = 0;
   int cus = 256;       // compute units of the device (persistent column workgroups)
   bool mixed = false;  // some transform length needs radix 2, 3, 5 or 7 (the kernels for short transforms)
+  bool small_rows = false;  // every scene's c^2 w <= kPcSmallElems: row passes of kPcSmallRowThreads threads
 };
 enum PcRowsOp { kPcRowsStart = 0, kPcRowsUpdate = 1, kPcRowsKernel = 2 };
 enum PcColsOp { kPcColsSolve = 0, kPcColsKernel = 1, kPcColsData = 2 };

@@ -37,9 +37,11 @@ using namespace dev;
 
 namespace {
 
-constexpr int T = kPcThreads;      // threads of the row passes
+constexpr int T = kPcThreads;      // threads of the row passes (TS for tables whose rows hold <= kPcSmallElems)
+constexpr int TS = kPcSmallRowThreads;
 constexpr int TC = kPcColThreads;  // threads of the column pass (more registers per thread for the group solve)
-constexpr int kPcWaves = T / 64;
+// Complex values a row-pass workgroup of TH threads holds at most.
+__host__ __device__ constexpr int row_elems(int TH) { return TH == T ? kPcMaxElems : kPcSmallElems; }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -287,12 +289,12 @@ __device__ __forceinline__ void fft_pass_p2_any(float2* buf, int L, int nseq, in
 
 // Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L; tw: the pass-major
 // twiddle table of the transform in LDS, see pass_twiddles).
-// TH threads.  MIXED = false: radices 8 and 4 only (L a power of two), up to kPcMaxElems / TH values per
-// thread; MIXED = true: every radix, up to kPcSmallElems / TH values per thread (short transforms only, see
-// pc_supported).  Splitting the two keeps every pass within the register budget.
-template <int TH, bool MIXED>
+// TH threads, at most ELEMS values.  MIXED = false: radices 8 and 4 only (L a power of two), up to ELEMS / TH
+// values per thread; MIXED = true: every radix, up to min(ELEMS, kPcSmallElems) / TH values per thread (short
+// transforms only, see pc_supported).  Splitting the two keeps every pass within the register budget.
+template <int TH, bool MIXED, int ELEMS = kPcMaxElems>
 __device__ __forceinline__ void fft_lds(float2* buf, int L, int nseq, const int* rad, int nrad, const float2* tw) {
-  constexpr int PER = (MIXED ? kPcSmallElems : kPcMaxElems) / TH;
+  constexpr int PER = (MIXED ? (ELEMS < kPcSmallElems ? ELEMS : kPcSmallElems) : ELEMS) / TH;
   int Ns = 1, off = 0;
   for (int p = 0; p < nrad; ++p) {
     const int R = rad[p];
@@ -541,7 +543,7 @@ __device__ __forceinline__ void stc(float* p, const float (&v)[C]) {
 // the band's partials (one per LR row).  Each thread moves whole cells: the C x C pixels (c m + al, c n + be)
 // of LR pixel (m, n) on the way in, the c^2 spectral values of frequency (m, k2) on the way out.
 
-template <int C, bool MIXED>
+template <int C, bool MIXED, int TH>
 __device__ __forceinline__ void rows_fwd(int op, const PcDesc& d, const ChanState* sst, int pair, int m, int prev,
                                          int cur, float2* pcsh, double* red) {
   constexpr int C2 = C * C;
@@ -554,7 +556,7 @@ __device__ __forceinline__ void rows_fwd(int op, const PcDesc& d, const ChanStat
   const size_t HW = (size_t)g.H * W;
   const int Sw = seq_stride(w);
   double acc_a = 0.0, acc_b = 0.0;
-  for (int n = threadIdx.x; n < w; n += T) {
+  for (int n = threadIdx.x; n < w; n += TH) {
 #pragma unroll
     for (int al = 0; al < C; ++al) {
       const int i = C * m + al;
@@ -605,27 +607,38 @@ __device__ __forceinline__ void rows_fwd(int op, const PcDesc& d, const ChanStat
       for (int be = 0; be < C; ++be) pcsh[pd(al * C + be, Sw, n)] = make_float2(va[be], vb[be]);
     }
   }
-  const float2* twl = stage_twiddles<T>(pcsh, C2, w, d.tww);
+  const float2* twl = stage_twiddles<TH>(pcsh, C2, w, d.tww);
   __syncthreads();
-  fft_lds<T, MIXED>(pcsh, w, C2, d.rw, d.nrw, twl);
+  fft_lds<TH, MIXED, row_elems(TH)>(pcsh, w, C2, d.rw, d.nrw, twl);
   float2* out = d.spec + ((size_t)pair * g.h + m) * (size_t)w * C2;
   // consecutive threads: consecutive values of a cell row
-  copy_elems<T, 8>(
+  copy_elems<TH, 8>(
       w * C2, [&](int e) { return pcsh[pd(e % C2, Sw, e / C2)]; }, [&](int e, float2 v) { gst(out + e, v); });
   if (op == kPcRowsKernel) return;
   double v[2] = {acc_a, acc_b};
-  block_sums<2, kPcWaves>(v, red);
+  block_sums<2, TH / 64>(v, red);
   if (threadIdx.x == 0) {
     if (ra) gst(d.partials + (size_t)ba * d.pstride * 3 + (size_t)m * 3 + 0, v[0]);
     if (rb) gst(d.partials + (size_t)bb * d.pstride * 3 + (size_t)m * 3 + 0, v[1]);
   }
 }
 
-template <bool MIXED>
-__global__ __launch_bounds__(T) void k_pc_rows(int op, const PcDesc* __restrict__ t, int count,
+template <bool MIXED, int TH>
+__device__ __forceinline__ void rows_fwd_c(int op, const PcDesc& d, const ChanState* sst, int pair, int m, int prev,
+                                           int cur, float2* pcsh, double* red) {
+  switch (d.g.c) {
+    case 4: rows_fwd<4, MIXED, TH>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
+    case 3: rows_fwd<3, MIXED, TH>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
+    case 2: rows_fwd<2, MIXED, TH>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
+    default: rows_fwd<1, MIXED, TH>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
+  }
+}
+
+template <bool MIXED, int TH>
+__global__ __launch_bounds__(TH) void k_pc_rows(int op, const PcDesc* __restrict__ t, int count,
                                                const ChanState* __restrict__ st, int prev, int cur) {
   extern __shared__ float2 pcsh[];
-  __shared__ double red[2 * kPcWaves];
+  __shared__ double red[2 * (TH / 64)];
   const int si = find_pc(t, count, (int)blockIdx.x, [](const PcDesc& d) { return d.row_block0; });
   const PcDesc& d = t[si];
   const Geom& g = d.g;
@@ -635,12 +648,9 @@ __global__ __launch_bounds__(T) void k_pc_rows(int op, const PcDesc* __restrict_
   const int pair = local / g.h, m = local - pair * g.h;
   const ChanState* sst = st + d.band0;
   if (op != kPcRowsKernel && !band_runs(sst, 2 * pair, g.N) && !band_runs(sst, 2 * pair + 1, g.N)) return;
-  switch (g.c) {
-    case 4: rows_fwd<4, MIXED>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
-    case 3: rows_fwd<3, MIXED>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
-    case 2: rows_fwd<2, MIXED>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
-    default: rows_fwd<1, MIXED>(op, d, sst, pair, m, prev, cur, pcsh, red); break;
-  }
+  // a launch for tables with mixed-radix lengths still runs the power-of-two passes on the scenes that allow them
+  if (MIXED && d.mixed_w) rows_fwd_c<true, TH>(op, d, sst, pair, m, prev, cur, pcsh, red);
+  else rows_fwd_c<false, TH>(op, d, sst, pair, m, prev, cur, pcsh, red);
 }
 
 // ---------------------------------------------------------------------------------------- column pass ---
@@ -654,6 +664,7 @@ __global__ __launch_bounds__(T) void k_pc_rows(int op, const PcDesc* __restrict_
 // and reuse its U from the L2 cache.  The next item's column is loaded into registers while the current one
 // is transformed, so the loads overlap the LDS passes.
 
+constexpr size_t kPcCuLds = 160 * 1024;    // LDS of a compute unit
 constexpr int kColPf = kPcMaxElems / TC;  // complex values per thread of one item's column
 
 // Issue the loads of the column (h cells of C^2 values) of pair `pair`, LR column k2 into registers.
@@ -737,6 +748,17 @@ __device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanSt
 }
 
 template <bool MIXED>
+__device__ __forceinline__ void cols_scene_c(int op, const PcDesc& d, const ChanState* sst, int lo, int hi,
+                                             float2* pcsh) {
+  switch (d.g.c) {
+    case 4: cols_scene<4, MIXED>(op, d, sst, lo, hi, pcsh); break;
+    case 3: cols_scene<3, MIXED>(op, d, sst, lo, hi, pcsh); break;
+    case 2: cols_scene<2, MIXED>(op, d, sst, lo, hi, pcsh); break;
+    default: cols_scene<1, MIXED>(op, d, sst, lo, hi, pcsh); break;
+  }
+}
+
+template <bool MIXED>
 __global__ __launch_bounds__(TC) void k_pc_cols(int op, const PcDesc* __restrict__ t, int count,
                                                const ChanState* __restrict__ st, int nitems) {
   extern __shared__ float2 pcsh[];
@@ -747,12 +769,8 @@ __global__ __launch_bounds__(TC) void k_pc_cols(int op, const PcDesc* __restrict
     const int end = min(i1, d.col_block0 + d.npair * d.g.w);
     const int lo = it - d.col_block0, hi = end - d.col_block0;
     const ChanState* sst = st + d.band0;
-    switch (d.g.c) {
-      case 4: cols_scene<4, MIXED>(op, d, sst, lo, hi, pcsh); break;
-      case 3: cols_scene<3, MIXED>(op, d, sst, lo, hi, pcsh); break;
-      case 2: cols_scene<2, MIXED>(op, d, sst, lo, hi, pcsh); break;
-      default: cols_scene<1, MIXED>(op, d, sst, lo, hi, pcsh); break;
-    }
+    if (MIXED && d.mixed_h) cols_scene_c<true>(op, d, sst, lo, hi, pcsh);
+    else cols_scene_c<false>(op, d, sst, lo, hi, pcsh);
     it = end;
   }
 }
@@ -761,7 +779,7 @@ __global__ __launch_bounds__(TC) void k_pc_cols(int op, const PcDesc* __restrict
 // s = P^{-1} r for both bands of a pair (inverse length-w transforms, scale 1/(h w)), and the partial sums of
 // r[cur]^T s per band into slot 1 of the band's partials.
 
-template <int C, bool MIXED>
+template <int C, bool MIXED, int TH>
 __device__ __forceinline__ void rows_inv(const PcDesc& d, const ChanState* sst, int pair, int m, int cur,
                                          float2* pcsh, double* red) {
   constexpr int C2 = C * C;
@@ -771,15 +789,15 @@ __device__ __forceinline__ void rows_inv(const PcDesc& d, const ChanState* sst, 
   const bool ra = band_runs(sst, ba, g.N), rb = band_runs(sst, bb, g.N);
   const float2* in = d.spec + ((size_t)pair * g.h + m) * (size_t)w * C2;
   const int Sw = seq_stride(w);
-  copy_elems<T, 16>(
+  copy_elems<TH, 16>(
       w * C2, [&](int e) { return conjf2(gld(in + e)); }, [&](int e, float2 v) { pcsh[pd(e % C2, Sw, e / C2)] = v; });
-  const float2* twl = stage_twiddles<T>(pcsh, C2, w, d.tww);
+  const float2* twl = stage_twiddles<TH>(pcsh, C2, w, d.tww);
   __syncthreads();
-  fft_lds<T, MIXED>(pcsh, w, C2, d.rw, d.nrw, twl);
+  fft_lds<TH, MIXED, row_elems(TH)>(pcsh, w, C2, d.rw, d.nrw, twl);
   const float scale = 1.0f / ((float)g.h * (float)w);
   const size_t HW = (size_t)g.H * W;
   double acc_a = 0.0, acc_b = 0.0;
-  for (int n = threadIdx.x; n < w; n += T) {
+  for (int n = threadIdx.x; n < w; n += TH) {
 #pragma unroll
     for (int al = 0; al < C; ++al) {
       const size_t e = (size_t)(C * m + al) * W + (size_t)C * n;
@@ -809,18 +827,29 @@ __device__ __forceinline__ void rows_inv(const PcDesc& d, const ChanState* sst, 
     }
   }
   double v[2] = {acc_a, acc_b};
-  block_sums<2, kPcWaves>(v, red);
+  block_sums<2, TH / 64>(v, red);
   if (threadIdx.x == 0) {
     if (ra) gst(d.partials + (size_t)ba * d.pstride * 3 + (size_t)m * 3 + 1, v[0]);
     if (rb) gst(d.partials + (size_t)bb * d.pstride * 3 + (size_t)m * 3 + 1, v[1]);
   }
 }
 
-template <bool MIXED>
-__global__ __launch_bounds__(T) void k_pc_rows_inv(const PcDesc* __restrict__ t, int count,
+template <bool MIXED, int TH>
+__device__ __forceinline__ void rows_inv_c(const PcDesc& d, const ChanState* sst, int pair, int m, int cur,
+                                           float2* pcsh, double* red) {
+  switch (d.g.c) {
+    case 4: rows_inv<4, MIXED, TH>(d, sst, pair, m, cur, pcsh, red); break;
+    case 3: rows_inv<3, MIXED, TH>(d, sst, pair, m, cur, pcsh, red); break;
+    case 2: rows_inv<2, MIXED, TH>(d, sst, pair, m, cur, pcsh, red); break;
+    default: rows_inv<1, MIXED, TH>(d, sst, pair, m, cur, pcsh, red); break;
+  }
+}
+
+template <bool MIXED, int TH>
+__global__ __launch_bounds__(TH) void k_pc_rows_inv(const PcDesc* __restrict__ t, int count,
                                                    const ChanState* __restrict__ st, int cur) {
   extern __shared__ float2 pcsh[];
-  __shared__ double red[2 * kPcWaves];
+  __shared__ double red[2 * (TH / 64)];
   const int si = find_pc(t, count, (int)blockIdx.x, [](const PcDesc& d) { return d.row_block0; });
   const PcDesc& d = t[si];
   const Geom& g = d.g;
@@ -829,12 +858,8 @@ __global__ __launch_bounds__(T) void k_pc_rows_inv(const PcDesc* __restrict__ t,
   const int pair = local / g.h, m = local - pair * g.h;
   const ChanState* sst = st + d.band0;
   if (!band_runs(sst, 2 * pair, g.N) && !band_runs(sst, 2 * pair + 1, g.N)) return;
-  switch (g.c) {
-    case 4: rows_inv<4, MIXED>(d, sst, pair, m, cur, pcsh, red); break;
-    case 3: rows_inv<3, MIXED>(d, sst, pair, m, cur, pcsh, red); break;
-    case 2: rows_inv<2, MIXED>(d, sst, pair, m, cur, pcsh, red); break;
-    default: rows_inv<1, MIXED>(d, sst, pair, m, cur, pcsh, red); break;
-  }
+  if (MIXED && d.mixed_w) rows_inv_c<true, TH>(d, sst, pair, m, cur, pcsh, red);
+  else rows_inv_c<false, TH>(d, sst, pair, m, cur, pcsh, red);
 }
 
 // --------------------------------------------------------------------------------------------- mbar ---
@@ -986,13 +1011,17 @@ void pc_fill(PcDesc& d, const Geom& g, float* tw_dev) {
   d.twW = tw + g.h + g.w + g.H;
   d.nrw = pc_radices(g.w, d.rw);
   d.nrh = pc_radices(g.h, d.rh);
+  d.mixed_w = pc_small_radix(g.w);
+  d.mixed_h = pc_small_radix(g.h);
 }
 
 hipError_t pc_prepare() {
   const int bytes = kPcMaxLds;
-  const void* kernels[6] = {(const void*)k_pc_rows<false>,     (const void*)k_pc_rows<true>,
-                            (const void*)k_pc_cols<false>,     (const void*)k_pc_cols<true>,
-                            (const void*)k_pc_rows_inv<false>, (const void*)k_pc_rows_inv<true>};
+  const void* kernels[10] = {(const void*)k_pc_rows<false, T>,      (const void*)k_pc_rows<true, T>,
+                             (const void*)k_pc_rows<false, TS>,     (const void*)k_pc_rows<true, TS>,
+                             (const void*)k_pc_cols<false>,         (const void*)k_pc_cols<true>,
+                             (const void*)k_pc_rows_inv<false, T>,  (const void*)k_pc_rows_inv<true, T>,
+                             (const void*)k_pc_rows_inv<false, TS>, (const void*)k_pc_rows_inv<true, TS>};
   for (const void* k : kernels) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -1036,23 +1065,39 @@ void pc_plan(PcDesc* h_tab, int count, PcPlan* plan) {
     P.cus = 256;
   P.row_lds = pc_row_lds(h_tab, count);
   P.col_lds = pc_col_lds(h_tab, count);
-  for (int i = 0; i < count; ++i) P.mixed |= pc_small_radix(h_tab[i].g.w) || pc_small_radix(h_tab[i].g.h);
+  P.small_rows = true;
+  for (int i = 0; i < count; ++i) {
+    const Geom& g = h_tab[i].g;
+    P.mixed |= pc_small_radix(g.w) || pc_small_radix(g.h);
+    P.small_rows &= (size_t)g.c * g.c * g.w <= (size_t)kPcSmallElems;
+  }
   *plan = P;
 }
 
 hipError_t launch_pc_rows(int op, const PcDesc* t, const PcPlan& P, const ChanState* st, int prev, int cur,
                           hipStream_t s) {
   if (P.row_blocks <= 0) return hipSuccess;
-  if (P.mixed)
-    hipLaunchKernelGGL(k_pc_rows<true>, dim3(P.row_blocks), dim3(T), P.row_lds, s, op, t, P.count, st, prev, cur);
-  else
-    hipLaunchKernelGGL(k_pc_rows<false>, dim3(P.row_blocks), dim3(T), P.row_lds, s, op, t, P.count, st, prev, cur);
+  if (P.small_rows) {
+    if (P.mixed)
+      hipLaunchKernelGGL((k_pc_rows<true, TS>), dim3(P.row_blocks), dim3(TS), P.row_lds, s, op, t, P.count, st, prev,
+                         cur);
+    else
+      hipLaunchKernelGGL((k_pc_rows<false, TS>), dim3(P.row_blocks), dim3(TS), P.row_lds, s, op, t, P.count, st, prev,
+                         cur);
+  } else if (P.mixed) {
+    hipLaunchKernelGGL((k_pc_rows<true, T>), dim3(P.row_blocks), dim3(T), P.row_lds, s, op, t, P.count, st, prev, cur);
+  } else {
+    hipLaunchKernelGGL((k_pc_rows<false, T>), dim3(P.row_blocks), dim3(T), P.row_lds, s, op, t, P.count, st, prev,
+                       cur);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_pc_cols(int op, const PcDesc* t, const PcPlan& P, const ChanState* st, hipStream_t s) {
   if (P.col_blocks <= 0) return hipSuccess;
-  const int grid = std::max(1, std::min(P.col_blocks, P.cus));  // one persistent workgroup per compute unit
+  // persistent workgroups: as many per compute unit as its LDS holds (one for 1024-point columns at c = 4)
+  const int per_cu = std::max(1, std::min((int)(kPcCuLds / (P.col_lds + 1024)), 2048 / TC));
+  const int grid = std::max(1, std::min(P.col_blocks, P.cus * per_cu));
   if (P.mixed)
     hipLaunchKernelGGL(k_pc_cols<true>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st, P.col_blocks);
   else
@@ -1062,10 +1107,16 @@ hipError_t launch_pc_cols(int op, const PcDesc* t, const PcPlan& P, const ChanSt
 
 hipError_t launch_pc_rows_inv(const PcDesc* t, const PcPlan& P, const ChanState* st, int cur, hipStream_t s) {
   if (P.row_blocks <= 0) return hipSuccess;
-  if (P.mixed)
-    hipLaunchKernelGGL(k_pc_rows_inv<true>, dim3(P.row_blocks), dim3(T), P.row_lds, s, t, P.count, st, cur);
-  else
-    hipLaunchKernelGGL(k_pc_rows_inv<false>, dim3(P.row_blocks), dim3(T), P.row_lds, s, t, P.count, st, cur);
+  if (P.small_rows) {
+    if (P.mixed)
+      hipLaunchKernelGGL((k_pc_rows_inv<true, TS>), dim3(P.row_blocks), dim3(TS), P.row_lds, s, t, P.count, st, cur);
+    else
+      hipLaunchKernelGGL((k_pc_rows_inv<false, TS>), dim3(P.row_blocks), dim3(TS), P.row_lds, s, t, P.count, st, cur);
+  } else if (P.mixed) {
+    hipLaunchKernelGGL((k_pc_rows_inv<true, T>), dim3(P.row_blocks), dim3(T), P.row_lds, s, t, P.count, st, cur);
+  } else {
+    hipLaunchKernelGGL((k_pc_rows_inv<false, T>), dim3(P.row_blocks), dim3(T), P.row_lds, s, t, P.count, st, cur);
+  }
   return hipGetLastError();
 }
 
