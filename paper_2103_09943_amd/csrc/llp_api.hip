@@ -313,7 +313,7 @@ bool ctx_config(llp_ctx* ctx, const Geom& g, OpConfig* cfg, bool batched) {
 
 // The preconditioner's descriptor for the context's buffers (z the float32 iterate, s the output plane), its
 // twiddles, the kernel DFT and mbar: the per-scene set-up of the Fourier-domain passes.
-llp_status pc_setup(llp_ctx* ctx, const Geom& g, const float* kernel, float* z, float* sout, PcPlan* PP,
+llp_status pc_setup(llp_ctx* ctx, const Geom& g, const float* kernel, float* sout, PcPlan* PP,
                     hipStream_t s) {
   PcDesc& pd = *ctx->h_pc;
   memset(&pd, 0, sizeof(pd));
@@ -328,7 +328,6 @@ llp_status pc_setup(llp_ctx* ctx, const Geom& g, const float* kernel, float* z, 
   pd.p[0] = ctx->p[0];
   pd.p[1] = ctx->p[1];
   pd.q = ctx->q;
-  pd.z = z;
   pd.s = sout;
   pd.partials = ctx->partials;
   pd.pstride = (int)max_partials_per_band(g);
@@ -404,7 +403,7 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
   const int nb_dir = dir_ntiles(g, cfg), nb_apply = apply_ntiles(g, cfg);
   PcPlan PP;
   if (pc) {
-    v = pc_setup(ctx, g, kernel, hrms, ctx->s, &PP, s);
+    v = pc_setup(ctx, g, kernel, ctx->s, &PP, s);
     if (v != LLP_OK) return v;
     // s_0 = P^{-1} r_0, rho_0 = r_0^T s_0, p_0 = s_0, y = D B p_0
     HIP_TRY(launch_pc_rows(kPcRowsStart, ctx->d_pc, PP, ctx->st, 0, 0, s));
@@ -706,7 +705,7 @@ static llp_status fourier_apply(llp_ctx* ctx, const llp_shape* shape, const llp_
   HIP_TRY(launch_init(g, 1, ctx->b, ctx->r[0], ctx->st, stream));  // every band active; r untouched
   HIP_TRY(hipMemcpyAsync(ctx->r[0], z, NHW * sizeof(float), hipMemcpyDeviceToDevice, stream));
   PcPlan PP;
-  v = pc_setup(ctx, g, kernel, ctx->q, out, &PP, stream);
+  v = pc_setup(ctx, g, kernel, out, &PP, stream);
   if (v != LLP_OK) return v;
   HIP_TRY(launch_pc_rows(kPcRowsStart, ctx->d_pc, PP, ctx->st, 0, 0, stream));
   HIP_TRY(launch_pc_cols(op, ctx->d_pc, PP, ctx->st, stream));
@@ -751,7 +750,7 @@ llp_status llp_polish(llp_ctx* ctx, const llp_shape* shape, const llp_params* pa
   HIP_TRY(launch_pc_axpy(ctx->b, ctx->q, ctx->r[0], -1.0f, NHW, stream));  // r = b - A Z0
   HIP_TRY(launch_init(g, 1, ctx->b, ctx->r[0], ctx->st, stream));           // every band active; r untouched
   PcPlan PP;
-  v = pc_setup(ctx, g, kernel, ctx->q, ctx->s, &PP, stream);
+  v = pc_setup(ctx, g, kernel, ctx->s, &PP, stream);
   if (v != LLP_OK) return v;
   HIP_TRY(launch_pc_set_mbar(ctx->d_pc, 1, (double)((2 * g.r + 1) * (2 * g.r + 1)), stream));
   HIP_TRY(launch_pc_rows(kPcRowsStart, ctx->d_pc, PP, ctx->st, 0, 0, stream));

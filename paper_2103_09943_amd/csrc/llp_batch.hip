@@ -388,7 +388,6 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
           pd.p[j] = d.p[j];
         }
         pd.q = d.q;
-        pd.z = d.x;
         pd.s = sv;
         pd.partials = d.partials;
         pd.pstride = (int)max_partials_per_band(g);

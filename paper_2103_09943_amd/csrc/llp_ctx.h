@@ -81,7 +81,7 @@ void ref_plan(RefDesc* tab, int count, RefPlan* plan);
 llp_status ref_pass(const RefDesc* d_tab, const RefPlan& P, ChanState* st, double* results, int fin_op, int force,
                     int rpar, int write_r, int max_iters, float tol, int plain_cg, hipStream_t s);
 
-llp_status pc_setup(llp_ctx* ctx, const Geom& g, const float* kernel, float* z, float* sout, PcPlan* PP,
+llp_status pc_setup(llp_ctx* ctx, const Geom& g, const float* kernel, float* sout, PcPlan* PP,
                     hipStream_t s);
 
 // The whole single-scene solve with launch configuration cfg (the body of llp_pansharpen).

@@ -78,7 +78,7 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
   };
   const __amdgpu_buffer_rsrc_t Rr = rsrc(A.rin);
   const __amdgpu_buffer_rsrc_t Rq = rsrc(MODE == 2 ? A.qin : A.rin), Rp = rsrc(MODE >= 2 ? A.pin : A.rin);
-  const __amdgpu_buffer_rsrc_t Rro = rsrc(MODE == 2 ? A.rout : A.rin), Rx = rsrc(MODE == 2 ? A.x : A.rin);
+  const __amdgpu_buffer_rsrc_t Rro = rsrc(MODE == 2 ? A.rout : A.rin), Rx = rsrc(MODE >= 2 ? A.x : A.rin);
   const __amdgpu_buffer_rsrc_t Rpo = rsrc(MODE != 0 ? A.pout : A.rin);
 
   // Column offsets of this lane (the same for every row of the region).
@@ -114,7 +114,7 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
           if (MODE == 2) qv[j][ci] = ld(Rq, vld[ci], so[j]);
           if (MODE >= 2) pv[j][ci] = ld(Rp, vld[ci], so[j]);
         }
-        if (MODE == 2 && own_row) {
+        if (MODE >= 2 && own_row) {
 #pragma unroll
           for (int ci = 0; ci < NCI; ++ci) xv[j][ci] = ld(Rx, vown[ci], so[j]);
         }
@@ -141,6 +141,7 @@ __device__ __forceinline__ void dir_fast_body(const Geom& g, const DirArgs& A, c
             acc += (double)(vown[ci] != kNoAccess ? vv[ci] * vv[ci] : 0.0f);
           } else if (MODE == 3) {
             st(vv[ci], Rpo, vown[ci], so[j]);
+            st(fmaf(alpha, pv[j][ci], xv[j][ci]), Rx, vown[ci], so[j]);
           } else {
             const float rn = fmaf(-alpha, qv[j][ci], rv[j][ci]);
             st(rn, Rro, vown[ci], so[j]);

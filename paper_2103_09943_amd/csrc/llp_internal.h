@@ -82,7 +82,8 @@ hipError_t launch_rhs(const Geom& g, const float* X, const float* u, float* b, d
 hipError_t launch_init(const Geom& g, int from_init, const float* b, float* r, ChanState* st, hipStream_t s);
 // mode 0: y = D B z (z = rin).  mode 1: p_0 = r_0 (rin), y = D B p_0, partials of rho_0.  mode 2: the update
 // of iteration k (x, r from alpha; p from beta), y = D B p_k, partials of rho_k; final_step skips p and y.
-// mode 3 (preconditioned iteration): p_k = s_k (rin) + beta p_{k-1} (pin), y = D B p_k; no partials.
+// mode 3 (preconditioned iteration): p_k = s_k (rin) + beta p_{k-1} (pin), x += alpha p_{k-1}, y = D B p_k; no
+// partials.
 // Modes 1 and 2 are followed by launch_finalize(kFinDir, nblk = dir_ntiles) for the stopping rule of x_k.
 hipError_t launch_dir(const Geom& g, const OpConfig& cfg, int mode, int final_step, int k_iter, const float* rin,
                       const float* qin, const float* pin, float* rout, float* pout, float* x, float* y,
@@ -231,7 +232,6 @@ struct PcDesc {
   float* r[2];          // residual buffers (iteration k writes r[k & 1])
   float* p[2];          // direction buffers
   const float* q;       // A p of the current iteration
-  float* z;             // float32 part of the iterate
   float* s;             // preconditioned residual P^{-1} r [N][H][W]
   double* partials;     // [N][pstride][3]: slot 0 |r|^2, slot 1 r^T s, one per LR row
   int pstride;

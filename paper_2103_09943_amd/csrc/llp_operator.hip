@@ -75,8 +75,12 @@ __global__ __launch_bounds__(kBlock) void k_dir(Geom g, DirArgs A, const float* 
           acc += (double)v * v;
         }
       } else if (A.mode == 3) {
-        v = fmaf(beta, A.pin[off], A.rin[off]);
-        if (own) A.pout[off] = v;
+        const float pv = A.pin[off];
+        v = fmaf(beta, pv, A.rin[off]);
+        if (own) {
+          A.pout[off] = v;
+          A.x[off] = fmaf(alpha, pv, A.x[off]);
+        }
       } else {
         const float pv = A.pin[off];
         const float rn = fmaf(-alpha, A.qin[off], A.rin[off]);

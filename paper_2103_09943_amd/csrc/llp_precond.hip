@@ -537,8 +537,9 @@ __device__ __forceinline__ void stc(float* p, const float (&v)[C]) {
   }
 }
 // ------------------------------------------------------------------------------------------- row pass ---
-// op kPcRowsStart: the bands' residual r[prev] as it is; kPcRowsUpdate: r[cur] = r[prev] - alpha q and
-// z += alpha p[prev] first (the CG update of iteration k); kPcRowsKernel: the blur kernel embedded in an H x W
+// op kPcRowsStart: the bands' residual r[prev] as it is; kPcRowsUpdate: r[cur] = r[prev] - alpha q first (the
+// residual update of iteration k; the iterate's update z += alpha p is done by the direction kernel, which reads
+// p anyway); kPcRowsKernel: the blur kernel embedded in an H x W
 // plane with its centre tap at (0, 0), in band a of pair 0.  Partial sums of |r|^2 per band go to slot 0 of
 // the band's partials (one per LR row).  Each thread moves whole cells: the C x C pixels (c m + al, c n + be)
 // of LR pixel (m, n) on the way in, the c^2 spectral values of frequency (m, k2) on the way out.
@@ -582,17 +583,11 @@ __device__ __forceinline__ void rows_fwd(int op, const PcDesc& d, const ChanStat
           float rv[C];
           ldc<C>(d.r[prev] + o, rv);
           if (op == kPcRowsUpdate) {
-            float qv[C], pv[C], zv[C];
+            float qv[C];
             ldc<C>(d.q + o, qv);
-            ldc<C>(d.p[prev] + o, pv);
-            ldc<C>(d.z + o, zv);
 #pragma unroll
-            for (int k = 0; k < C; ++k) {
-              rv[k] = fmaf(-al, qv[k], rv[k]);
-              zv[k] = fmaf(al, pv[k], zv[k]);
-            }
+            for (int k = 0; k < C; ++k) rv[k] = fmaf(-al, qv[k], rv[k]);
             stc<C>(d.r[cur] + o, rv);
-            stc<C>(d.z + o, zv);
           }
           double ss = 0.0;
 #pragma unroll
