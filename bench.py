@@ -74,8 +74,8 @@ def bytes_model(kt, host, reps, precond):
       operator (k_apply / sweep):   read p, r, y (1/c^2 of a plane); write q          12 + 4/c^2 per active px-band
                                     plus the PAN statistics G, mu, dinv per launch   12 per pixel
       plain update (k_dir mode 2):  read r, q, p, x; write r, p, x, y                 28 + 4/c^2
-      direction (k_dir mode 3):     read s, p; write p, y                             12 + 4/c^2
-      rows (forward, with update):  read r, q, p, x; write r, x, the spectrum         28  (spectrum: 8 B per pixel pair)
+      direction (k_dir mode 3):     read s, p, x; write p, x, y                       20 + 4/c^2
+      rows (forward, with update):  read r, q; write r, the spectrum                  16  (spectrum: 8 B per pixel pair)
       columns (group solve):        read and write the spectrum, read U               12  (8 + 8 + 8 B per pixel pair)
       rows (inverse):               read the spectrum and r; write s                  12
     Per scene: px-band iterations = H W * sum of band iterations; operator launches with an active band = the
@@ -88,8 +88,8 @@ def bytes_model(kt, host, reps, precond):
         c2 = float(c * c)
         out["apply"] += (12.0 + 4.0 / c2) * HW * band_iters + 12.0 * HW * busy
         if precond:
-            out["dir"] += (12.0 + 4.0 / c2) * HW * band_iters
-            out["pc_rows"] += 28.0 * HW * band_iters
+            out["dir"] += (20.0 + 4.0 / c2) * HW * band_iters
+            out["pc_rows"] += 16.0 * HW * band_iters
             out["pc_cols"] += 12.0 * HW * band_iters
             out["pc_rows_inv"] += 12.0 * HW * band_iters
         else:
@@ -99,8 +99,8 @@ def bytes_model(kt, host, reps, precond):
 
 KERNEL_NAMES = {
     "apply": "operator q = A p (column sweep k_llp: B^T D^T y on matrix cores + lambda L^T M L p)",
-    "dir": "direction kernel k_dir_fast (p = s + beta p, y = D B p)",
-    "pc_rows": "k_pc_rows (r, x update; forward row transforms of the band pairs)",
+    "dir": "direction kernel k_dir_fast (p = s + beta p, x += alpha p, y = D B p)",
+    "pc_rows": "k_pc_rows (r update; forward row transforms of the band pairs)",
     "pc_cols": "k_pc_cols (column transforms, per-group solve of P, inverse column transforms)",
     "pc_rows_inv": "k_pc_rows_inv (inverse row transforms, s = P^-1 r, r^T s)",
 }

@@ -236,7 +236,8 @@ struct PcDesc {
   double* partials;     // [N][pstride][3]: slot 0 |r|^2, slot 1 r^T s, one per LR row
   int pstride;
   int band0;
-  int row_block0, col_block0;  // first workgroup of the scene in the row and column launches
+  int row_block0;             // first workgroup of the scene in the row launches
+  int col_block0;             // first LR column of the scene among the table's columns (the column pass)
   int nrw, nrh;                // radix passes of the length-w and length-h transforms
   int mixed_w, mixed_h;        // the length-w (length-h) transform needs a radix other than 8 and 4
   int rw[kPcMaxRad], rh[kPcMaxRad];

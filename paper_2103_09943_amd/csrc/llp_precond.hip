@@ -709,12 +709,14 @@ __device__ __forceinline__ void cols_body(int op, const PcDesc& d, int pair, int
       [&](int e, float2 v) { gst(sp + ((size_t)(e / C2) * w + k2) * C2 + e % C2, v); });
 }
 
-// Items lo .. hi - 1 of one scene (local index k2 npair + pair), the next item's column in flight while the
-// current one is transformed.
+// The items of one scene that this workgroup owns: the LR columns k2 = k0, k0 + G, k0 + 2G, ... (G workgroups)
+// and, per column, its band pairs with a running band (the pairs of a column follow each other, so U of the
+// column is reused from L2).  The next item's column is in flight while the current one is transformed.
 template <int C, bool MIXED>
-__device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanState* sst, int lo, int hi,
+__device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanState* sst, int k0, int G,
                                            float2* pcsh) {
   const int np = d.npair;
+  const int hi = (d.g.w - k0 + G - 1) / G * np;  // items: l = j np + pair for the j-th owned column
   auto runs = [&](int l) {
     const int pair = l % np;
     return op == kPcColsKernel ? pair == 0
@@ -725,48 +727,49 @@ __device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanSt
       if (runs(l)) break;
     return l;
   };
-  int l = next(lo);
+  auto col_of = [&](int l) { return k0 + (l / np) * G; };
+  int l = next(0);
   if (l >= hi) return;
   float2 pf[kColPf];
-  col_prefetch<C>(d, l % np, l / np, pf);
+  col_prefetch<C>(d, l % np, col_of(l), pf);
   __syncthreads();  // the LDS of a previous scene is no longer read
   const float2* twl = stage_twiddles<TC>(pcsh, C * C, d.g.h, d.twh);
   while (l < hi) {
     col_stage<C>(d, pf, pcsh);
     const int nx = next(l + 1);
-    if (nx < hi) col_prefetch<C>(d, nx % np, nx / np, pf);
+    if (nx < hi) col_prefetch<C>(d, nx % np, col_of(nx), pf);
     __syncthreads();
-    cols_body<C, MIXED>(op, d, l % np, l / np, pcsh, twl);
+    cols_body<C, MIXED>(op, d, l % np, col_of(l), pcsh, twl);
     __syncthreads();  // the LDS reads of this item are done
     l = nx;
   }
 }
 
 template <bool MIXED>
-__device__ __forceinline__ void cols_scene_c(int op, const PcDesc& d, const ChanState* sst, int lo, int hi,
+__device__ __forceinline__ void cols_scene_c(int op, const PcDesc& d, const ChanState* sst, int k0, int G,
                                              float2* pcsh) {
   switch (d.g.c) {
-    case 4: cols_scene<4, MIXED>(op, d, sst, lo, hi, pcsh); break;
-    case 3: cols_scene<3, MIXED>(op, d, sst, lo, hi, pcsh); break;
-    case 2: cols_scene<2, MIXED>(op, d, sst, lo, hi, pcsh); break;
-    default: cols_scene<1, MIXED>(op, d, sst, lo, hi, pcsh); break;
+    case 4: cols_scene<4, MIXED>(op, d, sst, k0, G, pcsh); break;
+    case 3: cols_scene<3, MIXED>(op, d, sst, k0, G, pcsh); break;
+    case 2: cols_scene<2, MIXED>(op, d, sst, k0, G, pcsh); break;
+    default: cols_scene<1, MIXED>(op, d, sst, k0, G, pcsh); break;
   }
 }
 
+// Persistent: workgroup b owns the columns b, b + G, b + 2G, ... of the table's columns (every scene's LR
+// columns one after another), so the scenes that still have running bands are spread over all workgroups.
 template <bool MIXED>
 __global__ __launch_bounds__(TC) void k_pc_cols(int op, const PcDesc* __restrict__ t, int count,
-                                               const ChanState* __restrict__ st, int nitems) {
+                                               const ChanState* __restrict__ st) {
   extern __shared__ float2 pcsh[];
-  const int per = (nitems + (int)gridDim.x - 1) / (int)gridDim.x;
-  const int i1 = min((int)blockIdx.x * per + per, nitems);
-  for (int it = (int)blockIdx.x * per; it < i1;) {
-    const PcDesc& d = t[find_pc(t, count, it, [](const PcDesc& x) { return x.col_block0; })];
-    const int end = min(i1, d.col_block0 + d.npair * d.g.w);
-    const int lo = it - d.col_block0, hi = end - d.col_block0;
+  const int G = (int)gridDim.x, b = (int)blockIdx.x;
+  for (int si = 0; si < count; ++si) {
+    const PcDesc& d = t[si];
+    const int k0 = ((b - d.col_block0) % G + G) % G;  // first owned column of the scene
+    if (k0 >= d.g.w) continue;
     const ChanState* sst = st + d.band0;
-    if (MIXED && d.mixed_h) cols_scene_c<true>(op, d, sst, lo, hi, pcsh);
-    else cols_scene_c<false>(op, d, sst, lo, hi, pcsh);
-    it = end;
+    if (MIXED && d.mixed_h) cols_scene_c<true>(op, d, sst, k0, G, pcsh);
+    else cols_scene_c<false>(op, d, sst, k0, G, pcsh);
   }
 }
 
@@ -956,7 +959,7 @@ bool pc_supported(const Geom& g) {
 }
 
 int pc_row_blocks(const Geom& g) { return ((g.N + 1) / 2) * g.h; }
-int pc_col_blocks(const Geom& g) { return ((g.N + 1) / 2) * g.w; }
+int pc_col_blocks(const Geom& g) { return g.w; }  // LR columns (the column pass takes every band pair of one)
 
 size_t pc_spec_floats(const Geom& g) { return (size_t)((g.N + 1) / 2) * g.H * g.W * 2; }
 size_t pc_uhat_floats(const Geom& g) { return (size_t)g.H * g.W * 2; }
@@ -1094,9 +1097,9 @@ hipError_t launch_pc_cols(int op, const PcDesc* t, const PcPlan& P, const ChanSt
   const int per_cu = std::max(1, std::min((int)(kPcCuLds / (P.col_lds + 1024)), 2048 / TC));
   const int grid = std::max(1, std::min(P.col_blocks, P.cus * per_cu));
   if (P.mixed)
-    hipLaunchKernelGGL(k_pc_cols<true>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st, P.col_blocks);
+    hipLaunchKernelGGL(k_pc_cols<true>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st);
   else
-    hipLaunchKernelGGL(k_pc_cols<false>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st, P.col_blocks);
+    hipLaunchKernelGGL(k_pc_cols<false>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st);
   return hipGetLastError();
 }
 

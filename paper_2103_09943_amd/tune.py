@@ -2,7 +2,8 @@
 
     python -m paper_2103_09943_amd.tune [--out PATH]
 
-Tunes the 8-band 2048^2 scene (r 2, 17 taps) and one synthetic scene of every (PAN side, kernel size) class of
+Tunes the 16-band 4096^2 scene of the large workload and the 8-band 2048^2 scene (r 2, 17 taps), and one
+synthetic scene of every (PAN side, kernel size) class of
 the batch workload (sides 256..1024 in steps of 128, 9..17 taps, r 1), each for single-scene solves and for
 batched solves (on a batch of copies of the scene).  The library keys the table by (c, n, r)
 and the image area in half-octaves, and refuses a table made on another architecture.
@@ -31,6 +32,8 @@ def main():
         return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
     jobs = []
+    sc, st = scenes.config_scene(4, 0)
+    jobs.append(("16x4096^2 n17 r2", sc, st))
     sc, st = scenes.config_scene(1, 0)
     jobs.append(("8x2048^2 n17 r2", sc, st))
     for side in range(256, 1025, 128):
