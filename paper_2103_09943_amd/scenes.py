@@ -66,6 +66,27 @@ def gaussian_kernel(n: int, sigma_x: float, sigma_y: float | None = None, theta:
     return g / g.sum()
 
 
+def motion_blur_kernel(R: int, sigma: float, d: float, theta: float, cx: float = 0.0, cy: float = 0.0) -> np.ndarray:
+    """Unit-gain (2R+1) x (2R+1) blur kernel of eq. (blur_kernel_final): the isotropic Gaussian of eq.
+    (gaussian_blur) convolved with the d-wide motion blur of eq. (motion_blur) along direction theta, peak at
+    (cx, cy), sampled at the integer offsets (App. B, steps I-III), float64.  Index [a][b] is the offset
+    (y, x) = (a - R, b - R).  d = 0 gives the Gaussian itself."""
+    n = 2 * R + 1
+    yy, xx = np.mgrid[-R:R + 1, -R:R + 1].astype(np.float64)
+    ct, st = math.cos(theta), math.sin(theta)
+    xp = (xx - cx) * ct + (yy - cy) * st     # along the motion
+    yp = -(xx - cx) * st + (yy - cy) * ct    # across it
+    if d > 0:
+        def cdf(x):
+            return 0.5 * (1.0 + np.vectorize(math.erf)(x / (sigma * math.sqrt(2.0))))
+        along = (cdf(xp + d / 2) - cdf(xp - d / 2)) / d
+    else:
+        along = np.exp(-0.5 * (xp / sigma) ** 2)
+    g = along * np.exp(-0.5 * (yp / sigma) ** 2)
+    assert g.shape == (n, n)
+    return g / g.sum()
+
+
 def _ellipse_layer(rng, H, W, n_ellipses):
     """Geometry of the shared ellipses: list of (rows, cols, mask)."""
     out = []
