@@ -34,3 +34,4 @@ from .llp import (  # noqa: F401
 from . import polish  # noqa: F401,E402  (the A, C step and the Z step of Algorithm "Fast Pansharpening")
 from . import tgv  # noqa: F401,E402  (Algorithm "Blur Kernel Estimation", host side)
 from . import lgc  # noqa: F401,E402  (the LGC prior of eq. reg2_lgc, the comparison prior)
+from . import priors  # noqa: F401,E402  (the filter priors of the cross-channel prior comparison)
