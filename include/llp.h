@@ -314,6 +314,34 @@ llp_status llp_objective(llp_ctx* ctx, const llp_shape* shape, const llp_params*
                          const float* pan, const float* kernel, const float* z, double* obj,
                          hipStream_t stream);
 
+/* ---- Filter priors of the cross-channel prior comparison ---------------------------------------------- */
+
+/* The priors Sec. IV compares with LLP (Table "cross_channel_prior"): the window penalty of eq. (reg2) on F Z
+ * and F Y for other filters F in place of the Laplacian.  LLP: the 5-point Laplacian of eq. (reg2); LGC: the
+ * horizontal and vertical gradients of eq. (reg2_lgc), two filters (forward differences; the orientation does
+ * not change the operator); LPP: the identity (the pixels); LPF: the blur kernel u; HPF: delta - u.  Each
+ * filter d contributes lambda F_d^T M_{F_d Y} F_d, M the matting matrix of eq. (matting_matrix) with the guide
+ * F_d Y, so every band solves (B^T D^T D B + lambda sum_d F_d^T M_{F_d Y} F_d) Z = B^T D^T X. */
+typedef enum { LLP_PRIOR_LLP = 0, LLP_PRIOR_LGC = 1, LLP_PRIOR_LPP = 2, LLP_PRIOR_LPF = 3, LLP_PRIOR_HPF = 4 } llp_prior;
+
+/* out = lambda sum_d F_d^T M_{F_d Y} F_d z (+ B^T D^T D B z if data_term != 0) for every band of z.
+ * pan [H][W], kernel [n][n], z, out [N][H][W] device, 16-byte aligned, must not alias.  The filter side (n for
+ * LPF and HPF) must be <= 31 and the operator's tile must fit in LDS with it (LLP_E_UNSUPPORTED otherwise:
+ * n <= 17 at r = 2).  Asynchronous on `stream`. */
+llp_status llp_apply_prior(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, int prior,
+                           const float* pan, const float* kernel, const float* z, float* out, int data_term,
+                           hipStream_t stream);
+
+/* llp_pansharpen with the prior `prior`: plain conjugate gradients (precond must be 0; init_mode 0 or 1, else
+ * LLP_E_UNSUPPORTED) on float32 vectors with FP64 dot products.  With tol > 0 a band whose CG residual meets
+ * tol ||b|| has its residual recomputed as b - A Z (the float32 operator, FP64 sum); it stops if that meets the
+ * tolerance too, else CG restarts from that residual.  The report's true_rel_residual (and out_rel_residual)
+ * is that recomputed residual of the returned Z; objective is NaN.  Same buffers and rules as llp_pansharpen;
+ * synchronizes the stream. */
+llp_status llp_prior_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_params* params, int prior,
+                                const float* lrms, const float* pan, const float* kernel, const float* init,
+                                float* hrms, llp_report* rep, hipStream_t stream);
+
 /* ---- Kernel timing -------------------------------------------------------------------------------------- */
 
 typedef struct {

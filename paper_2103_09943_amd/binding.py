@@ -79,6 +79,10 @@ _SIGS = {
                                               _vp]),
     "llp_polish": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp]),
     "llp_apply_A_noalloc": (ctypes.c_int, [ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp]),
+    "llp_apply_prior": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), ctypes.c_int, _vp, _vp,
+                                       _vp, _vp, ctypes.c_int, _vp]),
+    "llp_prior_pansharpen": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), ctypes.c_int, _vp,
+                                            _vp, _vp, _vp, _vp, ctypes.POINTER(Report), _vp]),
     "llp_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "llp_get_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
     "llp_objective": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
@@ -109,6 +113,7 @@ BATCH_SERIAL = 2
 BATCH_AUTOTUNE = 4
 CNN_PARAMS = 28641
 INIT_ZERO, INIT_USER, INIT_NET, INIT_NET_REJECTED = 0, 1, 2, 3
+PRIORS = {"llp": 0, "lgc": 1, "lpp": 2, "lpf": 3, "hpf": 4}  # llp_prior
 
 
 def lib() -> ctypes.CDLL:
@@ -381,6 +386,37 @@ class Context:
         out = torch.empty_like(z0)
         _check(lib().llp_polish(self._h, ctypes.byref(shp), ctypes.byref(prm), _ptr(lrms), _ptr(pan), _ptr(kernel),
                                 _ptr(z0), _ptr(out), _stream(stream)), "llp_polish")
+        return out
+
+    def prior_pansharpen(self, prior: str, lrms, pan, kernel, *, r: int, lam: float, eps: float, max_iters: int,
+                         tol: float = 0.0, init=None, out=None, report: bool = True, stream=None,
+                         allow_not_converged: bool = True):
+        """Solve every band under one of the compared priors (llp_prior_pansharpen).  Returns (hrms, reports,
+        status)."""
+        import torch
+        shp = shape_of(lrms, pan, kernel)
+        H, W = pan.shape
+        if out is None:
+            out = torch.empty((shp.N, H, W), dtype=torch.float32, device=lrms.device)
+        prm = Params(int(r), float(lam), float(eps), int(max_iters), float(tol), 1 if init is not None else 0, 0)
+        reps = (Report * shp.N)() if report else None
+        st = lib().llp_prior_pansharpen(self._h, ctypes.byref(shp), ctypes.byref(prm), PRIORS[prior], _ptr(lrms),
+                                        _ptr(pan), _ptr(kernel), _ptr(init), _ptr(out), reps, _stream(stream))
+        allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        _check(st, "llp_prior_pansharpen", allow)
+        return out, ([rp.as_dict() for rp in reps] if report else None), st
+
+    def apply_prior(self, prior: str, z, pan, kernel, *, c: int, r: int, lam: float, eps: float,
+                    data_term: bool = False, stream=None):
+        """lambda sum_d F_d^T M_d F_d z (+ B^T D^T D B z) under one of the compared priors (llp_apply_prior)."""
+        import torch
+        N, H, W = z.shape
+        shp = Shape(N, H // c, W // c, c, kernel.shape[0])
+        prm = Params(int(r), float(lam), float(eps), 0, 0.0, 0)
+        out = torch.empty_like(z)
+        _check(lib().llp_apply_prior(self._h, ctypes.byref(shp), ctypes.byref(prm), PRIORS[prior], _ptr(pan),
+                                     _ptr(kernel), _ptr(z), _ptr(out), int(bool(data_term)), _stream(stream)),
+               "llp_apply_prior")
         return out
 
     def apply_data(self, z, kernel, *, c: int, r: int, stream=None):

@@ -602,6 +602,7 @@ void llp_destroy(llp_ctx* ctx) {
   if (ctx->bev_in) (void)hipEventDestroy(ctx->bev_in);
   if (ctx->bstream) (void)hipStreamDestroy(ctx->bstream);
   cnn_free(ctx->cnn);
+  if (ctx->prior_ws) (void)hipFree(ctx->prior_ws);
   delete ctx;
 }
 

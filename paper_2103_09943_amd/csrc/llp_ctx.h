@@ -153,4 +153,7 @@ struct llp_ctx {
   // launch configurations chosen by the autotuner (llp_autotune), by geometry class
   std::vector<llp::host::TuneEntry> tuned;
   llp::host::CnnState* cnn = nullptr;  // warm-start network (llp_cnn_set_weights)
+  // filter priors (llp_prior_pansharpen, llp_apply_prior): guides, statistics, taps, restart flags
+  void* prior_ws = nullptr;
+  size_t prior_bytes = 0;
 };
