@@ -11,7 +11,8 @@ call from Z = 0 (the metric's plain leg), `config.cg_cold_value` the unprecondit
 
 Other workloads (--workload): `scene` (one 8-band 2048^2 scene, r 2; value from Z = 0), `batch` (64 scenes of
 PAN side 256..1024, 4 or 8 bands, r 1; value from Z = 0), `warmstart` (500 held-out 8-band 512^2 scenes, network
-start vs Z = 0).
+start vs Z = 0), `priors` (the `scene` input solved under the compared priors of the paper's prior comparison:
+value = the LGC prior to tol 1e-6 from Z = 0; HPF likewise, LLP/LPP/LPF at a fixed iteration count as legs).
 
 Prints one JSON line.  `roofline` is the kernel class with the most device time in one separately profiled step
 (HIP events around every launch on the solver's stream; the timed steps carry no events): its algorithmic HBM
@@ -40,6 +41,7 @@ WORKLOADS = {
     "scene": (1, range(1), None, None),
     "batch": (2, range(64), None, None),
     "warmstart": (3, range(2000, 2500), "cnn", None),
+    "priors": (1, range(1), None, None),
 }
 
 
@@ -189,6 +191,8 @@ def main():
     from paper_2103_09943_amd import scenes
     from paper_2103_09943_amd.tune import DEFAULT_PATH
 
+    if args.workload == "priors":
+        return run_priors(args)
     config, ids, init, _ = WORKLOADS[args.workload]
     ids = list(ids)[: args.scenes] if args.scenes else list(ids)
     t0 = time.time()
@@ -313,6 +317,154 @@ def main():
         log("CPU baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(host, reps, st, args.cpu_seconds, net)
     print(json.dumps(line), flush=True)
+
+
+def prior_bytes_model(kind, HW, c, reps):
+    """Algorithmic HBM bytes of the prior solve's kernel classes over one call (float32 planes):
+      operator (k_prior_apply):    read p, r, y (1/c^2 of a plane); write q          12 + 4/c^2 per active px-band
+                                   plus per filter its guide, window means, dinv    12 per pixel and launch
+      plain update (k_dir mode 2): read r, q, p, x; write r, p, x, y                 28 + 4/c^2"""
+    nf = 2 if kind == "lgc" else 1
+    band_iters = sum(r["iters"] for r in reps)
+    busy = max(r["iters"] for r in reps)
+    c2 = float(c * c)
+    return {"apply": (12.0 + 4.0 / c2) * HW * band_iters + 12.0 * nf * HW * busy,
+            "dir": (28.0 + 4.0 / c2) * HW * band_iters}
+
+
+def run_priors(args):
+    """The `priors` workload: one 8-band 2048^2 scene (x4, 17-tap blur, r 2) under the compared priors."""
+    import numpy as np
+    import torch
+
+    from paper_2103_09943_amd import binding as B
+    from paper_2103_09943_amd import scenes
+
+    sc, st = scenes.config_scene(1, 0)
+    ds = (torch.from_numpy(sc.X).cuda(), torch.from_numpy(sc.Y).cuda(), torch.from_numpy(sc.u).cuda())
+    N, H, W = sc.X.shape[0], sc.Y.shape[0], sc.Y.shape[1]
+    pxb = N * H * W
+    out = torch.empty((N, H, W), dtype=torch.float32, device="cuda")
+    ctx = B.Context(0)
+    kw = dict(r=st.r, lam=st.lam, eps=st.eps, out=out)
+
+    def timed(kind, steps, **k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            _, reps, status = ctx.prior_pansharpen(kind, *ds, **kw, **k)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps, reps, status
+
+    tolkw = dict(max_iters=st.max_iters, tol=st.tol)
+    for i in range(args.warmup):
+        ctx.prior_pansharpen("lgc", *ds, **kw, **tolkw)
+        log(f"warm-up step {i + 1}/{args.warmup} done")
+    step_s, reps, status = timed("lgc", args.steps, **tolkw)
+    log(f"timed {args.steps} step(s): {step_s * 1e3:.1f} ms per step")
+    iters = [r["iters"] for r in reps]
+    cfg = {
+        "workload": f"1 scene of 8 bands, PAN 2048x2048, LRMS 512x512 (x4), Gaussian blur of 17 taps, r={st.r}, "
+                    f"lambda={st.lam}, eps={st.eps}; the LGC prior (eq. reg2_lgc) in place of LLP, tol={st.tol} on "
+                    f"the float32-operator residual; {pxb / 1e6:.1f} Mpixel*bands per step",
+        "solver": "plain conjugate gradients, float32 vectors, FP64 dot products, true-residual check and restart",
+        "start": "Z = 0",
+        "status": status,
+        "iters_min_mean_max": [min(iters), round(float(np.mean(iters)), 1), max(iters)],
+        "max_true_rel_residual": max(r["true_rel_residual"] for r in reps),
+    }
+    roofline = None
+    if not args.no_legs:
+        legs = {}
+        s_h, r_h, st_h = timed("hpf", 1, **tolkw)
+        legs["hpf"] = {"value": round(pxb / s_h / 1e6, 3), "ms": round(s_h * 1e3, 1), "status": st_h,
+                       "iters_max": max(r["iters"] for r in r_h)}
+        K = 20
+        for kind in ("llp", "lpp", "lpf"):  # residual floors of the float32 operator above 1e-6: fixed count
+            s_k, r_k, _ = timed(kind, 1, max_iters=K, tol=0.0)
+            legs[kind] = {"ms_per_iteration": round(s_k / K * 1e3, 2), "iters": K}
+        s_l, _, _ = timed("lgc", 1, max_iters=K, tol=0.0)
+        legs["lgc"] = {"ms_per_iteration": round(s_l / K * 1e3, 2), "iters": K}
+        cfg["legs"] = legs
+        ctx.set_profiling(True)
+        ctx.kernel_times(reset=True)
+        _, preps, _ = ctx.prior_pansharpen("lgc", *ds, **kw, **tolkw)
+        kt = ctx.kernel_times(reset=True)
+        ctx.set_profiling(False)
+        model = prior_bytes_model("lgc", H * W, sc.c, preps)
+        per = {}
+        for k in model:
+            ms, n = kt[f"{k}_ms"], kt[f"{k}_launches"]
+            if ms > 0 and n > 0:
+                per[k] = dict(gbs=model[k] / (ms * 1e-3) / 1e9, ms=ms, n=n)
+        for k, v in per.items():
+            cfg[f"{k}_gbs"] = round(v["gbs"], 1)
+            cfg[f"{k}_avg_us"] = round(v["ms"] / v["n"] * 1e3, 1)
+        dom = max(per, key=lambda k: per[k]["ms"])
+        d = per[dom]
+        roofline = {
+            "bound": "hbm",
+            "kernel": {"apply": "k_prior_apply<3, 2> (q = A p under LGC: two gradient filters, window sums in LDS, "
+                                "B^T D^T y, CG dot products)",
+                       "dir": "k_dir_fast (x, r, p update and D B p)"}[dom],
+            "achieved": round(d["gbs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(d["ms"] / d["n"] * 1e3, 1),
+            "traffic": None,
+        }
+    ctx.close()
+    line = {
+        "metric": METRIC,
+        "value": round(pxb / step_s / 1e6, 3),
+        "unit": "Mpixel*bands/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": cfg,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline_priors(sc, st, reps)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_priors(sc, st, reps):
+    """FP64 oracle (oracle/priors.py) on a bounded sample: the LGC scene set-up and one product with A for one
+    band at full size, extrapolated to every band at the GPU's iteration counts."""
+    import numpy as np
+    import oracle
+    from oracle import priors
+
+    t0 = time.perf_counter()
+    prob = priors.PriorProblem("lgc", u=sc.u, c=sc.c, Y=sc.Y, r=st.r, lam=float(np.float32(st.lam)),
+                               eps=float(np.float32(st.eps)))
+    b = oracle.rhs(sc.X[:1], prob)
+    t_setup = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    priors.apply_A_prior(b, prob)
+    t_iter = time.perf_counter() - t1
+    N = sc.X.shape[0]
+    band_iters = sum(r["iters"] for r in reps)
+    t_solve = t_setup + t_iter * band_iters
+    pxb = N * sc.Y.size
+    return {
+        "value": pxb / t_solve / 1e6,
+        "unit": "Mpixel*bands/s",
+        "cores": os.cpu_count(),
+        "kind": "oracle",
+        "sample": f"LGC scene set-up plus one product with A of one band at {sc.Y.shape[0]}x{sc.Y.shape[1]}, FP64 "
+                  f"numpy/scipy; extrapolated to {N} bands at the GPU's {band_iters} band-iterations "
+                  f"({t_setup:.1f} s set-up, {t_iter:.1f} s per band-iteration)",
+    }
 
 
 def describe(name, host, st, pxb):

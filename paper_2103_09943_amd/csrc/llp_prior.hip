@@ -32,6 +32,8 @@ constexpr int kPriorMaxSide = 31;  // longest filter side
 constexpr int kPriorTapStride = kPriorMaxSide * kPriorMaxSide;
 constexpr int kPriorTW = 64;
 constexpr int kPriorFlat = kBlock * 16;  // elements per workgroup of the flat kernels
+constexpr int kStageBatch = 8;           // loads a thread keeps in flight while staging a region
+constexpr int kPB = 512, kPW = kPB / 64;  // k_prior_apply: threads and waves per workgroup
 
 __host__ __device__ inline int prior_th(int c) { return c == 3 ? 24 : 16; }  // tile rows (tile count <= the
                                                                              // operator's, for the partials)
@@ -52,7 +54,8 @@ struct PriorArgs {
   ChanState* st;
   int TH, tiles_x, ntiles, pstride;
   int E;  // halo of the staged p: 2 max(RF) + 2r
-  int offL, offX, offH, offA, offQ, offY, YW;
+  int offL, offX, offG, offH, offA, offQ, offY, offT, offU, offR, YW;
+  int FT, RW;  // kernel instance: compile-time filter side (1, 3) and window radius (1, 2), or 0
 };
 
 }  // namespace
@@ -129,150 +132,204 @@ __global__ __launch_bounds__(kBlock) void k_prior_wstats(Geom g, const double* _
 }
 
 // q = B^T D^T y + lambda sum_d F_d^T M_d F_d p on one tile of one band (and the CG partials in mode 1).
-__global__ __launch_bounds__(kBlock) void k_prior_apply(Geom g, PriorArgs A, const float* __restrict__ u) {
+// FT: the filter side at compile time (1 or 3; taps in registers), 0: any side (taps staged in LDS); RW: the
+// window radius at compile time (1, 2), 0: any.  Every global
+// read is staged into LDS up front (p, then per filter its guide, window means and inverse denominators), so the
+// stages run on LDS only; tiles whose halo stays inside the image index without wrapping.
+template <int FT, int RW>
+__global__ __launch_bounds__(kPB) void k_prior_apply(Geom g, PriorArgs A, const float* __restrict__ u) {
   extern __shared__ float smem[];
-  __shared__ double red[3 * kWaves];
+  __shared__ double red[3 * kPW];
   int tile, ch;
   tile_and_band(A.ntiles, g.N, blockIdx.x, tile, ch);
   if (A.mode == 1 && !A.st[ch].active) return;
   const int TH = A.TH, TW = kPriorTW;
   const int i0 = (tile / A.tiles_x) * TH, j0 = (tile % A.tiles_x) * TW;
-  const int H = g.H, W = g.W, r = g.r, C = g.c, R = g.R, n = g.n;
+  const int H = g.H, W = g.W, r = RW > 0 ? RW : g.r, C = g.c, R = g.R, n = g.n;
   const size_t HW = (size_t)H * W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int E = A.E, PH = TH + 2 * E, PW = TW + 2 * E;
+  const bool wrapped = i0 - E < 0 || j0 - E < 0 || i0 + TH + E > H || j0 + TW + E > W;
   float* P = smem;
   float* Ls = smem + A.offL;
   float* Xs = smem + A.offX;
+  float* Gs = smem + A.offG;
   float* Hs = smem + A.offH;
   float* As = smem + A.offA;
   float* Q = smem + A.offQ;
   float* Ys = smem + A.offY;
+  float* Ts = smem + A.offT;
   const float* pc = A.p + (size_t)ch * HW;
+  // rows*cols region with top-left global pixel (gi0, gj0), periodic, from plane src into dst (row stride cols).
+  // Every thread issues kStageBatch loads (clamped, unconditional) before it stores any, so the loads of a batch
+  // are in flight together.
+  auto stage = [&](float* dst, const float* src, int gi0, int gj0, int rows, int cols) {
+    const int total = rows * cols;
+    const float inv = 1.0f / (float)cols;
+    for (int base = threadIdx.x; base < total; base += kStageBatch * kPB) {
+      float v[kStageBatch];
+#pragma unroll
+      for (int k = 0; k < kStageBatch; ++k) {
+        const int e = min(base + k * kPB, total - 1);
+        const int row = __float2int_rz(((float)e + 0.5f) * inv), col = e - row * cols;
+        const int gi = gi0 + row, gj = gj0 + col;
+        v[k] = wrapped ? src[(size_t)wrapi(gi, H) * W + wrapi(gj, W)] : src[(size_t)gi * W + gj];
+      }
+#pragma unroll
+      for (int k = 0; k < kStageBatch; ++k)
+        if (base + k * kPB < total) dst[base + k * kPB] = v[k];
+    }
+  };
 
-  // Stage p on [i0-E, i0+TH+E) x [j0-E, j0+TW+E) (periodic), the LR y the tile's B^T D^T taps reach, and
-  // clear the accumulator.
-  for (int row = wave; row < PH; row += kWaves) {
-    const size_t ro = (size_t)wrapi(i0 - E + row, H) * W;
-    for (int col = lane; col < PW; col += 64) P[row * PW + col] = pc[ro + wrapi(j0 - E + col, W)];
-  }
+  // body(row, col) over a rows x cols region, the elements dealt to the threads in row-major order (regions
+  // are a little wider than 64 columns, so row-by-row loops would leave most lanes idle on every second pass).
+  auto flat = [&](int rows, int cols, auto&& body) {
+    const int total = rows * cols;
+    const float inv = 1.0f / (float)cols;
+    for (int e = threadIdx.x; e < total; e += kPB) {
+      const int row = __float2int_rz(((float)e + 0.5f) * inv);
+      body(row, e - row * cols);
+    }
+  };
+
+  // p on [i0-E, i0+TH+E) x [j0-E, j0+TW+E), the LR y the tile's B^T D^T taps reach, a cleared accumulator.
+  stage(P, pc, i0 - E, j0 - E, PH, PW);
   const int mlo = floor_div(i0 - R, C), klo = floor_div(j0 - R, C);
   const int YH = (TH - 1 + 2 * R) / C + 2, YW = A.YW;
   {
     const float* yc = A.y + (size_t)ch * g.h * g.w;
-    for (int row = wave; row < YH; row += kWaves) {
+    for (int row = wave; row < YH; row += kPW) {
       const size_t ro = (size_t)wrapi(mlo + row, g.h) * g.w;
       for (int col = lane; col < YW; col += 64) Ys[row * YW + col] = yc[ro + wrapi(klo + col, g.w)];
     }
   }
-  for (int e = threadIdx.x; e < TH * TW; e += kBlock) Q[e] = 0.0f;
-  __syncthreads();
+  for (int e = threadIdx.x; e < TH * TW; e += kPB) Q[e] = 0.0f;
+  float* Rs = smem + A.offR;  // r on the tile (mode 1: r^T q)
+  if (A.mode == 1) stage(Rs, A.r + (size_t)ch * HW, i0, j0, TH, TW);
+  float* Us = smem + A.offU;  // the blur kernel: lanes of a wave sit on different phases and read different taps
+  for (int e = threadIdx.x; e < n * n; e += kPB) Us[e] = u[e];
 
   const float nwf = (float)((2 * r + 1) * (2 * r + 1)), inv_nw = 1.0f / nwf;
   for (int d = 0; d < A.nf; ++d) {
-    const int F = A.F[d], RF = (F - 1) / 2;
+    const int F = FT > 0 ? FT : A.F[d], RF = (F - 1) / 2;
     const float* f = A.taps + d * kPriorTapStride;
-    const float* Gd = A.G[d];
-    const float* MUd = A.MU[d];
-    const float* DId = A.DI[d];
     const int LH = TH + 2 * (RF + 2 * r), LW = TW + 2 * (RF + 2 * r);
     const int AH = TH + 2 * (RF + r), AW = TW + 2 * (RF + r);
     const int MH = TH + 2 * RF, W3 = TW + 2 * RF;
     const int off = E - (RF + 2 * r);  // P index of l-space (0, 0) before the tap shift
+    float tp[FT > 0 ? FT * FT : 1];
+    if (FT > 0) {
+#pragma unroll
+      for (int t = 0; t < (FT > 0 ? FT * FT : 1); ++t) tp[t] = f[t];
+    } else {
+      for (int t = threadIdx.x; t < F * F; t += kPB) Ts[t] = f[t];
+    }
+    // the filter's guide on l-space, its window means and inverse denominators on a-space (into the a, b slots)
+    float* Aa = As;
+    float* Ab = As + AH * AW;
+    stage(Gs, A.G[d], i0 - RF - 2 * r, j0 - RF - 2 * r, LH, LW);
+    stage(Aa, A.MU[d], i0 - RF - r, j0 - RF - r, AH, AW);
+    stage(Ab, A.DI[d], i0 - RF - r, j0 - RF - r, AH, AW);
+    __syncthreads();
 
     // l = F p and G l on l-space [i0-RF-2r, ..) x [j0-RF-2r, ..): l(x) = sum_{a,b} f[a][b] p(x - (a-RF, b-RF)).
-    for (int row = wave; row < LH; row += kWaves) {
-      const size_t gro = (size_t)wrapi(i0 - RF - 2 * r + row, H) * W;
-      for (int col = lane; col < LW; col += 64) {
+    flat(LH, LW, [&](int row, int col) {
         const float* pb = P + (row + off + RF) * PW + col + off + RF;
         float s = 0.0f;
-        for (int a = 0; a < F; ++a) {
-          const float* pr = pb - a * PW;
-          for (int b = 0; b < F; ++b) s = fmaf(f[a * F + b], pr[-b], s);
+        if (FT > 0) {
+#pragma unroll
+          for (int a = 0; a < (FT > 0 ? FT : 1); ++a)
+#pragma unroll
+            for (int b = 0; b < (FT > 0 ? FT : 1); ++b) s = fmaf(tp[a * FT + b], pb[-a * PW - b], s);
+        } else {
+          for (int a = 0; a < F; ++a) {
+            const float* pr = pb - a * PW;
+            const float* fr = Ts + a * F;
+            for (int b = 0; b < F; ++b) s = fmaf(fr[b], pr[-b], s);
+          }
         }
         Ls[row * LW + col] = s;
-        Xs[row * LW + col] = Gd[gro + wrapi(j0 - RF - 2 * r + col, W)] * s;
-      }
-    }
+        Xs[row * LW + col] = Gs[row * LW + col] * s;
+    });
     __syncthreads();
     // Horizontal window sums of l and G l, a-space columns.
     float* Hl = Hs;
     float* Hg = Hs + LH * AW;
-    for (int row = wave; row < LH; row += kWaves) {
-      for (int col = lane; col < AW; col += 64) {
+    flat(LH, AW, [&](int row, int col) {
         const float* lr = Ls + row * LW + col;
         const float* gr = Xs + row * LW + col;
         float s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
         for (int t = 0; t <= 2 * r; ++t) {
           s1 += lr[t];
           s2 += gr[t];
         }
         Hl[row * AW + col] = s1;
         Hg[row * AW + col] = s2;
-      }
-    }
+    });
     __syncthreads();
-    // Vertical sums: the window coefficients a = (mean(G l) - mu mean(l)) dinv and b = mean(l) - a mu.
-    float* Aa = As;
-    float* Ab = As + AH * AW;
-    for (int row = wave; row < AH; row += kWaves) {
-      const size_t gro = (size_t)wrapi(i0 - RF - r + row, H) * W;
-      for (int col = lane; col < AW; col += 64) {
+    // Vertical sums: the window coefficients a = (mean(G l) - mu mean(l)) dinv and b = mean(l) - a mu, written
+    // over the staged mu and dinv.
+    flat(AH, AW, [&](int row, int col) {
         float s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
         for (int t = 0; t <= 2 * r; ++t) {
           s1 += Hl[(row + t) * AW + col];
           s2 += Hg[(row + t) * AW + col];
         }
-        const size_t o = gro + wrapi(j0 - RF - r + col, W);
-        const float mu = MUd[o], di = DId[o];
+        const int o = row * AW + col;
+        const float mu = Aa[o], di = Ab[o];
         const float m1 = s1 * inv_nw, m2 = s2 * inv_nw;
         const float av = (m2 - mu * m1) * di;
-        Aa[row * AW + col] = av;
-        Ab[row * AW + col] = m1 - av * mu;
-      }
-    }
+        Aa[o] = av;
+        Ab[o] = m1 - av * mu;
+    });
     __syncthreads();
     // Horizontal sums of a and b (m-space columns).
     float* Ha = Hs;
     float* Hb = Hs + AH * W3;
-    for (int row = wave; row < AH; row += kWaves) {
-      for (int col = lane; col < W3; col += 64) {
+    flat(AH, W3, [&](int row, int col) {
         const float* ar = Aa + row * AW + col;
         const float* br = Ab + row * AW + col;
         float s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
         for (int t = 0; t <= 2 * r; ++t) {
           s1 += ar[t];
           s2 += br[t];
         }
         Ha[row * W3 + col] = s1;
         Hb[row * W3 + col] = s2;
-      }
-    }
+    });
     __syncthreads();
     // M l = |w| l - G S(a) - S(b) on m-space [i0-RF, i0+TH+RF) x [j0-RF, j0+TW+RF).
     float* Ml = Xs;
-    for (int row = wave; row < MH; row += kWaves) {
-      const size_t gro = (size_t)wrapi(i0 - RF + row, H) * W;
-      for (int col = lane; col < W3; col += 64) {
+    flat(MH, W3, [&](int row, int col) {
         float sa = 0.0f, sb = 0.0f;
+#pragma unroll
         for (int t = 0; t <= 2 * r; ++t) {
           sa += Ha[(row + t) * W3 + col];
           sb += Hb[(row + t) * W3 + col];
         }
-        const float lv = Ls[(row + 2 * r) * LW + col + 2 * r];
-        const float gv = Gd[gro + wrapi(j0 - RF + col, W)];
-        Ml[row * W3 + col] = nwf * lv - gv * sa - sb;
-      }
-    }
+        const int lo = (row + 2 * r) * LW + col + 2 * r;
+        Ml[row * W3 + col] = nwf * Ls[lo] - Gs[lo] * sa - sb;
+    });
     __syncthreads();
     // Q += lambda F^T (M l): (F^T m)(x) = sum_{a,b} f[a][b] m(x + (a-RF, b-RF)).
-    for (int row = wave; row < TH; row += kWaves) {
+    for (int row = wave; row < TH; row += kPW) {
       for (int col = lane; col < TW; col += 64) {
         const float* mb = Ml + row * W3 + col;
         float s = 0.0f;
-        for (int a = 0; a < F; ++a) {
-          const float* mr = mb + a * W3;
-          for (int b = 0; b < F; ++b) s = fmaf(f[a * F + b], mr[b], s);
+        if (FT > 0) {
+#pragma unroll
+          for (int a = 0; a < (FT > 0 ? FT : 1); ++a)
+#pragma unroll
+            for (int b = 0; b < (FT > 0 ? FT : 1); ++b) s = fmaf(tp[a * FT + b], mb[a * W3 + b], s);
+        } else {
+          for (int a = 0; a < F; ++a) {
+            const float* mr = mb + a * W3;
+            const float* fr = Ts + a * F;
+            for (int b = 0; b < F; ++b) s = fmaf(fr[b], mr[b], s);
+          }
         }
         Q[row * TW + col] = fmaf(g.lam, s, Q[row * TW + col]);
       }
@@ -284,8 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_prior_apply(Geom g, PriorArgs A, con
   // then write q and the partials.
   double v[3] = {0.0, 0.0, 0.0};
   float* qc = A.q + (size_t)ch * HW;
-  const float* rc = A.r ? A.r + (size_t)ch * HW : nullptr;
-  for (int row = wave; row < TH; row += kWaves) {
+  for (int row = wave; row < TH; row += kPW) {
     const int i = i0 + row;
     if (i >= H) break;
     const int a0 = pos_mod(R - i, C), m0 = (i + a0 - R) / C - mlo;
@@ -296,21 +352,21 @@ __global__ __launch_bounds__(kBlock) void k_prior_apply(Geom g, PriorArgs A, con
       float qd = 0.0f;
       for (int a = a0, m = m0; a < n; a += C, ++m) {
         const float* yrow = Ys + m * YW + k0;
-        const float* urow = u + a * n;
+        const float* urow = Us + a * n;
         for (int b = b0, k = 0; b < n; b += C, ++k) qd = fmaf(urow[b], yrow[k], qd);
       }
       const float qv = Q[row * TW + col] + qd;
       const size_t o = (size_t)i * W + j;
       qc[o] = qv;
       if (A.mode == 1) {
-        v[0] += (double)pc[o] * qv;
-        v[1] += (double)rc[o] * qv;
+        v[0] += (double)P[(row + E) * PW + col + E] * qv;
+        v[1] += (double)Rs[row * TW + col] * qv;
         v[2] += (double)qv * qv;
       }
     }
   }
   if (A.mode == 0) return;
-  block_partials<3>(v, red, A.partials + (size_t)ch * A.pstride * 3 + (size_t)tile * 3);
+  block_partials<3, kPW>(v, red, A.partials + (size_t)ch * A.pstride * 3 + (size_t)tile * 3);
 }
 
 // r = b - q (float32) and the partials of |r|^2, for the bands whose check is pending (all bands if !only_pending).
@@ -402,12 +458,15 @@ size_t prior_layout(const Geom& g, int RF, PriorArgs* A) {
   const size_t LH = TH + 2 * (RF + 2 * r), LW = TW + 2 * (RF + 2 * r);
   const size_t AH = TH + 2 * (RF + r), AW = TW + 2 * (RF + r);
   const size_t YH = (TH - 1 + 2 * g.R) / g.c + 2, YW = (TW - 1 + 2 * g.R) / g.c + 2;
+  const size_t F = 2 * RF + 1;
   size_t off = PH * PW;
   A->E = E;
   A->TH = TH;
   A->offL = (int)off;
   off += LH * LW;
   A->offX = (int)off;
+  off += LH * LW;
+  A->offG = (int)off;
   off += LH * LW;
   A->offH = (int)off;
   off += 2 * LH * AW;
@@ -417,8 +476,23 @@ size_t prior_layout(const Geom& g, int RF, PriorArgs* A) {
   off += (size_t)TH * TW;
   A->offY = (int)off;
   off += YH * YW;
+  A->offT = (int)off;
+  off += F * F;
+  A->offU = (int)off;
+  off += (size_t)g.n * g.n;
+  A->offR = (int)off;
+  off += (size_t)TH * TW;
   A->YW = (int)YW;
   return off;
+}
+
+template <int FT>
+const void* prior_kernel_r(int RW) {
+  return RW == 1 ? (const void*)k_prior_apply<FT, 1> : RW == 2 ? (const void*)k_prior_apply<FT, 2>
+                                                                : (const void*)k_prior_apply<FT, 0>;
+}
+const void* prior_kernel(int FT, int RW) {
+  return FT == 1 ? prior_kernel_r<1>(RW) : FT == 3 ? prior_kernel_r<3>(RW) : prior_kernel_r<0>(RW);
 }
 
 struct PriorWs {
@@ -504,7 +578,9 @@ llp_status prior_setup(llp_ctx* ctx, const llp_shape* shape, const llp_params* p
   A->partials = ctx->partials;
   A->st = ctx->st;
   // the LDS this geometry needs (the attribute may not exceed the CU's LDS less the kernel's static part)
-  HIP_TRY(hipFuncSetAttribute((const void*)k_prior_apply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  A->FT = A->F[0] == 1 ? 1 : (A->F[0] == 3 ? 3 : 0);  // every filter of a prior has the same side
+  A->RW = (g.r == 1 || g.r == 2) ? g.r : 0;
+  HIP_TRY(hipFuncSetAttribute(prior_kernel(A->FT, A->RW), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   *gout = g;
   *lds_bytes = lds;
   return LLP_OK;
@@ -517,8 +593,9 @@ hipError_t launch_prior_apply(const Geom& g, PriorArgs A, size_t lds, int mode, 
   A.r = r;
   A.y = y;
   A.q = q;
-  hipLaunchKernelGGL(k_prior_apply, dim3((unsigned)(A.ntiles * g.N)), dim3(kBlock), lds, s, g, A, u);
-  return hipGetLastError();
+  const dim3 grid((unsigned)(A.ntiles * g.N));
+  void* args[] = {(void*)&g, (void*)&A, (void*)&u};
+  return hipLaunchKernel(prior_kernel(A.FT, A.RW), grid, dim3(kPB), args, lds, s);
 }
 
 int flat_blocks(const Geom& g) { return (int)(((size_t)g.H * g.W + kPriorFlat - 1) / kPriorFlat); }

@@ -24,6 +24,7 @@ SHAPES = [  # N, h, w, c, n, r
     (1, 13, 11, 3, 7, 1),    # ragged under the c = 3 tiles
     (2, 40, 72, 1, 3, 1),
     (1, 16, 16, 4, 17, 2),   # the largest filter the operator takes at r = 2
+    (2, 20, 22, 2, 5, 3),    # a window radius without its own kernel instance
 ]
 
 
