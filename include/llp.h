@@ -342,6 +342,37 @@ llp_status llp_prior_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_
                                 const float* lrms, const float* pan, const float* kernel, const float* init,
                                 float* hrms, llp_report* rep, hipStream_t stream);
 
+/* ---- Blur-kernel estimation ------------------------------------------------------------------------------ */
+
+/* Parameters of Algorithm "Blur Kernel Estimation" (Sec. III-A): the kernel side n (odd, <= 29), the box sizes
+ * of eq. (objective3) (u_1 the (2l+1)^2 box on the LR grid, u_2 the (c l + 1)^2 box on the HR grid; c l + 1 must
+ * be odd), lam_w of eq. (objective3), the TGV weights alpha_1, alpha_2 of eq. (reg1), the penalties mu_1..mu_3
+ * and the step rho of the generalized ADMM (eq. Lagrangian, eq. subproblems), the iteration cap and the
+ * threshold on ||u^{t+1} - u^t|| / ||u^{t+1}||. */
+typedef struct {
+  int n, l;
+  double lam_w, alpha1, alpha2, mu1, mu2, mu3, rho;
+  int t_max;
+  double th;
+} llp_kernel_est_params;
+
+typedef struct {
+  int iters;     /* GADMM iterations run */
+  double change; /* relative change of u at the last iteration */
+} llp_kernel_est_report;
+
+/* Estimate the blur kernel from the LRMS bands that overlap PAN (Algorithm "Blur Kernel Estimation", App. A):
+ * the spectral weights omega of eq. (objective3), then the generalized ADMM on eq. (u_solve) with the TGV^2
+ * prior of eq. (reg1) and the simplex constraint of eq. (simplex), from the uniform kernel, in FP64 on the GPU.
+ * Readings: periodic forward differences on the kernel grid; the (u, p) step keeps the mu_3 coupling; the
+ * returned kernel is z (the simplex-projected copy).  lrms [Np][h][w] (Np <= 16) and pan [c h][c w] device
+ * float32; kernel [n][n] device float32 (output, unit gain, >= 0); omega_out device [Np] doubles or NULL; rep
+ * host or NULL (then the call is asynchronous on `stream`, else it synchronizes it).  LLP_E_UNSUPPORTED for
+ * n > 29, n > c h or c w, or an even c l + 1. */
+llp_status llp_estimate_kernel(llp_ctx* ctx, const llp_kernel_est_params* prm, int Np, int h, int w, int c,
+                               const float* lrms, const float* pan, float* kernel, double* omega_out,
+                               llp_kernel_est_report* rep, hipStream_t stream);
+
 /* ---- Kernel timing -------------------------------------------------------------------------------------- */
 
 typedef struct {

@@ -53,6 +53,16 @@ class TuneResult(ctypes.Structure):
                 ("candidates", ctypes.c_int)]
 
 
+class KernelEstParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("l", ctypes.c_int), ("lam_w", ctypes.c_double), ("alpha1", ctypes.c_double),
+                ("alpha2", ctypes.c_double), ("mu1", ctypes.c_double), ("mu2", ctypes.c_double),
+                ("mu3", ctypes.c_double), ("rho", ctypes.c_double), ("t_max", ctypes.c_int), ("th", ctypes.c_double)]
+
+
+class KernelEstReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("change", ctypes.c_double)]
+
+
 class LlpError(RuntimeError):
     def __init__(self, status: int, where: str):
         super().__init__(f"{where}: {status_str(status)} ({status})")
@@ -83,6 +93,9 @@ _SIGS = {
                                        _vp, _vp, ctypes.c_int, _vp]),
     "llp_prior_pansharpen": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), ctypes.c_int, _vp,
                                             _vp, _vp, _vp, _vp, ctypes.POINTER(Report), _vp]),
+    "llp_estimate_kernel": (ctypes.c_int, [_vp, ctypes.POINTER(KernelEstParams), ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                           ctypes.POINTER(KernelEstReport), _vp]),
     "llp_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "llp_get_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
     "llp_objective": (ctypes.c_int, [_vp, ctypes.POINTER(Shape), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
@@ -418,6 +431,23 @@ class Context:
                                      _ptr(kernel), _ptr(z), _ptr(out), int(bool(data_term)), _stream(stream)),
                "llp_apply_prior")
         return out
+
+    def estimate_kernel(self, lrms, pan, c: int, *, n: int, l: int = 1, lam_w: float = 10.0, alpha1: float = 1.0,
+                        alpha2: float = 0.006, mu1: float = 100.0, mu2: float = 100.0, mu3: float = 100.0,
+                        rho: float = 0.5, t_max: int = 10000, th: float = 1e-5, stream=None):
+        """Algorithm Blur Kernel Estimation (llp_estimate_kernel).  Returns (kernel [n][n] float32, omega [Np]
+        float64, report dict)."""
+        import torch
+        Np, h, w = lrms.shape
+        prm = KernelEstParams(int(n), int(l), float(lam_w), float(alpha1), float(alpha2), float(mu1), float(mu2),
+                              float(mu3), float(rho), int(t_max), float(th))
+        out = torch.empty((n, n), dtype=torch.float32, device=lrms.device)
+        om = torch.empty((Np,), dtype=torch.float64, device=lrms.device)
+        rep = KernelEstReport()
+        _check(lib().llp_estimate_kernel(self._h, ctypes.byref(prm), int(Np), int(h), int(w), int(c), _ptr(lrms),
+                                         _ptr(pan), _ptr(out), om.data_ptr(), ctypes.byref(rep), _stream(stream)),
+               "llp_estimate_kernel")
+        return out, om, {"iters": rep.iters, "change": rep.change}
 
     def apply_data(self, z, kernel, *, c: int, r: int, stream=None):
         """B^T D^T D B z (llp_apply_data)."""

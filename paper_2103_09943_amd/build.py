@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libllp.so")
 SOURCES = ["llp_kernels.hip", "llp_operator.hip", "llp_fast.hip", "llp_sweep.hip", "llp_refine.hip", "llp_precond.hip",
            "llp_api.hip",
            "llp_batch.hip", "llp_tune.hip", "llp_cnn.hip",
-           "llp_cnn_api.hip", "llp_noalloc.hip", "llp_prior.hip"]
+           "llp_cnn_api.hip", "llp_noalloc.hip", "llp_prior.hip", "llp_kernel_est.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -603,6 +603,7 @@ void llp_destroy(llp_ctx* ctx) {
   if (ctx->bstream) (void)hipStreamDestroy(ctx->bstream);
   cnn_free(ctx->cnn);
   if (ctx->prior_ws) (void)hipFree(ctx->prior_ws);
+  if (ctx->ke_ws) (void)hipFree(ctx->ke_ws);
   delete ctx;
 }
 

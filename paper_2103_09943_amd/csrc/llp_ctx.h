@@ -156,4 +156,7 @@ struct llp_ctx {
   // filter priors (llp_prior_pansharpen, llp_apply_prior): guides, statistics, taps, restart flags
   void* prior_ws = nullptr;
   size_t prior_bytes = 0;
+  // blur-kernel estimation (llp_estimate_kernel): omega terms, f, E^T f, correlations, E^T E and its inverse
+  void* ke_ws = nullptr;
+  size_t ke_bytes = 0;
 };

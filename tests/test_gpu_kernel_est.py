@@ -1,0 +1,117 @@
+"""GPU: Algorithm "Blur Kernel Estimation" (llp_estimate_kernel) against the oracle's host-side implementation
+(oracle/tgv.py), through the C ABI.
+
+Both run in FP64 on the same float32 inputs.  Bars: the spectral weights omega to 1e-9 relative; the kernel after
+a fixed number of GADMM iterations to 1e-6 relative L2 (the GPU returns it rounded to float32; the inverse of
+E^T E + mu_3 I is Gauss-Jordan there, Cholesky in the oracle); to convergence, the same kernel as the oracle's
+to 1e-4 and the true kernel within the oracle's own recovery bar (eq. relative_error_kernel).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import tgv
+from paper_2103_09943_amd import binding as B
+from paper_2103_09943_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def scene(u, side, N, c, key, noise=0.0):
+    rng = np.random.default_rng(np.random.SeedSequence([59, key]))
+    sc = scenes.make_scene(rng, side, side, N, c, u, pan_noise=noise, ms_noise=noise)
+    return sc.X.astype(np.float32), sc.Y.astype(np.float32)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+CASES = [  # kernel side, PAN side, bands, c, l
+    (9, 128, 4, 4, 1),
+    (5, 96, 3, 2, 1),
+    (13, 64, 5, 4, 2),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_fixed_iterations_match_oracle(ctx, torch_dev, case):
+    n, side, N, c, l = case
+    u = scenes.gaussian_kernel(n, 1.3, 1.0, theta=0.3, cx=0.4, cy=-0.2)
+    X, Y = scene(u, side, N, c, n)
+    prm = tgv.TgvParams(n=n, l=l, t_max=40, th=0.0)
+    want, info = tgv.estimate_kernel(X, Y, c, prm)
+    got, om, rep = ctx.estimate_kernel(dev(torch_dev, X), dev(torch_dev, Y), c, n=n, l=l, t_max=40, th=0.0)
+    assert rep["iters"] == 40
+    np.testing.assert_allclose(om.cpu().numpy(), info["omega"], rtol=1e-9, atol=1e-12)
+    g = got.cpu().numpy().astype(np.float64)
+    assert rel(g, want) < 1e-6, rel(g, want)
+    assert abs(g.sum() - 1.0) < 1e-5 and g.min() >= 0.0
+
+
+def test_largest_kernel_fixed_iterations(ctx, torch_dev):
+    """n = 29, the paper's kernel size (Sec. IV-C) and the largest the iteration's LDS holds."""
+    n, side, N, c = 29, 128, 3, 2
+    u = scenes.gaussian_kernel(n, 3.0, 2.0, theta=0.7)
+    X, Y = scene(u, side, N, c, 29)
+    want, _ = tgv.estimate_kernel(X, Y, c, tgv.TgvParams(n=n, t_max=12, th=0.0))
+    got, _, rep = ctx.estimate_kernel(dev(torch_dev, X), dev(torch_dev, Y), c, n=n, t_max=12, th=0.0)
+    assert rep["iters"] == 12
+    assert rel(got.cpu().numpy(), want) < 1e-6
+
+
+def test_recovers_known_kernel_like_the_oracle(ctx, torch_dev):
+    """The oracle's recovery scene (noiseless, 6 bands, 256^2, x4, an anisotropic off-centre 9 x 9 Gaussian) with
+    the paper's parameters, to convergence."""
+    rng = np.random.default_rng(np.random.SeedSequence([47, 8]))
+    u = scenes.gaussian_kernel(9, 1.6, 1.2, theta=0.4, cx=0.7, cy=-0.4)
+    sc = scenes.make_scene(rng, 256, 256, 6, 4, u, pan_noise=0.0, ms_noise=0.0)
+    X, Y = sc.X.astype(np.float32), sc.Y.astype(np.float32)
+    want, info = tgv.estimate_kernel(X, Y, 4, tgv.TgvParams(n=9))
+    got, _, rep = ctx.estimate_kernel(dev(torch_dev, X), dev(torch_dev, Y), 4, n=9)
+    g = got.cpu().numpy().astype(np.float64)
+    assert abs(rep["iters"] - info["iters"]) <= 2, (rep, info["iters"])
+    assert rel(g, want) < 1e-4
+    assert tgv.relative_kernel_error(u, g) < 5.0
+
+
+def test_motion_blur_kernel_of_the_paper(ctx, torch_dev):
+    """The paper's kernel-estimation kernel (R 9, sigma 2, d 3, theta -13.7 degrees, off-centre) at n = 19 on a
+    noisy scene: the GPU estimate equals the oracle's."""
+    u = scenes.motion_blur_kernel(9, 2.0, 3.0, math.radians(-13.7), 1.392, 0.093)
+    X, Y = scene(u, 128, 4, 4, 19, noise=0.005)
+    want, info = tgv.estimate_kernel(X, Y, 4, tgv.TgvParams(n=19, t_max=300))
+    got, _, rep = ctx.estimate_kernel(dev(torch_dev, X), dev(torch_dev, Y), 4, n=19, t_max=300)
+    assert abs(rep["iters"] - info["iters"]) <= 2
+    assert rel(got.cpu().numpy(), want) < 1e-4
+
+
+def test_refusals(ctx, torch_dev):
+    X = dev(torch_dev, np.zeros((2, 16, 16)))
+    Y = dev(torch_dev, np.zeros((64, 64)))
+    for kw, status in [(dict(n=31), B.E_UNSUPPORTED), (dict(n=8), B.E_ARG), (dict(n=9, mu1=0.0), B.E_ARG)]:
+        with pytest.raises(B.LlpError) as ei:
+            ctx.estimate_kernel(X, Y, 4, **kw)
+        assert ei.value.status == status
+    with pytest.raises(B.LlpError) as ei:  # c l + 1 even: the HR box has no centre tap
+        ctx.estimate_kernel(dev(torch_dev, np.zeros((2, 16, 16))), dev(torch_dev, np.zeros((48, 48))), 3, n=9)
+    assert ei.value.status == B.E_UNSUPPORTED
