@@ -12,7 +12,9 @@ call from Z = 0 (the metric's plain leg), `config.cg_cold_value` the unprecondit
 Other workloads (--workload): `scene` (one 8-band 2048^2 scene, r 2; value from Z = 0), `batch` (64 scenes of
 PAN side 256..1024, 4 or 8 bands, r 1; value from Z = 0), `warmstart` (500 held-out 8-band 512^2 scenes, network
 start vs Z = 0), `priors` (the `scene` input solved under the compared priors of the paper's prior comparison:
-value = the LGC prior to tol 1e-6 from Z = 0; HPF likewise, LLP/LPP/LPF at a fixed iteration count as legs).
+value = the LGC prior to tol 1e-6 from Z = 0; HPF likewise, LLP/LPP/LPF at a fixed iteration count as legs),
+`kernel_est` (Algorithm "Blur Kernel Estimation" on the `scene` input: a 29 x 29 kernel from the 8 LRMS bands and
+PAN with the paper's parameters, to convergence; value = the scene's Mpixel*bands per second of estimation).
 
 Prints one JSON line.  `roofline` is the kernel class with the most device time in one separately profiled step
 (HIP events around every launch on the solver's stream; the timed steps carry no events): its algorithmic HBM
@@ -42,6 +44,7 @@ WORKLOADS = {
     "batch": (2, range(64), None, None),
     "warmstart": (3, range(2000, 2500), "cnn", None),
     "priors": (1, range(1), None, None),
+    "kernel_est": (1, range(1), None, None),
 }
 
 
@@ -193,6 +196,8 @@ def main():
 
     if args.workload == "priors":
         return run_priors(args)
+    if args.workload == "kernel_est":
+        return run_kernel_est(args)
     config, ids, init, _ = WORKLOADS[args.workload]
     ids = list(ids)[: args.scenes] if args.scenes else list(ids)
     t0 = time.time()
@@ -465,6 +470,117 @@ def cpu_baseline_priors(sc, st, reps):
                   f"numpy/scipy; extrapolated to {N} bands at the GPU's {band_iters} band-iterations "
                   f"({t_setup:.1f} s set-up, {t_iter:.1f} s per band-iteration)",
     }
+
+
+KE_N = 29  # the paper's kernel size (Sec. IV-C)
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+
+
+def run_kernel_est(args):
+    """The `kernel_est` workload: Algorithm 1 on the 8-band 2048^2 scene (x4), n = 29, the paper's parameters.
+    The GADMM runs in one workgroup by design (its iterates are n x n); its roofline fraction is given against the
+    chip's FP64 vector peak and, in config, against one compute unit's share of it."""
+    import numpy as np
+    import torch
+
+    from paper_2103_09943_amd import binding as B
+    from paper_2103_09943_amd import scenes
+
+    sc, _ = scenes.config_scene(1, 0)
+    X = torch.from_numpy(sc.X).cuda()
+    Y = torch.from_numpy(sc.Y).cuda()
+    N, H, W = sc.X.shape[0], sc.Y.shape[0], sc.Y.shape[1]
+    pxb = N * H * W
+    ctx = B.Context(0)
+
+    def run(t_max, steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            k, om, rep = ctx.estimate_kernel(X, Y, sc.c, n=KE_N, t_max=t_max)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps, k, rep
+
+    for i in range(args.warmup):
+        run(10000, 1)
+        log(f"warm-up step {i + 1}/{args.warmup} done")
+    step_s, kern, rep = run(10000, args.steps)
+    log(f"timed {args.steps} step(s): {step_s * 1e3:.1f} ms per step")
+    setup_s, _, _ = run(0, 2)
+    it = rep["iters"]
+    n2 = KE_N * KE_N
+    # flops of one GADMM iteration: the product with the n^2 x n^2 inverse, twelve n x n DFT passes (complex
+    # multiply-adds over n terms), the per-frequency Cramer solves and the element-wise steps
+    flops_iter = 2.0 * n2 * n2 + 12 * n2 * KE_N * 8.0 + n2 * 400.0
+    gadmm_s = max(step_s - setup_s, 1e-9)
+    achieved = flops_iter * it / gadmm_s / 1e12
+    u_true = sc.u
+    k = kern.cpu().numpy().astype(np.float64)
+    R = (KE_N - 1) // 2
+    pad = np.zeros((KE_N, KE_N))
+    nt = u_true.shape[0]
+    o = R - (nt - 1) // 2
+    pad[o:o + nt, o:o + nt] = u_true
+    cfg = {
+        "workload": f"Algorithm 1 (blur-kernel estimation) on 1 scene of 8 bands, PAN 2048x2048, LRMS 512x512 (x4): "
+                    f"a {KE_N}x{KE_N} kernel, the paper's parameters (l 1, lambda_w 10, alpha 1 / 0.006, mu 100, "
+                    f"rho 0.5, threshold 1e-5); {pxb / 1e6:.1f} Mpixel*bands per step",
+        "gadmm_iters": it,
+        "setup_ms": round(setup_s * 1e3, 2),
+        "gadmm_ms": round(gadmm_s * 1e3, 2),
+        "gadmm_us_per_iter": round(gadmm_s / max(it, 1) * 1e6, 2),
+        "gadmm_gflops": round(achieved * 1e3, 1),
+        "gadmm_frac_of_one_cu": round(achieved / (FP64_PEAK_TFLOPS / 256.0), 4),
+        "kernel_rel_error_pct": round(float(100.0 * np.linalg.norm(k - pad) / np.linalg.norm(pad)), 2),
+    }
+    ctx.close()
+    line = {
+        "metric": METRIC,
+        "value": round(pxb / step_s / 1e6, 3),
+        "unit": "Mpixel*bands/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": cfg,
+        "roofline": {"bound": "alu", "kernel": "k_ke_gadmm (one workgroup: the n x n GADMM iterates in LDS)",
+                     "achieved": round(achieved, 5), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 6), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline_kernel_est(sc, it, pxb)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_kernel_est(sc, iters, pxb):
+    """The oracle's Algorithm 1 (oracle/tgv.py) on the same scene: the set-up alone (omega, E, the Cholesky factor
+    of E^T E + mu_3 I; t_max = 0) and the set-up with 200 GADMM iterations, each the faster of two runs; the
+    difference gives the time per iteration, extrapolated to the GPU's iteration count."""
+    from oracle import tgv
+
+    def timed(t_max):
+        best = None
+        for _ in range(2):
+            t0 = time.perf_counter()
+            tgv.estimate_kernel(sc.X, sc.Y, sc.c, tgv.TgvParams(n=KE_N, t_max=t_max, th=0.0))
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    K = 200
+    t_setup = timed(0)
+    t_iter = max(timed(K) - t_setup, 0.0) / K
+    t = t_setup + t_iter * iters
+    return {"value": pxb / t / 1e6, "unit": "Mpixel*bands/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"the oracle's set-up ({t_setup:.1f} s: omega, E, the Cholesky factor) and {K} GADMM iterations "
+                      f"({t_iter * 1e3:.2f} ms each), the faster of two runs each, extrapolated to the GPU's "
+                      f"{iters} iterations"}
 
 
 def describe(name, host, st, pxb):

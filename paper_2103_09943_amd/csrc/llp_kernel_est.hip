@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kKeMaxSide = 29;           // longest kernel side the iteration's LDS holds
 constexpr int kKeMaxBands = 16;          // overlapping LRMS bands
-constexpr int kKeThreads = 1024;         // the iteration workgroup
+constexpr int kKeThreads = 512;          // the iteration workgroup (2 waves per SIMD: room for the FP64 Cramer temporaries)
 constexpr int kKeFlat = kBlock * 16;     // LR pixels per workgroup of the flat reductions
 constexpr int kKeOmegaVals = kKeMaxBands * (kKeMaxBands + 1) / 2 + kKeMaxBands;
 
@@ -293,9 +293,10 @@ __device__ void dft_pass(double* F, double* T, const double* roots, int n, bool 
   for (int e = threadIdx.x; e < n2; e += kKeThreads) {
     const int j = e / n, k = e - j * n;
     double sr = 0.0, si = 0.0;
-    for (int m = 0; m < n; ++m) {
+    const int step = along_cols ? k : j;  // the root index advances by the output index per term
+    int idx = 0;
+    for (int m = 0; m < n; ++m, idx = (idx + step >= n ? idx + step - n : idx + step)) {
       const int src = along_cols ? j * n + m : m * n + k;
-      const int idx = ((along_cols ? m * k : j * m) % n);
       const double wr = roots[2 * idx], wi = inverse ? -roots[2 * idx + 1] : roots[2 * idx + 1];
       const double fr = F[2 * src], fi = F[2 * src + 1];
       sr += fr * wr - fi * wi;
@@ -386,13 +387,26 @@ __global__ __launch_bounds__(kKeThreads) void k_ke_gadmm(KeArgs K, const double*
     __syncthreads();
     // z = (E^T E + mu3 I)^{-1} rhs: one wave per row, lanes along the row (coalesced)
     {
+      // four rows per wave step, so that each lane has four independent streams of loads in flight
       const int lane = tid & 63, wave = tid >> 6;
-      for (int rr = wave; rr < n2; rr += kKeThreads / 64) {
-        const double* krow = Kinv + (size_t)rr * n2;
-        double s = 0.0;
-        for (int j = lane; j < n2; j += 64) s += krow[j] * S.F1[j];
-        s = wave_sum(s);
-        if (lane == 0) S.z[rr] = s;
+      constexpr int kRows = 4;
+      for (int r0 = wave * kRows; r0 < n2; r0 += (kKeThreads / 64) * kRows) {
+        double s[kRows];
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) s[q] = 0.0;
+        for (int j = lane; j < n2; j += 64) {
+          const double rv = S.F1[j];
+#pragma unroll
+          for (int q = 0; q < kRows; ++q) {
+            const int rr = min(r0 + q, n2 - 1);
+            s[q] += Kinv[(size_t)rr * n2 + j] * rv;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) {
+          const double t = wave_sum(s[q]);
+          if (lane == 0 && r0 + q < n2) S.z[r0 + q] = t;
+        }
       }
     }
     __syncthreads();
