@@ -103,15 +103,15 @@ def bytes_model(kt, host, reps, precond):
 
 
 KERNEL_NAMES = {
-    "apply": "operator q = A p (column sweep k_llp: B^T D^T y on matrix cores + lambda L^T M L p)",
-    "dir": "direction kernel k_dir_fast (p = s + beta p, x += alpha p, y = D B p)",
-    "pc_rows": "k_pc_rows (r update; forward row transforms of the band pairs)",
+    "apply": "operator q = A p (column sweep k_llp_batch: B^T D^T y on matrix cores + lambda L^T M L p)",
+    "dir": "direction kernel k_dir_fast_batch (x += alpha p, p = s + beta p, y = D B p)",
+    "pc_rows": "k_pc_rows (r -= alpha q; forward row transforms of the band pairs)",
     "pc_cols": "k_pc_cols (column transforms, per-group solve of P, inverse column transforms)",
     "pc_rows_inv": "k_pc_rows_inv (inverse row transforms, s = P^-1 r, r^T s)",
 }
 # kernel names in the traffic record (namespace and template arguments, no parameter list)
 PROF_PREFIX = {"pc_cols": "llp::k_pc_cols<", "pc_rows": "llp::k_pc_rows<", "pc_rows_inv": "llp::k_pc_rows_inv<",
-               "dir": "llp::k_dir_fast<4, 8, 4, 3>", "apply": "llp::k_llp<2, 1, 4, 8>"}
+               "dir": "llp::k_dir_fast_batch<", "apply": "llp::k_llp_batch<"}
 
 
 def measured_traffic(kernel):
