@@ -212,6 +212,7 @@ constexpr int kPcThreads = 1024;   // threads per workgroup of the row transform
 constexpr int kPcColThreads = 512; // threads per workgroup of the column pass
 constexpr int kPcSmallRowThreads = 256;  // row passes of tables whose rows hold at most kPcSmallElems values
 constexpr int kPcMaxElems = 16384; // complex values a workgroup holds in LDS: c W and c H at most this
+constexpr int kPcColBudget = 8192; // column pass: pairs of one column are grouped up to this many values
 constexpr int kPcSmallElems = 4096; // the same where a transform needs radix 2, 3, 5 or 7
 constexpr int kPcMaxRad = 16;      // radix passes per transform length
 constexpr int kPcMaxLds = 160 * 1024 - 512;  // dynamic LDS of a transform pass (sequences and twiddles)
@@ -245,6 +246,7 @@ struct PcDesc {
 struct PcPlan {
   int count = 0, bands = 0, row_blocks = 0, col_blocks = 0;
   size_t row_lds = 0, col_lds = 0;
+  int col_budget = 0;  // column pass: elements of one group of columns (band pairs of one LR column)
   int cus = 256;       // compute units of the device (persistent column workgroups)
   bool mixed = false;  // some transform length needs radix 2, 3, 5 or 7 (the kernels for short transforms)
   bool small_rows = false;  // every scene's c^2 w <= kPcSmallElems: row passes of kPcSmallRowThreads threads

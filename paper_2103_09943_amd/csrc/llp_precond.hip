@@ -29,6 +29,7 @@
 #include "llp_device.h"
 
 #include <math.h>
+#include <stdlib.h>
 
 #include <algorithm>
 
@@ -654,69 +655,108 @@ __global__ __launch_bounds__(TH) void k_pc_rows(int op, const PcDesc* __restrict
 // every group instead of P^{-1}.  op kPcColsKernel: forward transforms and the c x c DFT of pair 0 (the
 // embedded kernel), stored as U in the cell layout.  Each thread moves whole cells.
 //
-// Persistent workgroups, one per compute unit (the c^2 sequences fill its LDS): workgroup b takes a contiguous
-// range of items (scene, LR column k2, pair), pairs fastest, so that the items of one column follow each other
-// and reuse its U from the L2 cache.  The next item's column is loaded into registers while the current one
-// is transformed, so the loads overlap the LDS passes.
+// Persistent workgroups, as many per compute unit as the LDS holds: workgroup b owns every G-th LR column of the
+// table and transforms the running band pairs of a column together, as many as the launch's element budget
+// allows (short columns), so that U of the column is reused from the L2 cache.  The next group's columns are
+// loaded into registers while the current group is transformed.
 
 constexpr size_t kPcCuLds = 160 * 1024;    // LDS of a compute unit
 constexpr int kColPf = kPcMaxElems / TC;  // complex values per thread of one item's column
 
-// Issue the loads of the column (h cells of C^2 values) of pair `pair`, LR column k2 into registers.
+// Items of one column processed together: up to kColGroup band pairs of one LR column, as many as fit in the
+// element budget of the launch (short columns would otherwise leave most of the workgroup idle in the cell
+// operations and the transforms).
+constexpr int kColGroup = 8;
+
+__host__ __device__ __forceinline__ int col_group_max(const PcDesc& d, int budget) {
+  if (d.mixed_h && budget > kPcSmallElems) budget = kPcSmallElems;  // the mixed-radix passes' register budget
+  const int per = d.g.h * d.g.c * d.g.c;
+  int k = budget / per;
+  k = k < 1 ? 1 : k;
+  k = k > kColGroup ? kColGroup : k;
+  return k > d.npair ? d.npair : k;
+}
+
+// Issue the loads of the columns (h cells of C^2 values each) of the pairs gp[0..cnt), LR column k2, into
+// registers: element E of the group is item E / (h C^2), element E % (h C^2) of that item's column.
+// E / per for E < kPcMaxElems by a float product (the quotient is below 8 and its fraction at least 1/(2 per)
+// away from an integer, far beyond the product's rounding).
+__device__ __forceinline__ int item_of(int E, float inv_per) { return __float2int_rz(((float)E + 0.5f) * inv_per); }
+
 template <int C>
-__device__ __forceinline__ void col_prefetch(const PcDesc& d, int pair, int k2, float2 (&pf)[kColPf]) {
+__device__ __forceinline__ void col_prefetch(const PcDesc& d, const int* gp, int cnt, int k2, float2 (&pf)[kColPf]) {
   constexpr int C2 = C * C;
-  const int n = d.g.h * C2, w = d.g.w;
-  const float2* sp = d.spec + (size_t)pair * d.g.h * w * C2 + (size_t)k2 * C2;
+  const int per = d.g.h * C2, n = cnt * per, w = d.g.w;
+  const float inv_per = 1.0f / (float)per;
+  const size_t pstride = (size_t)d.g.h * w * C2;
 #pragma unroll
   for (int k = 0; k < kColPf; ++k) {
     if (k * TC < n) {  // uniform
-      const int e = min(k * TC + opaque_tid(), n - 1);
-      pf[k] = gld(sp + (size_t)(e / C2) * w * C2 + e % C2);
+      const int E = min(k * TC + opaque_tid(), n - 1);
+      const int it = item_of(E, inv_per), e = E - it * per;
+      pf[k] = gld(d.spec + gp[it] * pstride + (size_t)(e / C2) * w * C2 + (size_t)k2 * C2 + e % C2);
     }
   }
 }
 
-// The prefetched column into the LDS sequences.
+// The prefetched columns into the LDS sequences: item it's sequences are it C^2 .. it C^2 + C^2 - 1.
 template <int C>
-__device__ __forceinline__ void col_stage(const PcDesc& d, const float2 (&pf)[kColPf], float2* pcsh) {
+__device__ __forceinline__ void col_stage(const PcDesc& d, int cnt, const float2 (&pf)[kColPf], float2* pcsh) {
   constexpr int C2 = C * C;
-  const int n = d.g.h * C2, Sh = seq_stride(d.g.h);
+  const int per = d.g.h * C2, n = cnt * per, Sh = seq_stride(d.g.h);
+  const float inv_per = 1.0f / (float)per;
 #pragma unroll
   for (int k = 0; k < kColPf; ++k) {
-    const int e = k * TC + opaque_tid();
-    if (k * TC < n && e < n) pcsh[pd(e % C2, Sh, e / C2)] = pf[k];
+    const int E = k * TC + opaque_tid();
+    if (k * TC < n && E < n) {
+      const int it = item_of(E, inv_per), e = E - it * per;
+      pcsh[pd(it * C2 + e % C2, Sh, e / C2)] = pf[k];
+    }
   }
 }
 
-// Transforms, cell operations and the store of one item whose column is in LDS (twl: the length-h twiddles).
+// Transforms, cell operations and the store of one group whose columns are in LDS (twl: the length-h twiddles).
 template <int C, bool MIXED>
-__device__ __forceinline__ void cols_body(int op, const PcDesc& d, int pair, int k2, float2* pcsh, const float2* twl) {
+__device__ __forceinline__ void cols_body(int op, const PcDesc& d, const int* gp, int cnt, int k2, float2* pcsh,
+                                          const float2* twl) {
   constexpr int C2 = C * C;
   const Geom& g = d.g;
   const int h = g.h, w = g.w;
-  float2* sp = d.spec + (size_t)pair * h * w * C2;
   const int Sh = seq_stride(h);
-  fft_lds<TC, MIXED>(pcsh, h, C2, d.rh, d.nrh, twl);
+  fft_lds<TC, MIXED>(pcsh, h, cnt * C2, d.rh, d.nrh, twl);
   const float dscale = op == kPcColsSolve ? (float)((double)g.lam * d.mbar[0]) : 0.0f;
 #pragma unroll 1
-  for (int k1 = opaque_tid(); k1 < h; k1 += TC) cell_op<C>(op, d, pcsh, h, k1, k2, dscale);
+  for (int idx = opaque_tid(); idx < cnt * h; idx += TC) {
+    const int it = idx / h, k1 = idx - it * h;
+    cell_op<C>(op, d, pcsh + (size_t)it * C2 * Sh, h, k1, k2, dscale);
+  }
   if (op == kPcColsKernel) return;
   __syncthreads();
-  fft_lds<TC, MIXED>(pcsh, h, C2, d.rh, d.nrh, twl);
+  fft_lds<TC, MIXED>(pcsh, h, cnt * C2, d.rh, d.nrh, twl);
+  const int per = h * C2;
+  const float inv_per = 1.0f / (float)per;
+  const size_t pstride = (size_t)h * w * C2;
   copy_elems<TC, 8>(
-      h * C2, [&](int e) { return conjf2(pcsh[pd(e % C2, Sh, e / C2)]); },
-      [&](int e, float2 v) { gst(sp + ((size_t)(e / C2) * w + k2) * C2 + e % C2, v); });
+      cnt * per,
+      [&](int E) {
+        const int it = item_of(E, inv_per), e = E - it * per;
+        return conjf2(pcsh[pd(it * C2 + e % C2, Sh, e / C2)]);
+      },
+      [&](int E, float2 v) {
+        const int it = item_of(E, inv_per), e = E - it * per;
+        gst(d.spec + gp[it] * pstride + ((size_t)(e / C2) * w + k2) * C2 + e % C2, v);
+      });
 }
 
 // The items of one scene that this workgroup owns: the LR columns k2 = k0, k0 + G, k0 + 2G, ... (G workgroups)
-// and, per column, its band pairs with a running band (the pairs of a column follow each other, so U of the
-// column is reused from L2).  The next item's column is in flight while the current one is transformed.
+// and, per column, its band pairs with a running band, taken kmax at a time (U of the column is reused from L2
+// by every pair).  The next group's columns are in flight while the current group is transformed.
 template <int C, bool MIXED>
 __device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanState* sst, int k0, int G,
-                                           float2* pcsh) {
+                                           float2* pcsh, int budget, int* gsh) {
   const int np = d.npair;
   const int hi = (d.g.w - k0 + G - 1) / G * np;  // items: l = j np + pair for the j-th owned column
+  const int kmax = op == kPcColsKernel ? 1 : col_group_max(d, budget);
   auto runs = [&](int l) {
     const int pair = l % np;
     return op == kPcColsKernel ? pair == 0
@@ -727,32 +767,53 @@ __device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanSt
       if (runs(l)) break;
     return l;
   };
+  // the group starting at running item l: running items of l's column, at most kmax, their pairs into gp (every
+  // thread writes the same values); returns the item after the group
+  auto group = [&](int l, int* gp, int& cnt) {
+    const int j = l / np;
+    cnt = 0;
+    for (; l < hi && l / np == j && cnt < kmax; l = next(l + 1)) gp[cnt++] = l % np;
+    return l;
+  };
   auto col_of = [&](int l) { return k0 + (l / np) * G; };
   int l = next(0);
   if (l >= hi) return;
+  int* gp = gsh;
+  int* gpn = gsh + kColGroup;
+  int cnt = 0, cntn = 0;
+  __syncthreads();  // the group buffers of a previous scene are no longer read
+  int nx = group(l, gp, cnt);
   float2 pf[kColPf];
-  col_prefetch<C>(d, l % np, col_of(l), pf);
+  col_prefetch<C>(d, gp, cnt, col_of(l), pf);
   __syncthreads();  // the LDS of a previous scene is no longer read
-  const float2* twl = stage_twiddles<TC>(pcsh, C * C, d.g.h, d.twh);
+  const float2* twl = stage_twiddles<TC>(pcsh, kmax * C * C, d.g.h, d.twh);
   while (l < hi) {
-    col_stage<C>(d, pf, pcsh);
-    const int nx = next(l + 1);
-    if (nx < hi) col_prefetch<C>(d, nx % np, col_of(nx), pf);
+    col_stage<C>(d, cnt, pf, pcsh);
+    int nnx = hi;
+    if (nx < hi) {
+      nnx = group(nx, gpn, cntn);
+      col_prefetch<C>(d, gpn, cntn, col_of(nx), pf);
+    }
     __syncthreads();
-    cols_body<C, MIXED>(op, d, l % np, col_of(l), pcsh, twl);
-    __syncthreads();  // the LDS reads of this item are done
+    cols_body<C, MIXED>(op, d, gp, cnt, col_of(l), pcsh, twl);
+    __syncthreads();  // the LDS reads of this group are done
     l = nx;
+    nx = nnx;
+    cnt = cntn;
+    int* t = gp;  // the prefetched group becomes the current one
+    gp = gpn;
+    gpn = t;
   }
 }
 
 template <bool MIXED>
 __device__ __forceinline__ void cols_scene_c(int op, const PcDesc& d, const ChanState* sst, int k0, int G,
-                                             float2* pcsh) {
+                                             float2* pcsh, int budget, int* gsh) {
   switch (d.g.c) {
-    case 4: cols_scene<4, MIXED>(op, d, sst, k0, G, pcsh); break;
-    case 3: cols_scene<3, MIXED>(op, d, sst, k0, G, pcsh); break;
-    case 2: cols_scene<2, MIXED>(op, d, sst, k0, G, pcsh); break;
-    default: cols_scene<1, MIXED>(op, d, sst, k0, G, pcsh); break;
+    case 4: cols_scene<4, MIXED>(op, d, sst, k0, G, pcsh, budget, gsh); break;
+    case 3: cols_scene<3, MIXED>(op, d, sst, k0, G, pcsh, budget, gsh); break;
+    case 2: cols_scene<2, MIXED>(op, d, sst, k0, G, pcsh, budget, gsh); break;
+    default: cols_scene<1, MIXED>(op, d, sst, k0, G, pcsh, budget, gsh); break;
   }
 }
 
@@ -760,16 +821,17 @@ __device__ __forceinline__ void cols_scene_c(int op, const PcDesc& d, const Chan
 // columns one after another), so the scenes that still have running bands are spread over all workgroups.
 template <bool MIXED>
 __global__ __launch_bounds__(TC) void k_pc_cols(int op, const PcDesc* __restrict__ t, int count,
-                                               const ChanState* __restrict__ st) {
+                                               const ChanState* __restrict__ st, int budget) {
   extern __shared__ float2 pcsh[];
+  __shared__ int gsh[2 * kColGroup];  // the band pairs of the current and the prefetched group
   const int G = (int)gridDim.x, b = (int)blockIdx.x;
   for (int si = 0; si < count; ++si) {
     const PcDesc& d = t[si];
     const int k0 = ((b - d.col_block0) % G + G) % G;  // first owned column of the scene
     if (k0 >= d.g.w) continue;
     const ChanState* sst = st + d.band0;
-    if (MIXED && d.mixed_h) cols_scene_c<true>(op, d, sst, k0, G, pcsh);
-    else cols_scene_c<false>(op, d, sst, k0, G, pcsh);
+    if (MIXED && d.mixed_h) cols_scene_c<true>(op, d, sst, k0, G, pcsh, budget, gsh);
+    else cols_scene_c<false>(op, d, sst, k0, G, pcsh, budget, gsh);
   }
 }
 
@@ -1037,11 +1099,13 @@ static size_t pc_row_lds(const PcDesc* h_tab, int count) {
   return m;
 }
 
-static size_t pc_col_lds(const PcDesc* h_tab, int count) {
+// The column pass's LDS: the largest scene's group of kmax columns (pairs) of c^2 sequences, plus its twiddles.
+static size_t pc_col_lds(const PcDesc* h_tab, int count, int budget) {
   size_t m = 0;
   for (int i = 0; i < count; ++i) {
     const Geom& g = h_tab[i].g;
-    const size_t b = pc_lds_bytes(g.c, g.h);
+    const int k = col_group_max(h_tab[i], budget);
+    const size_t b = ((size_t)k * g.c * g.c * seq_stride(g.h) + g.h) * sizeof(float2);
     if (b > m) m = b;
   }
   return m;
@@ -1062,7 +1126,12 @@ void pc_plan(PcDesc* h_tab, int count, PcPlan* plan) {
                                                hipSuccess || P.cus < 1)
     P.cus = 256;
   P.row_lds = pc_row_lds(h_tab, count);
-  P.col_lds = pc_col_lds(h_tab, count);
+  P.col_budget = kPcColBudget;
+  if (const char* e = getenv("LLP_COL_BUDGET")) {  // launch-shape override (elements per column group)
+    const int v = atoi(e);
+    if (v >= 1 && v <= kPcMaxElems) P.col_budget = v;
+  }
+  P.col_lds = pc_col_lds(h_tab, count, P.col_budget);
   P.small_rows = true;
   for (int i = 0; i < count; ++i) {
     const Geom& g = h_tab[i].g;
@@ -1097,9 +1166,9 @@ hipError_t launch_pc_cols(int op, const PcDesc* t, const PcPlan& P, const ChanSt
   const int per_cu = std::max(1, std::min((int)(kPcCuLds / (P.col_lds + 1024)), 2048 / TC));
   const int grid = std::max(1, std::min(P.col_blocks, P.cus * per_cu));
   if (P.mixed)
-    hipLaunchKernelGGL(k_pc_cols<true>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st);
+    hipLaunchKernelGGL(k_pc_cols<true>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st, P.col_budget);
   else
-    hipLaunchKernelGGL(k_pc_cols<false>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st);
+    hipLaunchKernelGGL(k_pc_cols<false>, dim3(grid), dim3(TC), P.col_lds, s, op, t, P.count, st, P.col_budget);
   return hipGetLastError();
 }
 
