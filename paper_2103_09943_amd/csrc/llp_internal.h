@@ -212,7 +212,7 @@ constexpr int kPcThreads = 1024;   // threads per workgroup of the row transform
 constexpr int kPcColThreads = 512; // threads per workgroup of the column pass
 constexpr int kPcSmallRowThreads = 256;  // row passes of tables whose rows hold at most kPcSmallElems values
 constexpr int kPcMaxElems = 16384; // complex values a workgroup holds in LDS: c W and c H at most this
-constexpr int kPcColBudget = 8192; // column pass: pairs of one column are grouped up to this many values
+constexpr int kPcColBudget = 16384; // column pass: pairs of one column are grouped up to this many values
 constexpr int kPcSmallElems = 4096; // the same where a transform needs radix 2, 3, 5 or 7
 constexpr int kPcMaxRad = 16;      // radix passes per transform length
 constexpr int kPcMaxLds = 160 * 1024 - 512;  // dynamic LDS of a transform pass (sequences and twiddles)

@@ -683,24 +683,26 @@ __host__ __device__ __forceinline__ int col_group_max(const PcDesc& d, int budge
 // away from an integer, far beyond the product's rounding).
 __device__ __forceinline__ int item_of(int E, float inv_per) { return __float2int_rz(((float)E + 0.5f) * inv_per); }
 
-template <int C>
+// GR: groups of several pairs; otherwise one pair (gp[0]) and no item split.
+template <int C, bool GR>
 __device__ __forceinline__ void col_prefetch(const PcDesc& d, const int* gp, int cnt, int k2, float2 (&pf)[kColPf]) {
   constexpr int C2 = C * C;
   const int per = d.g.h * C2, n = cnt * per, w = d.g.w;
   const float inv_per = 1.0f / (float)per;
   const size_t pstride = (size_t)d.g.h * w * C2;
+  const float2* sp0 = d.spec + (GR ? 0 : gp[0] * pstride) + (size_t)k2 * C2;
 #pragma unroll
   for (int k = 0; k < kColPf; ++k) {
     if (k * TC < n) {  // uniform
       const int E = min(k * TC + opaque_tid(), n - 1);
-      const int it = item_of(E, inv_per), e = E - it * per;
-      pf[k] = gld(d.spec + gp[it] * pstride + (size_t)(e / C2) * w * C2 + (size_t)k2 * C2 + e % C2);
+      const int it = GR ? item_of(E, inv_per) : 0, e = E - it * per;
+      pf[k] = gld(sp0 + (GR ? gp[it] * pstride : 0) + (size_t)(e / C2) * w * C2 + e % C2);
     }
   }
 }
 
 // The prefetched columns into the LDS sequences: item it's sequences are it C^2 .. it C^2 + C^2 - 1.
-template <int C>
+template <int C, bool GR>
 __device__ __forceinline__ void col_stage(const PcDesc& d, int cnt, const float2 (&pf)[kColPf], float2* pcsh) {
   constexpr int C2 = C * C;
   const int per = d.g.h * C2, n = cnt * per, Sh = seq_stride(d.g.h);
@@ -709,14 +711,14 @@ __device__ __forceinline__ void col_stage(const PcDesc& d, int cnt, const float2
   for (int k = 0; k < kColPf; ++k) {
     const int E = k * TC + opaque_tid();
     if (k * TC < n && E < n) {
-      const int it = item_of(E, inv_per), e = E - it * per;
+      const int it = GR ? item_of(E, inv_per) : 0, e = E - it * per;
       pcsh[pd(it * C2 + e % C2, Sh, e / C2)] = pf[k];
     }
   }
 }
 
 // Transforms, cell operations and the store of one group whose columns are in LDS (twl: the length-h twiddles).
-template <int C, bool MIXED>
+template <int C, bool MIXED, bool GR>
 __device__ __forceinline__ void cols_body(int op, const PcDesc& d, const int* gp, int cnt, int k2, float2* pcsh,
                                           const float2* twl) {
   constexpr int C2 = C * C;
@@ -727,7 +729,7 @@ __device__ __forceinline__ void cols_body(int op, const PcDesc& d, const int* gp
   const float dscale = op == kPcColsSolve ? (float)((double)g.lam * d.mbar[0]) : 0.0f;
 #pragma unroll 1
   for (int idx = opaque_tid(); idx < cnt * h; idx += TC) {
-    const int it = idx / h, k1 = idx - it * h;
+    const int it = GR ? idx / h : 0, k1 = idx - it * h;
     cell_op<C>(op, d, pcsh + (size_t)it * C2 * Sh, h, k1, k2, dscale);
   }
   if (op == kPcColsKernel) return;
@@ -736,27 +738,27 @@ __device__ __forceinline__ void cols_body(int op, const PcDesc& d, const int* gp
   const int per = h * C2;
   const float inv_per = 1.0f / (float)per;
   const size_t pstride = (size_t)h * w * C2;
+  float2* sp0 = d.spec + (GR ? 0 : gp[0] * pstride) + (size_t)k2 * C2;
   copy_elems<TC, 8>(
       cnt * per,
       [&](int E) {
-        const int it = item_of(E, inv_per), e = E - it * per;
+        const int it = GR ? item_of(E, inv_per) : 0, e = E - it * per;
         return conjf2(pcsh[pd(it * C2 + e % C2, Sh, e / C2)]);
       },
       [&](int E, float2 v) {
-        const int it = item_of(E, inv_per), e = E - it * per;
-        gst(d.spec + gp[it] * pstride + ((size_t)(e / C2) * w + k2) * C2 + e % C2, v);
+        const int it = GR ? item_of(E, inv_per) : 0, e = E - it * per;
+        gst(sp0 + (GR ? gp[it] * pstride : 0) + (size_t)(e / C2) * w * C2 + e % C2, v);
       });
 }
 
 // The items of one scene that this workgroup owns: the LR columns k2 = k0, k0 + G, k0 + 2G, ... (G workgroups)
 // and, per column, its band pairs with a running band, taken kmax at a time (U of the column is reused from L2
 // by every pair).  The next group's columns are in flight while the current group is transformed.
-template <int C, bool MIXED>
+template <int C, bool MIXED, bool GR>
 __device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanState* sst, int k0, int G,
-                                           float2* pcsh, int budget, int* gsh) {
+                                           float2* pcsh, int kmax, int* gsh) {
   const int np = d.npair;
   const int hi = (d.g.w - k0 + G - 1) / G * np;  // items: l = j np + pair for the j-th owned column
-  const int kmax = op == kPcColsKernel ? 1 : col_group_max(d, budget);
   auto runs = [&](int l) {
     const int pair = l % np;
     return op == kPcColsKernel ? pair == 0
@@ -784,18 +786,18 @@ __device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanSt
   __syncthreads();  // the group buffers of a previous scene are no longer read
   int nx = group(l, gp, cnt);
   float2 pf[kColPf];
-  col_prefetch<C>(d, gp, cnt, col_of(l), pf);
+  col_prefetch<C, GR>(d, gp, cnt, col_of(l), pf);
   __syncthreads();  // the LDS of a previous scene is no longer read
   const float2* twl = stage_twiddles<TC>(pcsh, kmax * C * C, d.g.h, d.twh);
   while (l < hi) {
-    col_stage<C>(d, cnt, pf, pcsh);
+    col_stage<C, GR>(d, cnt, pf, pcsh);
     int nnx = hi;
     if (nx < hi) {
       nnx = group(nx, gpn, cntn);
-      col_prefetch<C>(d, gpn, cntn, col_of(nx), pf);
+      col_prefetch<C, GR>(d, gpn, cntn, col_of(nx), pf);
     }
     __syncthreads();
-    cols_body<C, MIXED>(op, d, gp, cnt, col_of(l), pcsh, twl);
+    cols_body<C, MIXED, GR>(op, d, gp, cnt, col_of(l), pcsh, twl);
     __syncthreads();  // the LDS reads of this group are done
     l = nx;
     nx = nnx;
@@ -809,11 +811,21 @@ __device__ __forceinline__ void cols_scene(int op, const PcDesc& d, const ChanSt
 template <bool MIXED>
 __device__ __forceinline__ void cols_scene_c(int op, const PcDesc& d, const ChanState* sst, int k0, int G,
                                              float2* pcsh, int budget, int* gsh) {
-  switch (d.g.c) {
-    case 4: cols_scene<4, MIXED>(op, d, sst, k0, G, pcsh, budget, gsh); break;
-    case 3: cols_scene<3, MIXED>(op, d, sst, k0, G, pcsh, budget, gsh); break;
-    case 2: cols_scene<2, MIXED>(op, d, sst, k0, G, pcsh, budget, gsh); break;
-    default: cols_scene<1, MIXED>(op, d, sst, k0, G, pcsh, budget, gsh); break;
+  const int kmax = op == kPcColsKernel ? 1 : col_group_max(d, budget);
+  if (kmax > 1) {
+    switch (d.g.c) {
+      case 4: cols_scene<4, MIXED, true>(op, d, sst, k0, G, pcsh, kmax, gsh); break;
+      case 3: cols_scene<3, MIXED, true>(op, d, sst, k0, G, pcsh, kmax, gsh); break;
+      case 2: cols_scene<2, MIXED, true>(op, d, sst, k0, G, pcsh, kmax, gsh); break;
+      default: cols_scene<1, MIXED, true>(op, d, sst, k0, G, pcsh, kmax, gsh); break;
+    }
+  } else {
+    switch (d.g.c) {
+      case 4: cols_scene<4, MIXED, false>(op, d, sst, k0, G, pcsh, 1, gsh); break;
+      case 3: cols_scene<3, MIXED, false>(op, d, sst, k0, G, pcsh, 1, gsh); break;
+      case 2: cols_scene<2, MIXED, false>(op, d, sst, k0, G, pcsh, 1, gsh); break;
+      default: cols_scene<1, MIXED, false>(op, d, sst, k0, G, pcsh, 1, gsh); break;
+    }
   }
 }
 
