@@ -185,32 +185,36 @@ __global__ __launch_bounds__(kBlock) void k_ke_etf(KeArgs K, const float* __rest
 
 // S[pa][pb][da + n - 1][db + n - 1] = sum_{m,k} Y[pa + c m][pb + c k] Y[pa + c m + da][pb + c k + db] (periodic),
 // for |da|, |db| <= n - 1.  One workgroup per (pa, pb, da); lane j of each wave owns the lag db = j - (n - 1); the
-// four waves split the LR columns; the HR row pa + c m + da is staged in LDS per LR row.
+// four waves split the LR columns.  Per LR row the HR row pa + c m + da is staged in LDS with a periodic halo of
+// n - 1 on both sides, so lane j reads position pb + c k + j: consecutive lanes, consecutive words, no wrap.
 __global__ __launch_bounds__(kBlock) void k_ke_corr(KeArgs K, const float* __restrict__ Y, double* __restrict__ S) {
   extern __shared__ float ke_row[];
   __shared__ double red[kWaves][64];
-  const int n = K.n, L = 2 * n - 1;
+  const int n = K.n, L = 2 * n - 1, W = K.W;
   const int da = (int)(blockIdx.x % L) - (n - 1);
   const int ph = blockIdx.x / L, pa = ph / K.c, pb = ph % K.c;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int db = lane - (n - 1);
   const bool live = lane < L;
-  float* row = ke_row;            // W floats: the HR row pa + c m + da
-  float* dec = ke_row + K.W;      // w floats: Y[pa + c m][pb + c k]
+  const int RW = W + 2 * (n - 1);
+  float* row = ke_row;         // RW floats: row[t] = Y[pa + c m + da][(t - (n - 1)) mod W]
+  float* dec = ke_row + RW;    // w floats: Y[pa + c m][pb + c k]
   double acc = 0.0;
   for (int m = 0; m < K.h; ++m) {
     const int i = pa + K.c * m;
-    const float* yr = Y + (size_t)wrapd(i + da, K.H) * K.W;
-    const float* y0 = Y + (size_t)i * K.W;
+    const float* yr = Y + (size_t)wrapd(i + da, K.H) * W;
+    const float* y0 = Y + (size_t)i * W;
     __syncthreads();
-    for (int j = threadIdx.x; j < K.W; j += kBlock) row[j] = yr[j];
+    for (int t = threadIdx.x; t < RW; t += kBlock) {
+      int j = t - (n - 1);
+      j += j < 0 ? W : 0;
+      j -= j >= W ? W : 0;
+      row[t] = yr[j];
+    }
     for (int k = threadIdx.x; k < K.w; k += kBlock) dec[k] = y0[pb + K.c * k];
     __syncthreads();
     if (live) {
-      for (int k = wave; k < K.w; k += kWaves) {
-        const int j = wrapd(pb + K.c * k + db, K.W);
-        acc += (double)dec[k] * (double)row[j];
-      }
+      const float* rl = row + pb + lane;
+      for (int k = wave; k < K.w; k += kWaves) acc += (double)dec[k] * (double)rl[K.c * k];
     }
   }
   red[wave][lane] = acc;
@@ -641,7 +645,7 @@ llp_status llp_estimate_kernel(llp_ctx* ctx, const llp_kernel_est_params* prm, i
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_ke_etf, dim3(n2), dim3(kBlock), 0, s, K, pan, (const double*)f, etf);
   HIP_TRY(hipGetLastError());
-  const size_t corr_lds = ((size_t)W + w) * sizeof(float);
+  const size_t corr_lds = ((size_t)W + 2 * (n - 1) + w) * sizeof(float);
   if (corr_lds > 64 * 1024)
     HIP_TRY(hipFuncSetAttribute((const void*)k_ke_corr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)corr_lds));
   hipLaunchKernelGGL(k_ke_corr, dim3((unsigned)(c * c * L)), dim3(kBlock), corr_lds, s, K, pan, Sc);
