@@ -350,23 +350,37 @@ __global__ __launch_bounds__(kBlock) void k_wgrad(CnnGeom g, const uint16_t* __r
   if (threadIdx.x < kCh) dst[kCh * kCh * kTaps + threadIdx.x] = bsum;
 }
 
-// Sum of the per-workgroup partials (fixed order) into the layer's gradient in the flat parameter layout
-// (W [cout][cin][3][3] then b [cout]) at grad.
+// Sum of the per-workgroup partials into the layer's gradient in the flat parameter layout (W [cout][cin][3][3]
+// then b [cout]) at grad.  A workgroup takes kRedOut outputs; its kRedSlices slices of threads each sum every
+// kRedSlices-th partial (slice s: partials s, s + kRedSlices, ...), then the slices are added in order: a fixed
+// order, so training stays deterministic, with the loads of many partials in flight at once.
+constexpr int kRedOut = 32, kRedSlices = kBlock / kRedOut;
+
 __global__ __launch_bounds__(kBlock) void k_wgrad_reduce(const float* __restrict__ part, int nparts, int cout,
                                                          int cin, float* __restrict__ grad) {
+  __shared__ double red[kRedSlices][kRedOut];
   const int nW = cout * cin * kTaps;
-  const int idx = blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= nW + cout) return;
-  int src;
-  if (idx < nW) {
-    const int o = idx / (cin * kTaps), c = (idx / kTaps) % cin, tap = idx % kTaps;
-    src = (o * kCh + c) * kTaps + tap;
-  } else {
-    src = kCh * kCh * kTaps + (idx - nW);
+  const int j = threadIdx.x % kRedOut, sl = threadIdx.x / kRedOut;
+  const int idx = blockIdx.x * kRedOut + j;
+  double acc = 0.0;
+  if (idx < nW + cout) {
+    int src;
+    if (idx < nW) {
+      const int o = idx / (cin * kTaps), c = (idx / kTaps) % cin, tap = idx % kTaps;
+      src = (o * kCh + c) * kTaps + tap;
+    } else {
+      src = kCh * kCh * kTaps + (idx - nW);
+    }
+#pragma unroll 8
+    for (int k = sl; k < nparts; k += kRedSlices) acc += (double)part[(size_t)k * kGradPart + src];
   }
-  double s = 0.0;
-  for (int k = 0; k < nparts; ++k) s += (double)part[(size_t)k * kGradPart + src];
-  grad[idx] = (float)s;
+  red[sl][j] = acc;
+  __syncthreads();
+  if (sl == 0 && idx < nW + cout) {
+    double s = 0.0;
+    for (int q = 0; q < kRedSlices; ++q) s += red[q][j];
+    grad[idx] = (float)s;
+  }
 }
 
 // ------------------------------------------------------------------------------------- loss and output grad ---
@@ -510,7 +524,7 @@ hipError_t cnn_launch_wgrad(const CnnGeom& g, const uint16_t* gout, const uint16
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = cout * cin * kTaps + cout;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, part, nparts, cout, cin,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + kRedOut - 1) / kRedOut), dim3(kBlock), 0, s, part, nparts, cout, cin,
                      grad);
   return hipGetLastError();
 }
