@@ -279,20 +279,29 @@ struct KeLds {
   double* red;    // reduction scratch
 };
 
-__device__ __forceinline__ double blk_sum(double v, double* red) {
+// Block sums of two values (red: 2 kKeThreads / 64 doubles); every thread gets both.
+__device__ __forceinline__ void blk_sum2(double& a, double& b, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  v = wave_sum(v);
+  a = wave_sum(a);
+  b = wave_sum(b);
   __syncthreads();
-  if (lane == 0) red[wave] = v;
+  if (lane == 0) {
+    red[wave] = a;
+    red[kKeThreads / 64 + wave] = b;
+  }
   __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < kKeThreads / 64; ++i) s += red[i];
-  return s;
+  double sa = 0.0, sb = 0.0;
+  for (int i = 0; i < kKeThreads / 64; ++i) {
+    sa += red[i];
+    sb += red[kKeThreads / 64 + i];
+  }
+  a = sa;
+  b = sb;
 }
 
-// F (complex n x n, rows j, columns k) <- W F or F W (forward, sign -1) or with conj(W) (inverse, sign +1),
-// through T.  rows: transform along the column index (F W); else along the row index (W F).
-__device__ void dft_pass(double* F, double* T, const double* roots, int n, bool along_cols, bool inverse) {
+// dst (complex n x n, rows j, columns k) = src W (along_cols: transform along the column index) or W src (along
+// the row index), W the DFT matrix (forward, exp(-2 pi i jk/n)) or its conjugate (inverse).
+__device__ void dft_pass(const double* F, double* T, const double* roots, int n, bool along_cols, bool inverse) {
   const int n2 = n * n;
   for (int e = threadIdx.x; e < n2; e += kKeThreads) {
     const int j = e / n, k = e - j * n;
@@ -309,8 +318,6 @@ __device__ void dft_pass(double* F, double* T, const double* roots, int n, bool 
     T[2 * e] = sr;
     T[2 * e + 1] = si;
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 2 * n2; e += kKeThreads) F[e] = T[e];
   __syncthreads();
 }
 
@@ -426,8 +433,8 @@ __global__ __launch_bounds__(kKeThreads) void k_ke_gadmm(KeArgs K, const double*
             s += S.z[e];
             cnt += 1.0;
           }
-        const double ssum = blk_sum(s, S.red);
-        const double csum = blk_sum(cnt, S.red);
+        double ssum = s, csum = cnt;
+        blk_sum2(ssum, csum, S.red);
         if (csum == prev_cnt) break;
         prev_cnt = csum;
         theta = (ssum - 1.0) / csum;
@@ -457,12 +464,13 @@ __global__ __launch_bounds__(kKeThreads) void k_ke_gadmm(KeArgs K, const double*
       S.F3[2 * e + 1] = 0.0;
     }
     __syncthreads();
+    // each 2-D transform goes F -> T (rows) -> F (columns)
     dft_pass(S.F1, S.T, S.roots, n, true, false);
-    dft_pass(S.F1, S.T, S.roots, n, false, false);
+    dft_pass(S.T, S.F1, S.roots, n, false, false);
     dft_pass(S.F2, S.T, S.roots, n, true, false);
-    dft_pass(S.F2, S.T, S.roots, n, false, false);
+    dft_pass(S.T, S.F2, S.roots, n, false, false);
     dft_pass(S.F3, S.T, S.roots, n, true, false);
-    dft_pass(S.F3, S.T, S.roots, n, false, false);
+    dft_pass(S.T, S.F3, S.roots, n, false, false);
     // Cramer's rule per frequency (k1 row, k2 column): symbols sh = e^{2 pi i k2/n} - 1, sv = e^{2 pi i k1/n} - 1
     for (int e = tid; e < n2; e += kKeThreads) {
       const int k1 = e / n, k2 = e - k1 * n;
@@ -511,11 +519,11 @@ __global__ __launch_bounds__(kKeThreads) void k_ke_gadmm(KeArgs K, const double*
     }
     __syncthreads();
     dft_pass(S.F1, S.T, S.roots, n, true, true);
-    dft_pass(S.F1, S.T, S.roots, n, false, true);
+    dft_pass(S.T, S.F1, S.roots, n, false, true);
     dft_pass(S.F2, S.T, S.roots, n, true, true);
-    dft_pass(S.F2, S.T, S.roots, n, false, true);
+    dft_pass(S.T, S.F2, S.roots, n, false, true);
     dft_pass(S.F3, S.T, S.roots, n, true, true);
-    dft_pass(S.F3, S.T, S.roots, n, false, true);
+    dft_pass(S.T, S.F3, S.roots, n, false, true);
     // u_new (real part / n^2, kept in F1's real slots), p; the multipliers; the change of u
     const double inv = 1.0 / (double)n2;
     double dsq = 0.0, nsq = 0.0;
@@ -538,7 +546,8 @@ __global__ __launch_bounds__(kKeThreads) void k_ke_gadmm(KeArgs K, const double*
       S.L23[e] += rho * (dv(S.p1, e) - S.y3[e]);
       S.L3[e] += rho * (un - S.z[e]);
     }
-    const double dtot = blk_sum(dsq, S.red), ntot = blk_sum(nsq, S.red);
+    double dtot = dsq, ntot = nsq;
+    blk_sum2(dtot, ntot, S.red);
     for (int e = tid; e < n2; e += kKeThreads) S.u[e] = S.T[e];
     __syncthreads();
     change = sqrt(dtot) / fmax(sqrt(ntot), 1e-300);
@@ -557,7 +566,7 @@ __global__ __launch_bounds__(kKeThreads) void k_ke_gadmm(KeArgs K, const double*
 namespace host {
 namespace {
 
-size_t ke_lds_bytes(int n) { return ((size_t)15 * n * n + 8 * n * n + 2 * n + kKeThreads / 64) * sizeof(double); }
+size_t ke_lds_bytes(int n) { return ((size_t)15 * n * n + 8 * n * n + 2 * n + 2 * kKeThreads / 64) * sizeof(double); }
 
 }  // namespace
 }  // namespace host
