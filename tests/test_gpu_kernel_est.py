@@ -115,3 +115,14 @@ def test_refusals(ctx, torch_dev):
     with pytest.raises(B.LlpError) as ei:  # c l + 1 even: the HR box has no centre tap
         ctx.estimate_kernel(dev(torch_dev, np.zeros((2, 16, 16))), dev(torch_dev, np.zeros((48, 48))), 3, n=9)
     assert ei.value.status == B.E_UNSUPPORTED
+
+
+def test_full_size_kernel_estimation(ctx, torch_dev):
+    """The kernel-estimation workload as the benchmark runs it: a 29 x 29 kernel from the 8-band 2048^2 scene (x4)
+    with the paper's parameters, against the oracle's estimate on the same float32 inputs."""
+    sc, _ = scenes.config_scene(1, 0)
+    want, info = tgv.estimate_kernel(sc.X, sc.Y, sc.c, tgv.TgvParams(n=29))
+    got, om, rep = ctx.estimate_kernel(dev(torch_dev, sc.X), dev(torch_dev, sc.Y), sc.c, n=29)
+    np.testing.assert_allclose(om.cpu().numpy(), info["omega"], rtol=1e-9, atol=1e-12)
+    assert abs(rep["iters"] - info["iters"]) <= 2, (rep, info["iters"])
+    assert rel(got.cpu().numpy(), want) < 1e-4

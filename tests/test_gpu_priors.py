@@ -181,3 +181,20 @@ def test_motion_blur_kernel_solve(ctx, torch_dev):
     Zp, rep, _ = ctx.pansharpen(*args, r=1, lam=1e-2, eps=1e-3, max_iters=30, precond=1)
     wantp, _ = oracle.pcg(prob, oracle.rhs(X, prob), max_iters=30)
     assert np.all(rel_l2(host(Zp), wantp) < 1e-5)
+
+
+def test_full_size_lgc_solve_sampled_bands(ctx, torch_dev):
+    """The priors workload as the benchmark runs it: the 8-band 2048^2 scene (x4, 17-tap blur, r 2) under LGC to
+    tol 1e-6; on two sampled bands the oracle re-evaluates the returned HRMS's residual in FP64."""
+    sc, st = scenes.config_scene(1, 0)
+    args = (dev(torch_dev, sc.X), dev(torch_dev, sc.Y), dev(torch_dev, sc.u))
+    Z, rep, status = ctx.prior_pansharpen("lgc", *args, r=st.r, lam=st.lam, eps=st.eps, max_iters=st.max_iters,
+                                          tol=st.tol)
+    assert status == B.OK and all(x["true_rel_residual"] <= st.tol for x in rep), rep
+    prob = priors.PriorProblem("lgc", u=sc.u, c=sc.c, Y=sc.Y, r=st.r, lam=f32(st.lam), eps=f32(st.eps))
+    for band in (0, 5):
+        Zb = host(Z[band:band + 1])
+        b = oracle.rhs(sc.X[band:band + 1], prob).astype(np.float32).astype(np.float64)
+        res = b - priors.apply_A_prior(Zb, prob)
+        rel = float(np.linalg.norm(res) / np.linalg.norm(b))
+        assert rel <= 1.5 * st.tol, (band, rel)
