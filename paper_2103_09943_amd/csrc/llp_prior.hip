@@ -680,7 +680,7 @@ llp_status llp_prior_pansharpen(llp_ctx* ctx, const llp_shape* shape, const llp_
                           s));
   const bool tol_mode = tol > 0.0f;
   // The check of bands whose recursive residual met the tolerance: r = b - A x into the buffers of parity `cur`,
-  // verdict, p = r for the bands that restart, and y = D B p again (the check used y for D B x).
+  // decision, p = r for the bands that restart, and y = D B p again (the check used y for D B x).
   auto check = [&](int cur) -> llp_status {
     HIP_TRY(launch_dir(g, cfg, 0, 0, 0, hrms, nullptr, nullptr, nullptr, nullptr, nullptr, ctx->y, kernel,
                        ctx->partials, ctx->st, 0, 0.0f, s));
