@@ -475,7 +475,8 @@ llp_status solve_scene(llp_ctx* ctx, const Geom& g, const OpConfig& cfg, const l
   // The returned HRMS: float32(xacc + z).  With a report: the FP64 residual of the iterate before that rounding,
   // the FP64 residual of the float32 output, and the objective of the output.
   if (rep) {
-    v = ref_pass(ctx->d_ref, P, ctx->st, ctx->results, kRefFinal, 1, 0, 0, max_iters, tol, 1, s);
+    // the FP64 residual of every band's returned iterate (a band stopped by the tolerance has it already)
+    v = ref_pass(ctx->d_ref, P, ctx->st, ctx->results, kRefFinal, 2, 0, 0, max_iters, tol, 1, s);
     if (v != LLP_OK) return v;
   }
   HIP_TRY(launch_ref_elem(rep ? kRefOutputBack : kRefOutput, ctx->d_ref, 1, P.eblocks, ctx->st, 1, s));

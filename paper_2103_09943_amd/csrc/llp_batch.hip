@@ -577,7 +577,8 @@ llp_status llp_pansharpen_batch(llp_ctx* ctx, int S, const llp_shape* shapes, co
     // The returned HRMS float32(xacc + x); with a report, the FP64 residuals of the iterate and of that output
     // and the output's objective.
     if (rep) {
-      v = ref_pass(d_ref, rplan, st, results, kRefFinal, 1, 0, 0, max_iters, tol, 1, s);
+      // the FP64 residual of every band's returned iterate (a band stopped by the tolerance has it already)
+      v = ref_pass(d_ref, rplan, st, results, kRefFinal, 2, 0, 0, max_iters, tol, 1, s);
       if (v != LLP_OK) return v;
     }
     HIP_TRY(launch_ref_elem(rep ? kRefOutputBack : kRefOutput, d_ref, nf, rplan.eblocks, st, 1, s));

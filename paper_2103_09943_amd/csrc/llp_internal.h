@@ -25,6 +25,7 @@ struct ChanState {
   int init;       // how the band started: kInitZero, kInitUser, kInitNet, kInitNetRejected
   int pending;    // 1: the recursive residual met the tolerance; the band waits for its true residual
   int last_rep;   // iteration of the band's last residual replacement
+  int ref_iter;   // iteration whose FP64 residual the results hold (its part z flushed); -1: none yet
   double rr;      // preconditioned iteration: r_k^T r_k (rho holds r_k^T P^{-1} r_k)
 };
 

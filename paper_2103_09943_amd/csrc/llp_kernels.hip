@@ -313,6 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Geom g, int from_init, const fl
     s.init = from_init ? kInitUser : kInitZero;
     s.pending = 0;
     s.last_rep = 0;
+    s.ref_iter = -1;
   }
 }
 
@@ -340,7 +341,10 @@ __global__ __launch_bounds__(kBlock) void k_fallback(Geom g, const double* __res
       r[base + e] = b[base + e];
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) st[ch].init = reject ? kInitNetRejected : kInitNet;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st[ch].init = reject ? kInitNetRejected : kInitNet;
+    if (reject) st[ch].ref_iter = -1;  // the residual in the results is the rejected start's
+  }
 }
 
 hipError_t launch_fallback(const Geom& g, const double* results, ChanState* st, const float* b, float* r,

@@ -33,8 +33,26 @@ __device__ __forceinline__ int wrapr(int i, int n) {
   return m < 0 ? m + n : m;
 }
 
+// force 1: every band; 0: the pending bands and those kRepEvery iterations past their last replacement; 2: the
+// bands whose FP64 residual in the results is not that of their current iterate.
 __device__ __forceinline__ bool rep_selected(const ChanState& c, int force) {
+  if (force == 2) return c.ref_iter != c.iters;
   return force || c.pending || (c.active && c.iters - c.last_rep >= kRepEvery);
+}
+
+// Whether any band of the table is selected (every thread of the block gets the answer): a pass that selects
+// none returns at once instead of striding over every tile.  One LDS word, so that the tiled launches keep their
+// dynamic LDS limit.
+__device__ __forceinline__ bool any_selected(const RefDesc* t, int count, const ChanState* st, int force) {
+  __shared__ int flag;
+  const int nb = t[count - 1].band0 + t[count - 1].g.N;
+  if (threadIdx.x == 0) flag = 0;
+  __syncthreads();
+  bool mine = false;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) mine = mine || rep_selected(st[b], force);
+  if (mine) flag = 1;
+  __syncthreads();
+  return flag != 0;
 }
 
 // Scene of workgroup `bid` in a table ordered by block offsets: the last entry whose offset <= bid.
@@ -93,6 +111,7 @@ __device__ __forceinline__ void ref_elem_block(int op, const RefDesc* __restrict
 // in which no band is selected costs a few state reads per workgroup, whatever the image sizes.
 __global__ __launch_bounds__(kBlock) void k_ref_elem(int op, const RefDesc* __restrict__ t, int count, int total,
                                                      const ChanState* __restrict__ st, int force) {
+  if (op == kRefFlush && !any_selected(t, count, st, force)) return;
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) ref_elem_block(op, t, count, st, force, vb);
 }
 
@@ -139,6 +158,7 @@ __device__ __forceinline__ void ref_y_block(const RefDesc* __restrict__ t, int c
 __global__ __launch_bounds__(kBlock) void k_ref_y(const RefDesc* __restrict__ t, int count, int total,
                                                   const ChanState* __restrict__ st, int force) {
   extern __shared__ double ysh[];
+  if (!any_selected(t, count, st, force)) return;
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
     ref_y_block(t, count, st, force, vb, ysh);
     __syncthreads();  // the next block's staging overwrites the region
@@ -387,6 +407,7 @@ __global__ __launch_bounds__(kResThreads) void k_ref_res(const RefDesc* __restri
                                                          int write_r) {
   extern __shared__ double rsh[];
   __shared__ double red[kResThreads / 64];
+  if (!any_selected(t, count, st, force)) return;
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
     ref_res_block(t, count, st, force, rpar, write_r, vb, rsh, red);
     __syncthreads();  // the next tile's staging overwrites the regions
@@ -424,6 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_ref_fin(int op, const RefDesc* __res
     return;
   }
   res[kSlotTrueRes] = s;
+  cs.ref_iter = cs.iters;
   if (op != kRefStep) return;
   cs.last_rep = cs.iters;
   if (plain_cg) cs.rho = s;  // the recursion continues from the replaced residual

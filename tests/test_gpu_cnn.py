@@ -162,6 +162,12 @@ def test_rejected_network_start_equals_cold_start(ctx, torch_dev):
         w = dict(w)
         w["init"] = c["init"]
         assert w == c
+    # without an iteration the report still gives the residual of the cold start, not the rejected one's
+    kw["max_iters"] = 0
+    _, cold0, _ = ctx.pansharpen(Xd, Yd, ud, **kw)
+    _, warm0, _ = ctx.pansharpen(Xd, Yd, ud, init="cnn", **kw)
+    assert all(r["true_rel_residual"] == pytest.approx(1.0, rel=1e-6) for r in cold0), cold0
+    assert [r["true_rel_residual"] for r in warm0] == [r["true_rel_residual"] for r in cold0]
 
 
 def test_batch_network_start_matches_single(ctx, torch_dev):
