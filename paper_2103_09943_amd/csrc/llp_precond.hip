@@ -130,6 +130,44 @@ struct Dft<8> {
   }
 };
 
+// 16 = 4 x 4 (Cooley-Tukey): v_{4 n1 + n2} -> four 4-point DFTs over n1, the twiddles e^{-2 pi i n2 k1 / 16},
+// four 4-point DFTs over n2; output k1 + 4 k2.
+template <>
+struct Dft<16> {
+  static __device__ __forceinline__ void rot(float2& a, float c, float s) {  // a * (c + i s)
+    a = make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+  static __device__ __forceinline__ void run(float2 (&v)[16]) {
+    constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
+    constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
+    constexpr float h = 0.70710678118654752440f;   // cos(pi/4)
+    float2 a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      float2 q[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      Dft<4>::run(q);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = q[k1];
+    }
+    rot(a[1][1], c1, -s1);  // W^1
+    rot(a[1][2], h, -h);    // W^2
+    rot(a[1][3], s1, -c1);  // W^3
+    rot(a[2][1], h, -h);    // W^2
+    a[2][2] = mul_mi(a[2][2]);  // W^4
+    rot(a[2][3], -h, -h);   // W^6
+    rot(a[3][1], s1, -c1);  // W^3
+    rot(a[3][2], -h, -h);   // W^6
+    rot(a[3][3], -c1, s1);  // W^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 q[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4>::run(q);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = q[k2];
+    }
+  }
+};
+
 // Odd radices by the definition, with cos and sin of 2 pi k / R as constants.
 __constant__ float kCos3[3] = {1.0f, -0.5f, -0.5f};
 __constant__ float kSin3[3] = {0.0f, 0.86602540378443865f, -0.86602540378443865f};
@@ -213,7 +251,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, c
   __syncthreads();
 }
 
-// The same pass for L a power of two (R = 8 or 4), with every LDS index an offset from one base per butterfly:
+// The same pass for L a power of two (R = 16, 8 or 4), with every LDS index an offset from one base per butterfly:
 // when M = L / R is a multiple of 16 (LIN) the R inputs jj + t M sit (M + M / 16) slots apart, and the outputs
 // o + t Ns always sit t Ns + (t Ns) / 16 slots from o (the padding of a block of R Ns outputs is linear in t, as
 // the block starts on a multiple of min(R Ns, 16)).  TW = false for the first pass (Ns = 1: every twiddle is 1).
@@ -228,7 +266,7 @@ __device__ __forceinline__ void fft_pass_p2(float2* gbuf, int L, int nseq, int N
     return make_float2(x.x, x.y);
   };
   constexpr int NB = (PER + R - 1) / R;
-  constexpr int LR = R == 8 ? 3 : 2;
+  constexpr int LR = R == 16 ? 4 : R == 8 ? 3 : 2;
   const int M = L >> LR, total = nseq * M, S = seq_stride(L);
   const int lgM = __builtin_ctz(M), lgNs = __builtin_ctz(Ns);
   const int rstep = M + (M >> 4);
@@ -291,9 +329,10 @@ __device__ __forceinline__ void fft_pass_p2_any(float2* buf, int L, int nseq, in
 // Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L; tw: the pass-major
 // twiddle table of the transform in LDS, see pass_twiddles).
 // TH threads, at most ELEMS values.  MIXED = false: radices 8 and 4 only (L a power of two), up to ELEMS / TH
-// values per thread; MIXED = true: every radix, up to min(ELEMS, kPcSmallElems) / TH values per thread (short
-// transforms only, see pc_supported).  Splitting the two keeps every pass within the register budget.
-template <int TH, bool MIXED, int ELEMS = kPcMaxElems>
+// values per thread, and with WIDE radix 16 too (the column plan, pc_col_radices); MIXED = true: every radix,
+// up to min(ELEMS, kPcSmallElems) / TH values per thread (short transforms only, see pc_supported).  Splitting
+// them keeps every pass within the register budget.
+template <int TH, bool MIXED, int ELEMS = kPcMaxElems, bool WIDE = false>
 __device__ __forceinline__ void fft_lds(float2* buf, int L, int nseq, const int* rad, int nrad, const float2* tw) {
   constexpr int PER = (MIXED ? (ELEMS < kPcSmallElems ? ELEMS : kPcSmallElems) : ELEMS) / TH;
   int Ns = 1, off = 0;
@@ -308,6 +347,8 @@ __device__ __forceinline__ void fft_lds(float2* buf, int L, int nseq, const int*
         case 5: fft_pass<TH, 5, PER>(buf, L, nseq, Ns, tw + off); break;
         default: fft_pass<TH, 7, PER>(buf, L, nseq, Ns, tw + off); break;
       }
+    } else if (WIDE && R == 16) {
+      fft_pass_p2_any<TH, 16, PER>(buf, L, nseq, Ns, tw + off);
     } else if (R == 8) {
       fft_pass_p2_any<TH, 8, PER>(buf, L, nseq, Ns, tw + off);
     } else {
@@ -725,7 +766,7 @@ __device__ __forceinline__ void cols_body(int op, const PcDesc& d, const int* gp
   const Geom& g = d.g;
   const int h = g.h, w = g.w;
   const int Sh = seq_stride(h);
-  fft_lds<TC, MIXED>(pcsh, h, cnt * C2, d.rh, d.nrh, twl);
+  fft_lds<TC, MIXED, kPcMaxElems, !MIXED>(pcsh, h, cnt * C2, d.rh, d.nrh, twl);
   const float dscale = op == kPcColsSolve ? (float)((double)g.lam * d.mbar[0]) : 0.0f;
 #pragma unroll 1
   for (int idx = opaque_tid(); idx < cnt * h; idx += TC) {
@@ -734,7 +775,7 @@ __device__ __forceinline__ void cols_body(int op, const PcDesc& d, const int* gp
   }
   if (op == kPcColsKernel) return;
   __syncthreads();
-  fft_lds<TC, MIXED>(pcsh, h, cnt * C2, d.rh, d.nrh, twl);
+  fft_lds<TC, MIXED, kPcMaxElems, !MIXED>(pcsh, h, cnt * C2, d.rh, d.nrh, twl);
   const int per = h * C2;
   const float inv_per = 1.0f / (float)per;
   const size_t pstride = (size_t)h * w * C2;
@@ -1009,6 +1050,31 @@ int pc_radices(int L, int* rad) {
   return L == 1 ? n : -1;
 }
 
+// The column pass's plan: for a power of two 2^a, a >= 6, radix-16 passes (a / 4 of them) and one pass of 4 or 8
+// for the rest (a = 4k + 1: 16^(k-1) 8 4), fewer LDS passes and barriers than radix 8; otherwise pc_radices.
+// LLP_COL_RADIX=8 keeps the radix-8 plan (comparison runs).
+int pc_col_radices(int L, int* rad) {
+  static const bool narrow = [] {
+    const char* e = getenv("LLP_COL_RADIX");
+    return e && atoi(e) == 8;
+  }();
+  int a = 0;
+  while (a < 30 && (1 << a) < L) ++a;
+  if (narrow || (1 << a) != L || a < 6) return pc_radices(L, rad);
+  int n = 0;
+  const int k = a / 4, rest = a % 4;
+  for (int i = 0; i < (rest == 1 ? k - 1 : k); ++i) rad[n++] = 16;
+  if (rest == 1) {
+    rad[n++] = 8;
+    rad[n++] = 4;
+  } else if (rest == 2) {
+    rad[n++] = 4;
+  } else if (rest == 3) {
+    rad[n++] = 8;
+  }
+  return n;
+}
+
 // Whether a transform of length L needs a radix with the smaller per-thread budget.
 static bool pc_small_radix(int L) {
   int rad[kPcMaxRad];
@@ -1042,9 +1108,9 @@ size_t pc_tw_floats(const Geom& g) { return (size_t)2 * (g.h + g.w + g.H + g.W);
 // The pass-major twiddles of a length-L transform (L complex values): pass p, of radix R over sub-transforms of
 // length Ns, holds e^{-2 pi i t k / (Ns R)} for k < Ns, 0 < t < R at sum_{q < p} Ns_q (R_q - 1) + (t - 1) Ns +
 // k; the passes use L - 1 entries and the last is unused.  FP64 evaluated, rounded once.
-static float* pass_twiddles(int L, float* out) {
+static float* pass_twiddles(int L, float* out, bool col) {
   int rad[kPcMaxRad];
-  const int n = pc_radices(L, rad);
+  const int n = col ? pc_col_radices(L, rad) : pc_radices(L, rad);
   float* end = out + 2 * (size_t)L;
   int Ns = 1;
   for (int p = 0; p < n; ++p) {
@@ -1062,8 +1128,8 @@ static float* pass_twiddles(int L, float* out) {
 }
 
 void pc_twiddles(const Geom& g, float* out) {
-  out = pass_twiddles(g.h, out);
-  out = pass_twiddles(g.w, out);
+  out = pass_twiddles(g.h, out, true);
+  out = pass_twiddles(g.w, out, false);
   const int lens[2] = {g.H, g.W};
   for (int L : lens)
     for (int m = 0; m < L; ++m) {
@@ -1082,7 +1148,7 @@ void pc_fill(PcDesc& d, const Geom& g, float* tw_dev) {
   d.twH = tw + g.h + g.w;
   d.twW = tw + g.h + g.w + g.H;
   d.nrw = pc_radices(g.w, d.rw);
-  d.nrh = pc_radices(g.h, d.rh);
+  d.nrh = pc_col_radices(g.h, d.rh);
   d.mixed_w = pc_small_radix(g.w);
   d.mixed_h = pc_small_radix(g.h);
 }
