@@ -329,7 +329,7 @@ __device__ __forceinline__ void fft_pass_p2_any(float2* buf, int L, int nseq, in
 // Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L; tw: the pass-major
 // twiddle table of the transform in LDS, see pass_twiddles).
 // TH threads, at most ELEMS values.  MIXED = false: radices 8 and 4 only (L a power of two), up to ELEMS / TH
-// values per thread, and with WIDE radix 16 too (the column plan, pc_col_radices); MIXED = true: every radix,
+// values per thread, and with WIDE radix 16 too (the plan of pc_wide_radices); MIXED = true: every radix,
 // up to min(ELEMS, kPcSmallElems) / TH values per thread (short transforms only, see pc_supported).  Splitting
 // them keeps every pass within the register budget.
 template <int TH, bool MIXED, int ELEMS = kPcMaxElems, bool WIDE = false>
@@ -646,7 +646,7 @@ __device__ __forceinline__ void rows_fwd(int op, const PcDesc& d, const ChanStat
   }
   const float2* twl = stage_twiddles<TH>(pcsh, C2, w, d.tww);
   __syncthreads();
-  fft_lds<TH, MIXED, row_elems(TH)>(pcsh, w, C2, d.rw, d.nrw, twl);
+  fft_lds<TH, MIXED, row_elems(TH), !MIXED>(pcsh, w, C2, d.rw, d.nrw, twl);
   float2* out = d.spec + ((size_t)pair * g.h + m) * (size_t)w * C2;
   // consecutive threads: consecutive values of a cell row
   copy_elems<TH, 8>(
@@ -906,7 +906,7 @@ __device__ __forceinline__ void rows_inv(const PcDesc& d, const ChanState* sst, 
       w * C2, [&](int e) { return conjf2(gld(in + e)); }, [&](int e, float2 v) { pcsh[pd(e % C2, Sw, e / C2)] = v; });
   const float2* twl = stage_twiddles<TH>(pcsh, C2, w, d.tww);
   __syncthreads();
-  fft_lds<TH, MIXED, row_elems(TH)>(pcsh, w, C2, d.rw, d.nrw, twl);
+  fft_lds<TH, MIXED, row_elems(TH), !MIXED>(pcsh, w, C2, d.rw, d.nrw, twl);
   const float scale = 1.0f / ((float)g.h * (float)w);
   const size_t HW = (size_t)g.H * W;
   double acc_a = 0.0, acc_b = 0.0;
@@ -1050,14 +1050,18 @@ int pc_radices(int L, int* rad) {
   return L == 1 ? n : -1;
 }
 
-// The column pass's plan: for a power of two 2^a, a >= 6, radix-16 passes (a / 4 of them) and one pass of 4 or 8
-// for the rest (a = 4k + 1: 16^(k-1) 8 4), fewer LDS passes and barriers than radix 8; otherwise pc_radices.
-// LLP_COL_RADIX=8 keeps the radix-8 plan (comparison runs).
-int pc_col_radices(int L, int* rad) {
-  static const bool narrow = [] {
-    const char* e = getenv("LLP_COL_RADIX");
-    return e && atoi(e) == 8;
-  }();
+// The plan of the transform passes (rows: col = false, columns: col = true): for a power of two 2^a, a >= 6,
+// radix-16 passes (a / 4 of them) and one pass of 4 or 8 for the rest (a = 4k + 1: 16^(k-1) 8 4), fewer LDS
+// passes and barriers than radix 8; otherwise pc_radices.  LLP_COL_RADIX=8 / LLP_ROW_RADIX=8 keep the radix-8
+// plan (comparison runs).
+static bool env_is_8(const char* name) {
+  const char* e = getenv(name);
+  return e && atoi(e) == 8;
+}
+
+int pc_wide_radices(int L, int* rad, bool col) {
+  static const bool narrow_col = env_is_8("LLP_COL_RADIX"), narrow_row = env_is_8("LLP_ROW_RADIX");
+  const bool narrow = col ? narrow_col : narrow_row;
   int a = 0;
   while (a < 30 && (1 << a) < L) ++a;
   if (narrow || (1 << a) != L || a < 6) return pc_radices(L, rad);
@@ -1110,7 +1114,7 @@ size_t pc_tw_floats(const Geom& g) { return (size_t)2 * (g.h + g.w + g.H + g.W);
 // k; the passes use L - 1 entries and the last is unused.  FP64 evaluated, rounded once.
 static float* pass_twiddles(int L, float* out, bool col) {
   int rad[kPcMaxRad];
-  const int n = col ? pc_col_radices(L, rad) : pc_radices(L, rad);
+  const int n = pc_wide_radices(L, rad, col);
   float* end = out + 2 * (size_t)L;
   int Ns = 1;
   for (int p = 0; p < n; ++p) {
@@ -1147,8 +1151,8 @@ void pc_fill(PcDesc& d, const Geom& g, float* tw_dev) {
   d.tww = tw + g.h;
   d.twH = tw + g.h + g.w;
   d.twW = tw + g.h + g.w + g.H;
-  d.nrw = pc_radices(g.w, d.rw);
-  d.nrh = pc_col_radices(g.h, d.rh);
+  d.nrw = pc_wide_radices(g.w, d.rw, false);
+  d.nrh = pc_wide_radices(g.h, d.rh, true);
   d.mixed_w = pc_small_radix(g.w);
   d.mixed_h = pc_small_radix(g.h);
 }
