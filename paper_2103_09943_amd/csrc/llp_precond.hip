@@ -32,6 +32,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <utility>
 
 namespace llp {
 using namespace dev;
@@ -168,6 +169,61 @@ struct Dft<16> {
   }
 };
 
+// cos(pi k / 16) for 0 <= k < 32, and a * e^{-i pi m / 16} with m a compile-time constant.
+__host__ __device__ constexpr float cos16(int k) {
+  return k > 16 ? cos16(32 - k)
+       : k > 8  ? -cos16(16 - k)
+       : k == 0 ? 1.0f
+       : k == 1 ? 0.98078528040323044913f
+       : k == 2 ? 0.92387953251128675613f
+       : k == 3 ? 0.83146961230254523708f
+       : k == 4 ? 0.70710678118654752440f
+       : k == 5 ? 0.55557023301960222474f
+       : k == 6 ? 0.38268343236508977173f
+       : k == 7 ? 0.19509032201612826785f
+                : 0.0f;
+}
+template <int m>
+__device__ __forceinline__ void twiddle32(float2& a) {
+  if constexpr (m % 32 == 0) {
+    return;
+  } else if constexpr (m % 32 == 8) {
+    a = mul_mi(a);
+  } else {
+    constexpr float c = cos16(m % 32), s = cos16(m % 32 <= 8 ? 8 - m % 32 : m % 32 - 8);  // sin(pi m / 16)
+    a = make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
+  }
+}
+template <int N2, int... K1>
+__device__ __forceinline__ void twiddle32_row(float2 (&a)[8], std::integer_sequence<int, K1...>) {
+  (twiddle32<N2 * K1>(a[K1]), ...);
+}
+
+// 32 = 8 x 4 (Cooley-Tukey): v_{4 n1 + n2} -> four 8-point DFTs over n1, the twiddles e^{-2 pi i n2 k1 / 32},
+// eight 4-point DFTs over n2; output k1 + 8 k2.
+template <>
+struct Dft<32> {
+  static __device__ __forceinline__ void run(float2 (&v)[32]) {
+    float2 a[4][8];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 8; ++n1) a[n2][n1] = v[4 * n1 + n2];
+      Dft<8>::run(a[n2]);
+    }
+    twiddle32_row<1>(a[1], std::make_integer_sequence<int, 8>{});
+    twiddle32_row<2>(a[2], std::make_integer_sequence<int, 8>{});
+    twiddle32_row<3>(a[3], std::make_integer_sequence<int, 8>{});
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+      float2 q[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4>::run(q);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 8 * k2] = q[k2];
+    }
+  }
+};
+
 // Odd radices by the definition, with cos and sin of 2 pi k / R as constants.
 __constant__ float kCos3[3] = {1.0f, -0.5f, -0.5f};
 __constant__ float kSin3[3] = {0.0f, 0.86602540378443865f, -0.86602540378443865f};
@@ -251,7 +307,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, int L, int nseq, int Ns, c
   __syncthreads();
 }
 
-// The same pass for L a power of two (R = 16, 8 or 4), with every LDS index an offset from one base per butterfly:
+// The same pass for L a power of two (R = 32, 16, 8 or 4), with every LDS index an offset from one base per butterfly:
 // when M = L / R is a multiple of 16 (LIN) the R inputs jj + t M sit (M + M / 16) slots apart, and the outputs
 // o + t Ns always sit t Ns + (t Ns) / 16 slots from o (the padding of a block of R Ns outputs is linear in t, as
 // the block starts on a multiple of min(R Ns, 16)).  TW = false for the first pass (Ns = 1: every twiddle is 1).
@@ -266,7 +322,7 @@ __device__ __forceinline__ void fft_pass_p2(float2* gbuf, int L, int nseq, int N
     return make_float2(x.x, x.y);
   };
   constexpr int NB = (PER + R - 1) / R;
-  constexpr int LR = R == 16 ? 4 : R == 8 ? 3 : 2;
+  constexpr int LR = R == 32 ? 5 : R == 16 ? 4 : R == 8 ? 3 : 2;
   const int M = L >> LR, total = nseq * M, S = seq_stride(L);
   const int lgM = __builtin_ctz(M), lgNs = __builtin_ctz(Ns);
   const int rstep = M + (M >> 4);
@@ -329,7 +385,8 @@ __device__ __forceinline__ void fft_pass_p2_any(float2* buf, int L, int nseq, in
 // Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L; tw: the pass-major
 // twiddle table of the transform in LDS, see pass_twiddles).
 // TH threads, at most ELEMS values.  MIXED = false: radices 8 and 4 only (L a power of two), up to ELEMS / TH
-// values per thread, and with WIDE radix 16 too (the plan of pc_wide_radices); MIXED = true: every radix,
+// values per thread, and with WIDE radix 16 too and radix 32 where a thread holds 32 values (the plan of
+// pc_wide_radices); MIXED = true: every radix,
 // up to min(ELEMS, kPcSmallElems) / TH values per thread (short transforms only, see pc_supported).  Splitting
 // them keeps every pass within the register budget.
 template <int TH, bool MIXED, int ELEMS = kPcMaxElems, bool WIDE = false>
@@ -347,6 +404,8 @@ __device__ __forceinline__ void fft_lds(float2* buf, int L, int nseq, const int*
         case 5: fft_pass<TH, 5, PER>(buf, L, nseq, Ns, tw + off); break;
         default: fft_pass<TH, 7, PER>(buf, L, nseq, Ns, tw + off); break;
       }
+    } else if (WIDE && R == 32) {
+      if constexpr (WIDE && PER >= 32) fft_pass_p2_any<TH, 32, PER>(buf, L, nseq, Ns, tw + off);
     } else if (WIDE && R == 16) {
       fft_pass_p2_any<TH, 16, PER>(buf, L, nseq, Ns, tw + off);
     } else if (R == 8) {
@@ -1052,20 +1111,33 @@ int pc_radices(int L, int* rad) {
 
 // The plan of the transform passes (rows: col = false, columns: col = true): for a power of two 2^a, a >= 6,
 // radix-16 passes (a / 4 of them) and one pass of 4 or 8 for the rest (a = 4k + 1: 16^(k-1) 8 4), fewer LDS
-// passes and barriers than radix 8; otherwise pc_radices.  LLP_COL_RADIX=8 / LLP_ROW_RADIX=8 keep the radix-8
-// plan (comparison runs).
-static bool env_is_8(const char* name) {
+// passes and barriers than radix 8; for columns with a >= 9 radix-32 passes (a / 5 of them) and one of 4, 8 or
+// 16 for the rest (a = 5k + 1: 32^(k-1) 16 4), as the column pass holds 32 values per thread; otherwise
+// pc_radices.  For comparison runs, LLP_COL_RADIX / LLP_ROW_RADIX = 8 keep the radix-8 plan and
+// LLP_COL_RADIX = 16 the radix-16 plan.
+static int env_radix(const char* name) {
   const char* e = getenv(name);
-  return e && atoi(e) == 8;
+  return e ? atoi(e) : 0;
 }
 
 int pc_wide_radices(int L, int* rad, bool col) {
-  static const bool narrow_col = env_is_8("LLP_COL_RADIX"), narrow_row = env_is_8("LLP_ROW_RADIX");
-  const bool narrow = col ? narrow_col : narrow_row;
+  static const int col_radix = env_radix("LLP_COL_RADIX"), row_radix = env_radix("LLP_ROW_RADIX");
+  const bool narrow = (col ? col_radix : row_radix) == 8;
   int a = 0;
   while (a < 30 && (1 << a) < L) ++a;
   if (narrow || (1 << a) != L || a < 6) return pc_radices(L, rad);
   int n = 0;
+  if (col && a >= 9 && col_radix != 16) {
+    const int k = a / 5, rest = a % 5;
+    for (int i = 0; i < (rest == 1 ? k - 1 : k); ++i) rad[n++] = 32;
+    if (rest == 1) {
+      rad[n++] = 16;
+      rad[n++] = 4;
+    } else if (rest > 1) {
+      rad[n++] = 1 << rest;
+    }
+    return n;
+  }
   const int k = a / 4, rest = a % 4;
   for (int i = 0; i < (rest == 1 ? k - 1 : k); ++i) rad[n++] = 16;
   if (rest == 1) {

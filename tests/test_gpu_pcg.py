@@ -4,7 +4,8 @@ against the oracle, through the C ABI.
 Bars as for the plain solve: operators to relative L2 <= 1e-5 per band (float32 transforms against FP64), the
 preconditioned CG iterate after a fixed count to 1e-5, and at tol 1e-6 the FP64 residual of the iterate within
 the tolerance and the objective within 1e-6 of the exact minimiser's.  Shapes cover every radix (8, 4, 2 and
-3, 5, 7: LR sides 12, 14, 20, 24, 30), odd band counts (a band pair with an empty half), and c = 1..4.
+3, 5, 7: LR sides 12, 14, 20, 24, 30; the radix-16 and radix-32 plans of power-of-two sides up to 2048), odd
+band counts (a band pair with an empty half), and c = 1..4.
 """
 import json
 import os
@@ -61,9 +62,18 @@ SHAPES = [  # N, h, w, c, n, r
     (1, 8, 8, 3, 5, 1),       # c = 3
     (5, 32, 40, 4, 15, 2),    # five bands: the third pair has one band
 ]
+# Power-of-two sides with the wide radix plans: radix 16 (sides 64..256, rows up to 1024), radix 32 (columns of
+# 512 and more, including a remainder pass).
+WIDE_SHAPES = [
+    (1, 128, 256, 2, 5, 1),   # columns 16 x 8, rows 16 x 16
+    (2, 512, 128, 1, 3, 1),   # columns 32 x 16, rows 16 x 8
+    (1, 1024, 64, 4, 9, 1),   # columns 32 x 32 (the large workload's), rows 16 x 4
+    (1, 64, 1024, 2, 5, 1),   # rows 16 x 16 x 4
+    (1, 2048, 16, 1, 3, 1),   # columns 32 x 16 x 4
+]
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + WIDE_SHAPES)
 def test_data_term_in_fourier_domain(ctx, torch_dev, shape):
     """B^T D^T D B z through the transforms against the oracle's convolution and decimation."""
     N, h, w, c, n, r = shape
@@ -75,7 +85,7 @@ def test_data_term_in_fourier_domain(ctx, torch_dev, shape):
     assert np.all(err < 1e-5), err
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + WIDE_SHAPES)
 def test_preconditioner_matches_oracle(ctx, torch_dev, shape):
     """P^{-1} r with mbar from the PAN statistics, against the oracle's block solve."""
     N, h, w, c, n, r = shape
