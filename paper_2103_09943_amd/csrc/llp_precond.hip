@@ -825,16 +825,20 @@ __device__ __forceinline__ void cols_body(int op, const PcDesc& d, const int* gp
   const Geom& g = d.g;
   const int h = g.h, w = g.w;
   const int Sh = seq_stride(h);
-  fft_lds<TC, MIXED, kPcMaxElems, !MIXED>(pcsh, h, cnt * C2, d.rh, d.nrh, twl);
-  const float dscale = op == kPcColsSolve ? (float)((double)g.lam * d.mbar[0]) : 0.0f;
+  // forward transforms, the cell operations, inverse transforms: one copy of the transform code for both
 #pragma unroll 1
-  for (int idx = opaque_tid(); idx < cnt * h; idx += TC) {
-    const int it = GR ? idx / h : 0, k1 = idx - it * h;
-    cell_op<C>(op, d, pcsh + (size_t)it * C2 * Sh, h, k1, k2, dscale);
+  for (int pass = 0;; ++pass) {
+    fft_lds<TC, MIXED, kPcMaxElems, !MIXED>(pcsh, h, cnt * C2, d.rh, d.nrh, twl);
+    if (pass == 1) break;
+    const float dscale = op == kPcColsSolve ? (float)((double)g.lam * d.mbar[0]) : 0.0f;
+#pragma unroll 1
+    for (int idx = opaque_tid(); idx < cnt * h; idx += TC) {
+      const int it = GR ? idx / h : 0, k1 = idx - it * h;
+      cell_op<C>(op, d, pcsh + (size_t)it * C2 * Sh, h, k1, k2, dscale);
+    }
+    if (op == kPcColsKernel) return;
+    __syncthreads();
   }
-  if (op == kPcColsKernel) return;
-  __syncthreads();
-  fft_lds<TC, MIXED, kPcMaxElems, !MIXED>(pcsh, h, cnt * C2, d.rh, d.nrh, twl);
   const int per = h * C2;
   const float inv_per = 1.0f / (float)per;
   const size_t pstride = (size_t)h * w * C2;
