@@ -385,8 +385,8 @@ __device__ __forceinline__ void fft_pass_p2_any(float2* buf, int L, int nseq, in
 // Forward DFT of nseq sequences of length L in LDS (radices rad[0..nrad), product L; tw: the pass-major
 // twiddle table of the transform in LDS, see pass_twiddles).
 // TH threads, at most ELEMS values.  MIXED = false: radices 8 and 4 only (L a power of two), up to ELEMS / TH
-// values per thread, and with WIDE radix 16 too and radix 32 where a thread holds 32 values (the plan of
-// pc_wide_radices); MIXED = true: every radix,
+// values per thread, and with WIDE radix 16 too and radix 32 in workgroups that hold kPcMaxElems values (the
+// plan of pc_wide_radices; the small-row workgroups keep their register budget); MIXED = true: every radix,
 // up to min(ELEMS, kPcSmallElems) / TH values per thread (short transforms only, see pc_supported).  Splitting
 // them keeps every pass within the register budget.
 template <int TH, bool MIXED, int ELEMS = kPcMaxElems, bool WIDE = false>
@@ -405,7 +405,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, int L, int nseq, const int*
         default: fft_pass<TH, 7, PER>(buf, L, nseq, Ns, tw + off); break;
       }
     } else if (WIDE && R == 32) {
-      if constexpr (WIDE && PER >= 32) fft_pass_p2_any<TH, 32, PER>(buf, L, nseq, Ns, tw + off);
+      if constexpr (WIDE && PER * TH >= kPcMaxElems) fft_pass_p2_any<TH, 32, PER>(buf, L, nseq, Ns, tw + off);
     } else if (WIDE && R == 16) {
       fft_pass_p2_any<TH, 16, PER>(buf, L, nseq, Ns, tw + off);
     } else if (R == 8) {
@@ -1115,23 +1115,24 @@ int pc_radices(int L, int* rad) {
 
 // The plan of the transform passes (rows: col = false, columns: col = true): for a power of two 2^a, a >= 6,
 // radix-16 passes (a / 4 of them) and one pass of 4 or 8 for the rest (a = 4k + 1: 16^(k-1) 8 4), fewer LDS
-// passes and barriers than radix 8; for columns with a >= 9 radix-32 passes (a / 5 of them) and one of 4, 8 or
-// 16 for the rest (a = 5k + 1: 32^(k-1) 16 4), as the column pass holds 32 values per thread; otherwise
-// pc_radices.  For comparison runs, LLP_COL_RADIX / LLP_ROW_RADIX = 8 keep the radix-8 plan and
-// LLP_COL_RADIX = 16 the radix-16 plan.
+// passes and barriers than radix 8; with allow32 and a >= 9 radix-32 passes (a / 5 of them) and one of 4, 8 or
+// 16 for the rest (a = 5k + 1: 32^(k-1) 16 4); otherwise pc_radices.  allow32: the columns, and the rows that
+// only the full-size row workgroups take (c^2 w > kPcSmallElems; their threads hold 16 values, so half of them
+// idle in a radix-32 pass).  For comparison runs, LLP_COL_RADIX / LLP_ROW_RADIX = 8 keep the radix-8 plan and
+// LLP_COL_RADIX / LLP_ROW_RADIX = 16 the radix-16 plan.
 static int env_radix(const char* name) {
   const char* e = getenv(name);
   return e ? atoi(e) : 0;
 }
 
-int pc_wide_radices(int L, int* rad, bool col) {
+int pc_wide_radices(int L, int* rad, bool col, bool allow32) {
   static const int col_radix = env_radix("LLP_COL_RADIX"), row_radix = env_radix("LLP_ROW_RADIX");
   const bool narrow = (col ? col_radix : row_radix) == 8;
   int a = 0;
   while (a < 30 && (1 << a) < L) ++a;
   if (narrow || (1 << a) != L || a < 6) return pc_radices(L, rad);
   int n = 0;
-  if (col && a >= 9 && col_radix != 16) {
+  if (allow32 && a >= 9 && (col ? col_radix : row_radix) != 16) {
     const int k = a / 5, rest = a % 5;
     for (int i = 0; i < (rest == 1 ? k - 1 : k); ++i) rad[n++] = 32;
     if (rest == 1) {
@@ -1185,12 +1186,19 @@ size_t pc_spec_floats(const Geom& g) { return (size_t)((g.N + 1) / 2) * g.H * g.
 size_t pc_uhat_floats(const Geom& g) { return (size_t)g.H * g.W * 2; }
 size_t pc_tw_floats(const Geom& g) { return (size_t)2 * (g.h + g.w + g.H + g.W); }
 
+// The plans of a scene's row and column transforms.
+static int row_plan(const Geom& g, int* rad) {
+  return pc_wide_radices(g.w, rad, false, (size_t)g.c * g.c * g.w > (size_t)kPcSmallElems);
+}
+static int col_plan(const Geom& g, int* rad) { return pc_wide_radices(g.h, rad, true, true); }
+
 // The pass-major twiddles of a length-L transform (L complex values): pass p, of radix R over sub-transforms of
 // length Ns, holds e^{-2 pi i t k / (Ns R)} for k < Ns, 0 < t < R at sum_{q < p} Ns_q (R_q - 1) + (t - 1) Ns +
 // k; the passes use L - 1 entries and the last is unused.  FP64 evaluated, rounded once.
-static float* pass_twiddles(int L, float* out, bool col) {
+static float* pass_twiddles(const Geom& g, float* out, bool col) {  // L = h (columns) or w (rows)
   int rad[kPcMaxRad];
-  const int n = pc_wide_radices(L, rad, col);
+  const int n = col ? col_plan(g, rad) : row_plan(g, rad);
+  const int L = col ? g.h : g.w;
   float* end = out + 2 * (size_t)L;
   int Ns = 1;
   for (int p = 0; p < n; ++p) {
@@ -1208,8 +1216,8 @@ static float* pass_twiddles(int L, float* out, bool col) {
 }
 
 void pc_twiddles(const Geom& g, float* out) {
-  out = pass_twiddles(g.h, out, true);
-  out = pass_twiddles(g.w, out, false);
+  out = pass_twiddles(g, out, true);
+  out = pass_twiddles(g, out, false);
   const int lens[2] = {g.H, g.W};
   for (int L : lens)
     for (int m = 0; m < L; ++m) {
@@ -1227,8 +1235,8 @@ void pc_fill(PcDesc& d, const Geom& g, float* tw_dev) {
   d.tww = tw + g.h;
   d.twH = tw + g.h + g.w;
   d.twW = tw + g.h + g.w + g.H;
-  d.nrw = pc_wide_radices(g.w, d.rw, false);
-  d.nrh = pc_wide_radices(g.h, d.rh, true);
+  d.nrw = row_plan(g, d.rw);
+  d.nrh = col_plan(g, d.rh);
   d.mixed_w = pc_small_radix(g.w);
   d.mixed_h = pc_small_radix(g.h);
 }

@@ -62,13 +62,15 @@ SHAPES = [  # N, h, w, c, n, r
     (1, 8, 8, 3, 5, 1),       # c = 3
     (5, 32, 40, 4, 15, 2),    # five bands: the third pair has one band
 ]
-# Power-of-two sides with the wide radix plans: radix 16 (sides 64..256, rows up to 1024), radix 32 (columns of
-# 512 and more, including a remainder pass).
+# Power-of-two sides with the wide radix plans: radix 16 (sides 64..256, and rows of at most 4096 values),
+# radix 32 (longer sides, including a remainder pass).
 WIDE_SHAPES = [
     (1, 128, 256, 2, 5, 1),   # columns 16 x 8, rows 16 x 16
     (2, 512, 128, 1, 3, 1),   # columns 32 x 16, rows 16 x 8
     (1, 1024, 64, 4, 9, 1),   # columns 32 x 32 (the large workload's), rows 16 x 4
-    (1, 64, 1024, 2, 5, 1),   # rows 16 x 16 x 4
+    (1, 64, 1024, 2, 5, 1),   # rows 16 x 16 x 4 (c^2 w = 4096: the small-row workgroups)
+    (1, 16, 512, 4, 9, 1),    # rows 32 x 16
+    (1, 16, 2048, 2, 5, 1),   # rows 32 x 16 x 4
     (1, 2048, 16, 1, 3, 1),   # columns 32 x 16 x 4
 ]
 
